@@ -1,0 +1,306 @@
+"""FP64 CPU oracle for the twisted-mass disconnected-loop hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.  It shares no
+code with the HIP path; the only common inputs come from the seeded generators
+in ``synth`` (gauge links), and the Z4 noise is re-derived here from the
+published SplitMix64 definition.
+
+Layouts are canonical numpy complex128 arrays:
+  links   U[mu, site, row, col]   shape (4, V, 3, 3)
+  spinor  psi[site, spin, colour] shape (V, 4, 3)
+  loops   L[n, t]                  shape (16, Lt),  n the Gamma index
+with site = x + Lx*(y + Ly*(z + Lz*t)).
+
+The arithmetic lives in oracle.c (plain C, OpenMP over sites); this module
+marshals arguments and writes out the estimator formulas of the paper:
+  * stochastic estimate of M^-1 and the standard loop (section II.A, eqs.
+    estiM and loopSt),
+  * the Truncated Solver Method combination (section II.B, eq. estiTSM),
+  * the one-end trick (section II.C, eq. loopVv),
+  * the Hopping Parameter Expansion (section II.E, eqs. HPE and loopHPE1).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_c_int4 = ctypes.c_int * 4
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.or_gamma.argtypes = [ctypes.c_int, dp]
+        L.or_twist.argtypes = [_c_int4, ctypes.c_double, ctypes.c_int, dp, dp]
+        L.or_hop.argtypes = [_c_int4, ctypes.c_double, ctypes.c_int, dp, dp, dp, ctypes.c_int]
+        L.or_apply_M.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 dp, dp, dp, ctypes.c_int]
+        L.or_schur.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                               dp, dp, dp, ctypes.c_int, ctypes.c_int]
+        L.or_source_prep.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     dp, dp, dp, ctypes.c_int]
+        L.or_reconstruct.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     dp, dp, dp, dp]
+        L.or_cgnr.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                              dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_int)]
+        L.or_cgnr.restype = ctypes.c_double
+        L.or_cgnr_iterations.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, dp, dp, ctypes.c_int]
+        L.or_cgnr_iterations.restype = ctypes.c_double
+        L.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.or_splitmix64.restype = ctypes.c_uint64
+        L.or_noise_z4.argtypes = [_c_int4, ctypes.c_uint64, ctypes.c_long, dp]
+        L.or_contract_std.argtypes = [_c_int4, dp, dp, dp]
+        L.or_contract_oneend.argtypes = [_c_int4, ctypes.c_double, dp, dp]
+        L.or_bh_power.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                  dp, dp, dp, ctypes.c_int]
+        L.or_hpe_exact.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   dp, dp]
+        L.or_site_parity.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_int)]
+        L.or_neighbours.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_long)]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _L(L):
+    return _c_int4(*[int(v) for v in L])
+
+
+def volume(L):
+    return int(np.prod(L))
+
+
+def _cvec(x, shape):
+    a = np.ascontiguousarray(x, dtype=np.complex128)
+    assert a.shape == tuple(shape), (a.shape, shape)
+    return a
+
+
+def _spinor(L, x):
+    return _cvec(x, (volume(L), 4, 3))
+
+
+def _links(L, U):
+    return _cvec(U, (4, volume(L), 3, 3))
+
+
+# ---------------------------------------------------------------- geometry
+
+def site_parity(L):
+    out = np.zeros(volume(L), dtype=np.intc)
+    lib().or_site_parity(_L(L), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return out
+
+
+def neighbours(L):
+    """nb[s, 2*mu + 0] = s + mu, nb[s, 2*mu + 1] = s - mu (periodic wrap)."""
+    out = np.zeros((volume(L), 8), dtype=np.int_)
+    lib().or_neighbours(_L(L), out.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+    return out
+
+
+def gamma(n):
+    out = np.zeros((4, 4), dtype=np.complex128)
+    lib().or_gamma(int(n), _p(out))
+    return out
+
+
+# ---------------------------------------------------------------- operators
+
+def twist(L, eps, psi, which=0):
+    """which: 0 R, 1 R^dag, 2 R^-1, 3 (R^-1)^dag with R = 1 + i eps gamma5."""
+    psi = _spinor(L, psi)
+    out = np.empty_like(psi)
+    lib().or_twist(_L(L), float(eps), int(which), _p(psi), _p(out))
+    return out
+
+
+def hop(L, kappa, t_bc, U, psi, adj=False):
+    U, psi = _links(L, U), _spinor(L, psi)
+    out = np.empty_like(psi)
+    lib().or_hop(_L(L), float(kappa), int(t_bc), _p(U), _p(psi), _p(out), int(adj))
+    return out
+
+
+def apply_M(L, kappa, eps, t_bc, U, psi, adj=False):
+    U, psi = _links(L, U), _spinor(L, psi)
+    out = np.empty_like(psi)
+    lib().or_apply_M(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(psi), _p(out),
+                     int(adj))
+    return out
+
+
+def schur(L, kappa, eps, t_bc, U, psi, adj=False, form=0):
+    """Even-site Schur complement applied to the even part of a full vector."""
+    U, psi = _links(L, U), _spinor(L, psi)
+    out = np.empty_like(psi)
+    lib().or_schur(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(psi), _p(out),
+                   int(adj), int(form))
+    return out
+
+
+def source_prep(L, kappa, eps, t_bc, U, b, form=0):
+    U, b = _links(L, U), _spinor(L, b)
+    out = np.empty_like(b)
+    lib().or_source_prep(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(b), _p(out),
+                         int(form))
+    return out
+
+
+def reconstruct(L, kappa, eps, t_bc, U, b, xe):
+    U, b, xe = _links(L, U), _spinor(L, b), _spinor(L, xe)
+    out = np.empty_like(b)
+    lib().or_reconstruct(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(b), _p(xe),
+                         _p(out))
+    return out
+
+
+def cgnr(L, kappa, eps, t_bc, U, b, tol, maxiter=100000, form=0):
+    """Solve M x = b; returns (x, iterations, true relative residual)."""
+    U, b = _links(L, U), _spinor(L, b)
+    x = np.empty_like(b)
+    it = ctypes.c_int(0)
+    res = lib().or_cgnr(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(b), _p(x),
+                        float(tol), int(maxiter), int(form), ctypes.byref(it))
+    return x, it.value, res
+
+
+def cgnr_iterations(L, kappa, eps, t_bc, U, b, niter):
+    U, b = _links(L, U), _spinor(L, b)
+    return lib().or_cgnr_iterations(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(b),
+                                    int(niter))
+
+
+def bh_power(L, kappa, eps, t_bc, U, psi, k=4):
+    U, psi = _links(L, U), _spinor(L, psi)
+    out = np.empty_like(psi)
+    lib().or_bh_power(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(psi), _p(out),
+                      int(k))
+    return out
+
+
+# ---------------------------------------------------------------- noise
+
+def splitmix64(seed, c):
+    return int(lib().or_splitmix64(ctypes.c_uint64(seed & (2**64 - 1)), ctypes.c_uint64(c)))
+
+
+def noise_z4(L, seed, r):
+    out = np.empty((volume(L), 4, 3), dtype=np.complex128)
+    lib().or_noise_z4(_L(L), ctypes.c_uint64(seed & (2**64 - 1)), int(r), _p(out))
+    return out
+
+
+def dilute_spin_colour(eta):
+    """Spin-colour dilution: 12 sources, number d = 3*spin + colour keeps only
+    that component of eta (section II.D)."""
+    out = np.zeros((12,) + eta.shape, dtype=np.complex128)
+    for a in range(4):
+        for c in range(3):
+            out[3 * a + c, :, a, c] = eta[:, a, c]
+    return out
+
+
+# ---------------------------------------------------------------- contractions
+
+def contract_std(L, eta, s):
+    """sum_{x in t} eta^dag Gamma_n s  ->  (16, Lt)"""
+    out = np.zeros((16, L[3]), dtype=np.complex128)
+    lib().or_contract_std(_L(L), _p(_spinor(L, eta)), _p(_spinor(L, s)), _p(out))
+    return out
+
+
+def contract_oneend(L, eps, s):
+    """2 i eps sum_{x in t} s^dag gamma5 Gamma_n s  ->  (16, Lt)"""
+    out = np.zeros((16, L[3]), dtype=np.complex128)
+    lib().or_contract_oneend(_L(L), float(eps), _p(_spinor(L, s)), _p(out))
+    return out
+
+
+def hpe_exact(L, kappa, eps, t_bc, U):
+    """sum_{x in t} tr[Gamma_n (B + (BH)^2 B)_xx]  ->  (16, Lt)"""
+    out = np.zeros((16, L[3]), dtype=np.complex128)
+    lib().or_hpe_exact(_L(L), float(kappa), float(eps), int(t_bc), _p(_links(L, U)),
+                       _p(out))
+    return out
+
+
+# ---------------------------------------------------------------- estimators
+
+EST_STD, EST_ONE_END, EST_HPE = 1, 2, 4
+
+
+def loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators):
+    """Per-noise loops from the sources of one noise vector (one entry per
+    dilution component) and their solutions.  Returns {estimator: (16, Lt)}.
+
+    STD:     sum_d eta_d^dag Gamma s_d                  (eq. loopSt)
+    ONE_END: 2 i eps sum_d s_d^dag gamma5 Gamma s_d     (eq. loopVv, lhs)
+    HPE:     sum_d eta_d^dag Gamma (BH)^4 s_d           (eq. loopHPE1); the
+             exactly known part is added once per estimate, not per noise.
+    """
+    out = {}
+    if estimators & EST_STD:
+        out[EST_STD] = sum(contract_std(L, e, s) for e, s in zip(etas, sols))
+    if estimators & EST_ONE_END:
+        out[EST_ONE_END] = sum(contract_oneend(L, eps, s) for s in sols)
+    if estimators & EST_HPE:
+        out[EST_HPE] = sum(contract_std(L, e, bh_power(L, kappa, eps, t_bc, U, s, 4))
+                           for e, s in zip(etas, sols))
+    return out
+
+
+def tsm_combine(hp_loops, lp_of_hp_loops, lp_only_loops):
+    """Truncated Solver Method (eq. estiTSM), applied to any loop functional:
+       (1/N_HP) sum_{r<=N_HP} [L(s_HP,r) - L(s_LP,r)] + (1/N_LP) sum_{r>N_HP} L(s_LP,r).
+    With no LP-only noises the plain estimate (1/N_HP) sum L(s_HP,r) is
+    returned; with no HP noises, the (biased) LP mean."""
+    n_hp, n_lp = len(hp_loops), len(lp_only_loops)
+    if n_lp == 0:
+        return sum(hp_loops) / n_hp
+    if n_hp == 0:
+        return sum(lp_only_loops) / n_lp
+    corr = sum(h - l for h, l in zip(hp_loops, lp_of_hp_loops)) / n_hp
+    return corr + sum(lp_only_loops) / n_lp
+
+
+def solve_sources(L, kappa, eps, t_bc, U, srcs, tol, maxiter=100000):
+    sols, its, res = [], [], []
+    for b in srcs:
+        x, it, r = cgnr(L, kappa, eps, t_bc, U, b, tol, maxiter)
+        sols.append(x)
+        its.append(it)
+        res.append(r)
+    return sols, its, res
+
+
+def loops(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, dilution=False,
+          noise_offset=0):
+    """Plain stochastic loop estimate from n_noise Z4 noise vectors solved to
+    tol (mean over noises, eq. estiM / loopSt / loopVv / loopHPE1).
+    Returns ({estimator: (16, Lt)}, per_noise list of {estimator: (16, Lt)})."""
+    per_noise = []
+    for r in range(noise_offset, noise_offset + n_noise):
+        eta = noise_z4(L, seed, r)
+        etas = dilute_spin_colour(eta) if dilution else [eta]
+        sols, _, _ = solve_sources(L, kappa, eps, t_bc, U, etas, tol)
+        per_noise.append(loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators))
+    mean = {e: sum(p[e] for p in per_noise) / n_noise for e in per_noise[0]}
+    if estimators & EST_HPE:
+        mean[EST_HPE] = mean[EST_HPE] + hpe_exact(L, kappa, eps, t_bc, U)
+    return mean, per_noise

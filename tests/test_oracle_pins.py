@@ -1,0 +1,365 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's own formulas: each checks it against
+something independent of its code -- a closed form (free-field spectrum and
+traces, the hopping-expansion constants), an identity of the method
+(gamma5-hermiticity, M^dag M = D_W^dag D_W + eps^2, the one-end identity,
+the hopping expansion, gauge covariance), a dense brute-force computation
+(LU inverse on tiny lattices), published generator outputs, or statistics of
+the estimators.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+G5 = np.diag([1, 1, -1, -1]).astype(complex)
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def dense(f, L):
+    """Dense matrix of a linear map on spinor fields, column by column."""
+    V = int(np.prod(L))
+    n = 12 * V
+    D = np.zeros((n, n), dtype=complex)
+    for i in range(n):
+        e = np.zeros(n, dtype=complex)
+        e[i] = 1
+        D[:, i] = f(e.reshape(V, 4, 3)).ravel()
+    return D
+
+
+def slice_traces(L, A):
+    """Tr_t(Gamma_n A) = sum_{x in t} tr[(Gamma_n (x) 1_c) A_xx] for a dense A."""
+    V, Lt = int(np.prod(L)), L[3]
+    out = np.zeros((16, Lt), dtype=complex)
+    blocks = np.array([A[12 * x:12 * x + 12, 12 * x:12 * x + 12] for x in range(V)])
+    for n in range(16):
+        Gc = np.kron(O.gamma(n), np.eye(3))
+        per_site = np.einsum("ij,xji->x", Gc, blocks)
+        out[n] = per_site.reshape(Lt, -1).sum(1)
+    return out
+
+
+def g5(psi):
+    return np.einsum("ab,...bc->...ac", G5, psi)
+
+
+def momenta(L, t_bc):
+    ps = []
+    for nx in range(L[0]):
+        for ny in range(L[1]):
+            for nz in range(L[2]):
+                for nt in range(L[3]):
+                    pt = (2 * nt + (1 if t_bc == -1 else 0)) * np.pi / L[3]
+                    ps.append([2 * np.pi * nx / L[0], 2 * np.pi * ny / L[1],
+                               2 * np.pi * nz / L[2], pt])
+    return np.array(ps)
+
+
+# ---------------------------------------------------------------- gamma algebra
+
+def test_gamma_algebra():
+    g = [O.gamma(1 << mu) for mu in range(4)]
+    for m in range(4):
+        assert np.allclose(g[m], g[m].conj().T)
+        for n in range(4):
+            assert np.allclose(g[m] @ g[n] + g[n] @ g[m], 2 * np.eye(4) * (m == n), atol=0)
+    assert np.array_equal(O.gamma(0), np.eye(4))
+    assert np.allclose(O.gamma(15), G5, atol=0)  # gamma5 = g1 g2 g3 g4 is diag(1,1,-1,-1)
+    for m in range(16):
+        for n in range(16):
+            tr = np.trace(O.gamma(m).conj().T @ O.gamma(n))
+            assert abs(tr - 4 * (m == n)) < 1e-14
+    # chiral basis: gamma_4 couples upper and lower spin pairs
+    assert np.allclose(O.gamma(8), np.block([[np.zeros((2, 2)), np.eye(2)],
+                                             [np.eye(2), np.zeros((2, 2))]]))
+
+
+# ---------------------------------------------------------------- free field
+
+@pytest.mark.parametrize("t_bc", [-1, +1])
+def test_free_field_singular_values(t_bc):
+    """U = 1: singular values of M are sqrt(A^2 + eps^2 + sum_mu (2 kappa sin p_mu)^2),
+    A = 1 - 2 kappa sum_mu cos p_mu, each 12-fold; p_t odd multiples of pi/Lt
+    for antiperiodic time."""
+    L, kappa, eps = (4, 2, 2, 4), 0.13, 0.05
+    M = dense(lambda v: O.apply_M(L, kappa, eps, t_bc, S.unit_links(L), v), L)
+    sv = np.sort(np.linalg.svd(M, compute_uv=False))
+    p = momenta(L, t_bc)
+    A = 1 - 2 * kappa * np.cos(p).sum(1)
+    ex = np.sqrt(A ** 2 + eps ** 2 + 4 * kappa ** 2 * (np.sin(p) ** 2).sum(1))
+    assert np.abs(sv - np.sort(np.repeat(ex, 12))).max() < 1e-13
+
+
+def test_free_field_slice_traces_full_dilution():
+    """Every unit source solved by the oracle CG and contracted with the standard
+    estimator gives Tr_t(Gamma_n M^-1) exactly; for U = 1 that is
+    (12/Lt) sum_p A/den for n=0, -(12 i eps/Lt) sum_p 1/den for gamma5, 0 else."""
+    L, kappa, eps = (2, 2, 2, 4), 0.125, 0.1
+    U = S.unit_links(L)
+    V = int(np.prod(L))
+    tot = np.zeros((16, L[3]), dtype=complex)
+    for i in range(12 * V):
+        e = np.zeros((V, 4, 3), dtype=complex)
+        e.reshape(-1)[i] = 1
+        x, _, res = O.cgnr(L, kappa, eps, -1, U, e, 1e-13)
+        assert res < 1e-12
+        tot += O.contract_std(L, e, x)
+    p = momenta(L, -1)
+    A = 1 - 2 * kappa * np.cos(p).sum(1)
+    den = A ** 2 + eps ** 2 + 4 * kappa ** 2 * (np.sin(p) ** 2).sum(1)
+    ex0 = 12.0 / L[3] * (A / den).sum()
+    ex15 = -12j * eps / L[3] * (1 / den).sum()
+    assert np.abs(tot[0] - ex0).max() < 1e-10
+    assert np.abs(tot[15] - ex15).max() < 1e-10
+    assert np.abs(tot[1:15]).max() < 1e-10
+
+
+# ---------------------------------------------------------------- operator identities
+
+@pytest.fixture(scope="module")
+def small():
+    L = (4, 2, 2, 4)
+    return dict(L=L, kappa=0.124, eps=0.07, U=S.gauge_links(L, 0.4, 11))
+
+
+def test_adjoint_and_gamma5_hermiticity(small):
+    L, kappa, eps, U = small["L"], small["kappa"], small["eps"], small["U"]
+    v, w = S.random_spinor(L, 1), S.random_spinor(L, 2)
+    # the adjoint apply is the adjoint: <v, M w> = <M^dag v, w>
+    Mw = O.apply_M(L, kappa, eps, -1, U, w)
+    Mdv = O.apply_M(L, kappa, eps, -1, U, v, adj=True)
+    assert abs(np.vdot(v, Mw) - np.vdot(Mdv, w)) < 1e-12
+    # M(mu)^dag = gamma5 M(-mu) gamma5
+    assert np.abs(Mdv - g5(O.apply_M(L, kappa, -eps, -1, U, g5(v)))).max() < 1e-14
+    par = O.site_parity(L)
+    ve, we = v.copy(), w.copy()
+    ve[par == 1] = 0
+    we[par == 1] = 0
+    for form in (0, 1):
+        Aw = O.schur(L, kappa, eps, -1, U, we, form=form)
+        Adv = O.schur(L, kappa, eps, -1, U, ve, adj=True, form=form)
+        assert abs(np.vdot(ve, Aw) - np.vdot(Adv, we)) < 1e-12
+        assert np.abs(Aw[par == 1]).max() == 0
+    # asymmetric Schur complement: Ahat(mu)^dag = gamma5 Ahat(-mu) gamma5
+    Adv = O.schur(L, kappa, eps, -1, U, ve, adj=True)
+    assert np.abs(Adv - g5(O.schur(L, kappa, -eps, -1, U, g5(ve)))).max() < 1e-14
+
+
+def test_normal_operator_identity(small):
+    """M^dag M = D_W^dag D_W + eps^2 (twist and Wilson operator anticommute
+    up to the mass term), so sigma_min(M) >= eps."""
+    L, kappa, eps, U = small["L"], small["kappa"], small["eps"], small["U"]
+    v = S.random_spinor(L, 3)
+    MdM = O.apply_M(L, kappa, eps, -1, U, O.apply_M(L, kappa, eps, -1, U, v), adj=True)
+    DdD = O.apply_M(L, kappa, 0.0, -1, U, O.apply_M(L, kappa, 0.0, -1, U, v), adj=True)
+    assert np.abs(MdM - DdD - eps ** 2 * v).max() < 1e-13
+
+
+def test_gauge_covariance(small):
+    L, kappa, eps, U = small["L"], small["kappa"], small["eps"], small["U"]
+    V = int(np.prod(L))
+    g = S.random_su3(V, 99)
+    Ug = S.gauge_transform(L, U, g)
+    psi = S.random_spinor(L, 4)
+    gpsi = np.einsum("xab,xsb->xsa", g, psi)
+    lhs = O.apply_M(L, kappa, eps, -1, Ug, gpsi)
+    rhs = np.einsum("xab,xsb->xsa", g, O.apply_M(L, kappa, eps, -1, U, psi))
+    assert np.abs(lhs - rhs).max() < 1e-13
+    # per-noise loops: rotated noise through the rotated field gives the same loop
+    eta = O.noise_z4(L, 5, 0)
+    geta = np.einsum("xab,xsb->xsa", g, eta)
+    s, _, _ = O.cgnr(L, kappa, eps, -1, U, eta, 1e-12)
+    sg, _, _ = O.cgnr(L, kappa, eps, -1, Ug, geta, 1e-12)
+    l1 = O.loops_for_solution(L, kappa, eps, -1, U, [eta], [s], 7)
+    l2 = O.loops_for_solution(L, kappa, eps, -1, Ug, [geta], [sg], 7)
+    for e in l1:
+        assert np.abs(l1[e] - l2[e]).max() < 1e-9 * max(1, np.abs(l1[e]).max())
+    assert np.abs(O.hpe_exact(L, kappa, eps, -1, U) - O.hpe_exact(L, kappa, eps, -1, Ug)).max() \
+        < 1e-12
+
+
+# ---------------------------------------------------------------- EO and the solver
+
+def test_eo_solver_against_lu(small):
+    """CG on the Schur normal equations, odd reconstruction, and the reported
+    residual: x equals the dense LU solution, and the true full-system
+    residual is below tol."""
+    L, kappa, eps, U = small["L"], small["kappa"], small["eps"], small["U"]
+    b = S.random_spinor(L, 6)
+    M = dense(lambda v: O.apply_M(L, kappa, eps, -1, U, v), L)
+    x_lu = np.linalg.solve(M, b.ravel()).reshape(b.shape)
+    for form in (0, 1):
+        x, it, res = O.cgnr(L, kappa, eps, -1, U, b, 1e-12, form=form)
+        assert it > 0 and res < 1e-12
+        true_res = np.linalg.norm(b.ravel() - M @ x.ravel()) / np.linalg.norm(b)
+        assert abs(true_res - res) < 1e-14
+        assert np.abs(x - x_lu).max() < 1e-9
+    # odd reconstruction from the exact even part solves the odd rows exactly
+    par = O.site_parity(L)
+    xe = x_lu.copy()
+    xe[par == 1] = 0
+    full = O.reconstruct(L, kappa, eps, -1, U, b, xe)
+    assert np.abs(full - x_lu).max() < 1e-12
+    # Schur residual of the exact even part is zero
+    bh = O.source_prep(L, kappa, eps, -1, U, b)
+    assert np.abs(bh - O.schur(L, kappa, eps, -1, U, xe)).max() < 1e-12
+
+
+def test_maxiter_bounds_cg(small):
+    L, kappa, eps, U = small["L"], small["kappa"], small["eps"], small["U"]
+    b = S.random_spinor(L, 7)
+    x, it, res = O.cgnr(L, kappa, eps, -1, U, b, 1e-14, maxiter=3)
+    assert it == 3 and res > 1e-6
+
+
+# ---------------------------------------------------------------- dense brute force
+
+@pytest.fixture(scope="module")
+def dense2():
+    """2^4 lattice, random links: dense M, M_d and their inverses."""
+    L, kappa, eps = (2, 2, 2, 2), 0.124, 0.05
+    U = S.gauge_links(L, 0.5, 21)
+    M = dense(lambda v: O.apply_M(L, kappa, eps, -1, U, v), L)
+    Md = dense(lambda v: O.apply_M(L, kappa, -eps, -1, U, v), L)
+    return dict(L=L, kappa=kappa, eps=eps, U=U, M=M, Mi=np.linalg.inv(M), Mdi=np.linalg.inv(Md))
+
+
+def full_dilution_solutions(d, tol=1e-13):
+    L, V = d["L"], int(np.prod(d["L"]))
+    etas, sols = [], []
+    for i in range(12 * V):
+        e = np.zeros((V, 4, 3), dtype=complex)
+        e.reshape(-1)[i] = 1
+        x, _, res = O.cgnr(L, d["kappa"], d["eps"], -1, d["U"], e, tol)
+        assert res < 10 * tol
+        etas.append(e)
+        sols.append(x)
+    return etas, sols
+
+
+def test_dense_traces_full_dilution(dense2):
+    """Standard, one-end and HPE estimators with full dilution equal their dense
+    traces: Tr_t(Gamma M^-1), Tr_t(Gamma M_d^-1) - Tr_t(Gamma M_u^-1) (the one-end
+    identity, eq. loopVv, per time slice and for every Gamma), and again
+    Tr_t(Gamma M^-1) for the hopping expansion (its exact part computed by the
+    oracle's path sum, valid also with L = 2)."""
+    d = dense2
+    L, kappa, eps, U = d["L"], d["kappa"], d["eps"], d["U"]
+    etas, sols = full_dilution_solutions(d)
+    est = O.loops_for_solution(L, kappa, eps, -1, U, etas, sols, 7)
+    ex_u = slice_traces(L, d["Mi"])
+    ex_d = slice_traces(L, d["Mdi"])
+    assert np.abs(est[O.EST_STD] - ex_u).max() < 1e-10
+    assert np.abs(est[O.EST_ONE_END] - (ex_d - ex_u)).max() < 1e-10
+    hpe = est[O.EST_HPE] + O.hpe_exact(L, kappa, eps, -1, U)
+    assert np.abs(hpe - ex_u).max() < 1e-10
+
+
+# ---------------------------------------------------------------- hopping expansion
+
+def test_hpe_expansion_and_exact_part():
+    """M^-1 = B - BHB + (BH)^2 B - (BH)^3 B + (BH)^4 M^-1 (eq. HPE); odd powers
+    have no diagonal on a bipartite (all-even) lattice; the exact part from the
+    path sum equals the diagonal of B + (BH)^2 B from unit vectors, and for all
+    L >= 3 the closed forms
+      tr B = 12/(1+eps^2),  tr g5 B = -12 i eps/(1+eps^2),
+      tr (BH)^2 B = -384 kappa^2 eps^2/(1+eps^2)^3,
+      tr g5 (BH)^2 B = -192 i kappa^2 eps (1-eps^2)/(1+eps^2)^3  per site."""
+    L, kappa, eps = (4, 4, 2, 4), 0.124, 0.07
+    U = S.gauge_links(L, 0.4, 31)
+    H = dense(lambda v: O.hop(L, kappa, -1, U, v), L)
+    B = dense(lambda v: O.twist(L, eps, v, 2), L)
+    M = dense(lambda v: O.apply_M(L, kappa, eps, -1, U, v), L)
+    Mi = np.linalg.inv(M)
+    BH = B @ H
+    BH2 = BH @ BH
+    rhs = B - BH @ B + BH2 @ B - BH2 @ BH @ B + BH2 @ BH2 @ Mi
+    assert np.abs(rhs - Mi).max() < 1e-13
+    assert np.abs(np.diag(BH @ B)).max() < 1e-15
+    assert np.abs(np.diag(BH2 @ BH @ B)).max() < 1e-15
+    ex = slice_traces(L, B + BH2 @ B)
+    he = O.hpe_exact(L, kappa, eps, -1, U)
+    assert np.abs(he - ex).max() < 1e-12
+    # closed form on a lattice with every L >= 3 (only back-and-forth paths)
+    L3 = (4, 4, 4, 4)
+    U3 = S.gauge_links(L3, 0.4, 32)
+    he3 = O.hpe_exact(L3, kappa, eps, -1, U3)
+    Vs = 64
+    e2 = eps * eps
+    c0 = Vs * (12 / (1 + e2) - 384 * kappa ** 2 * e2 / (1 + e2) ** 3)
+    c15 = Vs * (-12j * eps / (1 + e2) - 192j * kappa ** 2 * eps * (1 - e2) / (1 + e2) ** 3)
+    assert np.abs(he3[0] - c0).max() < 1e-12 * abs(c0)
+    assert np.abs(he3[15] - c15).max() < 1e-12 * abs(c15)
+    assert np.abs(he3[1:15]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- noise
+
+def test_splitmix64_published_outputs():
+    rows = [ln.split() for ln in open(os.path.join(HERE, "golden", "splitmix64_seed0.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    for c, v in rows:
+        assert O.splitmix64(0, int(c)) == int(v, 16)
+
+
+def test_z4_noise_properties():
+    """Entries in {1, i, -1, -i}; eq. eq1 (mean -> 0) and eq. eq2
+    (eta eta^dag -> 1) at rate 1/sqrt(N)."""
+    L = (2, 2, 2, 2)
+    N = 2000
+    etas = np.array([O.noise_z4(L, 77, r).ravel() for r in range(N)])
+    assert np.all(np.isin(np.round(etas, 12), [1, 1j, -1, -1j]))
+    mean = etas.mean(0)
+    assert np.abs(mean).max() < 5 / np.sqrt(N)
+    C = etas.T @ etas.conj() / N
+    assert np.allclose(np.diag(C), 1)
+    off = C - np.eye(C.shape[0])
+    assert np.abs(off).max() < 5 / np.sqrt(N)
+    # different seeds and noise indices give different vectors
+    assert not np.array_equal(O.noise_z4(L, 77, 0), O.noise_z4(L, 78, 0))
+    assert not np.array_equal(O.noise_z4(L, 77, 0), O.noise_z4(L, 77, 1))
+
+
+# ---------------------------------------------------------------- TSM
+
+def test_tsm_reduces_to_plain_and_is_unbiased(dense2):
+    """With LP tolerance equal to HP tolerance the TSM estimate equals the plain
+    one; with truncated LP solves its mean over many independent estimates
+    equals the exact trace (eq. estiTSM)."""
+    d = dense2
+    L, kappa, eps, U = d["L"], d["kappa"], d["eps"], d["U"]
+    ex = slice_traces(L, d["Mi"])
+    est = O.EST_STD
+
+    def one(seed, n_hp, n_lp, lp_tol, hp_tol=1e-12):
+        etas = [O.noise_z4(L, seed, r) for r in range(n_hp + n_lp)]
+        lp = [O.cgnr(L, kappa, eps, -1, U, e, lp_tol)[0] for e in etas]
+        hp = [O.cgnr(L, kappa, eps, -1, U, e, hp_tol)[0] for e in etas[:n_hp]]
+        lfun = lambda e, s: O.contract_std(L, e, s)  # noqa: E731
+        return O.tsm_combine([lfun(e, s) for e, s in zip(etas, hp)],
+                             [lfun(e, s) for e, s in zip(etas, lp)],
+                             [lfun(e, s) for e, s in zip(etas[n_hp:], lp[n_hp:])])
+
+    t = one(5, 2, 6, 1e-12)
+    etas = [O.noise_z4(L, 5, r) for r in range(8)]
+    # noises 2..7 are LP-only; with exact LP the correction vanishes
+    plain_lp = sum(O.contract_std(L, e, O.cgnr(L, kappa, eps, -1, U, e, 1e-12)[0])
+                   for e in etas[2:]) / 6
+    assert np.abs(t - plain_lp).max() < 1e-9
+    K = 300
+    samples = np.array([one(1000 + k, 2, 6, 3e-1) for k in range(K)])
+    m = samples.mean(0)
+    se = samples.std(0) / np.sqrt(K)
+    z = np.abs(m - ex) / np.maximum(se, 1e-12)
+    assert np.max(z[se > 1e-12]) < 5
+    assert np.abs(m - ex)[se <= 1e-12].max(initial=0) < 1e-9
+    # the uncorrected LP mean is detectably biased at this truncation
+    lp_only = np.array([O.contract_std(L, O.noise_z4(L, 5000 + k, 0),
+                                       O.cgnr(L, kappa, eps, -1, U, O.noise_z4(L, 5000 + k, 0),
+                                              3e-1)[0]) for k in range(K)])
+    assert np.max(np.abs(lp_only.mean(0) - ex) / (lp_only.std(0) / np.sqrt(K) + 1e-30)) > 5
