@@ -1,0 +1,241 @@
+/*
+ * tm.h -- C-ABI of the MI355X (gfx950) twisted-mass solve and disconnected-loop
+ * library.
+ *
+ * The library computes the data-parallel hot path of the stochastic
+ * disconnected-quark-loop method of Alexandrou et al. (arXiv:1309.2256):
+ * Z4 noise sources (sec. II.A), even-odd preconditioned twisted-mass
+ * inversions by CG on the normal equations (sec. II.B and appendix A.1),
+ * the Truncated Solver Method (sec. II.B, eq. estiTSM), the one-end trick
+ * (sec. II.C, eq. loopVv), spin-colour dilution (sec. II.D) and the Hopping
+ * Parameter Expansion (sec. II.E, eqs. HPE and loopHPE1), with the loops at
+ * every time slice from volume sources.
+ *
+ * Operator (kappa normalisation; eps = 2 kappa mu, sec. II.E):
+ *   M(+-mu) = R(+-eps) + H,  R(eps) = 1 + i eps gamma5,  B = R^-1,
+ *   (H psi)(x) = -kappa sum_mu [ (1-gamma_mu) U_mu(x) psi(x+mu)
+ *                               +(1+gamma_mu) U_mu(x-mu)^dag psi(x-mu) ],
+ *   chiral gamma basis: gamma_k = [[0,-i sigma_k],[i sigma_k,0]],
+ *   gamma_4 = [[0,1],[1,0]], gamma5 = gamma1 gamma2 gamma3 gamma4 = diag(1,1,-1,-1).
+ *   Gamma_n = gamma1^n0 gamma2^n1 gamma3^n2 gamma4^n3 for n = n0+2n1+4n2+8n3.
+ *   Fermion boundary: periodic in space; in time per tm_lattice.t_bc.
+ * Even-odd system (appendix A.1, eq. A.2, "asymmetric"):
+ *   Ahat = R_ee - H_eo R_oo^-1 H_oe,  bhat_e = b_e - H_eo R_oo^-1 b_o,
+ *   psi_o = R_oo^-1 (b_o - H_oe psi_e).
+ *
+ * LAYOUTS
+ *   Canonical (every full-lattice FP64 argument):
+ *     site s = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2 (0 = even);
+ *     spinor field  psi[rhs][s][spin 4][colour 3]   complex double (re, im);
+ *     gauge field   U[mu 4][s][row 3][col 3]        complex double, U_mu(x)
+ *                   on the link x -> x+mu; the boundary phase is NOT in U.
+ *   Half-lattice (tm_dslash's HOP/SCHUR kinds, tm_pack/tm_unpack):
+ *     one parity p, half-site index i = s >> 1 over the sites of parity p
+ *     (unique because Lx is even), structure of arrays:
+ *     element (rhs r, spin a, colour c, half-site i) at complex offset
+ *     (r*12 + 3*a + c) * (V/2) + i, each complex stored as (re, im) pairs of
+ *     the precision given (double, float, IEEE binary16, bfloat16).
+ *
+ * OWNERSHIP AND STREAMS
+ *   Every pointer argument is owned by the caller; the library never frees
+ *   or retains it past the call.  Device pointers must be on the context's
+ *   device.  The library owns its own work buffers (allocated on first use,
+ *   freed by tm_destroy).  All device work is enqueued on the stream given
+ *   (0 = the null stream); tm_solve and tm_loops synchronise that stream
+ *   before returning (they read convergence data), tm_dslash/tm_pack/
+ *   tm_unpack/tm_set_gauge do not.
+ *
+ * ERRORS
+ *   Every call returns a tm_status.  Arguments are validated before any
+ *   launch; on failure tm_last_error(ctx) gives a message.  No C++ exception
+ *   crosses this boundary.  A context is used by one host thread at a time.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tm_ctx tm_ctx;
+typedef void *tm_stream; /* hipStream_t */
+
+typedef enum {
+    TM_OK = 0,
+    TM_ERR_ARG = -1,         /* invalid argument (nothing was launched) */
+    TM_ERR_HIP = -2,         /* a HIP runtime call failed */
+    TM_ERR_OOM = -3,         /* device allocation failed */
+    TM_ERR_NOCONV = -4,      /* a solve reached maxiter; x holds the last iterate */
+    TM_ERR_NAN = -5,         /* NaN/Inf met in a solver reduction */
+    TM_ERR_UNSUPPORTED = -6  /* valid request that this build does not implement */
+} tm_status;
+
+typedef enum { TM_F64 = 0, TM_F32 = 1, TM_F16 = 2, TM_BF16 = 3 } tm_prec;
+
+typedef struct {
+    int L[4];            /* Lx, Ly, Lz, Lt: all even, Lx >= 2 */
+    double kappa;        /* hopping parameter */
+    double two_kappa_mu; /* eps = 2 kappa mu (twisted mass, kappa normalised) */
+    int t_bc;            /* -1 antiperiodic in time (default), +1 periodic */
+} tm_lattice;
+
+/* Create a context on HIP device `device` for the given lattice.
+ * Returns TM_ERR_ARG for odd or non-positive extents. */
+int tm_create(tm_ctx **ctx, const tm_lattice *lat, int device);
+
+/* Destroy a context and free every buffer it owns.  NULL is ignored. */
+void tm_destroy(tm_ctx *ctx);
+
+/* Message for the last failing call on ctx ("" if none). */
+const char *tm_last_error(const tm_ctx *ctx);
+
+/* Upload the gauge field.  U: device pointer, canonical [4][V][3][3] complex
+ * double.  Builds the internal even-odd link layout (forward links and
+ * pre-conjugated backward links per site, boundary phase folded in) in FP64,
+ * and the FP32 copy on first use by a FP32-link kernel (round to nearest
+ * even).  U is not retained. */
+int tm_set_gauge(tm_ctx *ctx, const double *U, tm_stream stream);
+
+/* Operator kinds of tm_dslash. */
+typedef enum {
+    TM_HOP_EO = 0,      /* out_e = H_eo in_o                     (half layout)  */
+    TM_HOP_OE = 1,      /* out_o = H_oe in_e                     (half layout)  */
+    TM_RINV_HOP_OE = 2, /* out_o = R_oo^-1 H_oe in_e             (half layout)  */
+    TM_SCHUR = 3,       /* out_e = Ahat in_e                     (half layout)  */
+    TM_SCHUR_DAG = 4,   /* out_e = Ahat^dag in_e = g5 Ahat(-mu) g5 in_e         */
+    TM_NORMAL = 5,      /* out_e = Ahat^dag Ahat in_e            (half layout)  */
+    TM_FULL = 6,        /* out = M in, canonical full FP64 spinors              */
+    TM_FULL_DAG = 7,    /* out = M^dag in, canonical full FP64 spinors          */
+    TM_RINV_HOP_EO = 8  /* out_e = R_ee^-1 H_eo in_o             (half layout)  */
+} tm_dslash_kind;
+
+/* Apply the operator of `kind` to nrhs right-hand sides.
+ *   in, out     device pointers; half layout in spinor_prec for the half
+ *               kinds, canonical FP64 for TM_FULL/TM_FULL_DAG (spinor_prec
+ *               and link_prec must then be TM_F64).  in != out.
+ *   mu_sign     +1: M_u (twist +eps), -1: M_d (twist -eps), sec. II.C.
+ *   spinor_prec TM_F64 (links TM_F64) or TM_F32/TM_F16/TM_BF16 (links TM_F32);
+ *               half/bf16 storage is computed in FP32.
+ * Enqueued on `stream`; does not synchronise. */
+int tm_dslash(tm_ctx *ctx, void *out, const void *in, int nrhs, int kind, int mu_sign,
+              int spinor_prec, int link_prec, tm_stream stream);
+
+/* Canonical full FP64 spinors [nrhs][V][4][3] -> two half-layout fields
+ * (even, odd) in precision `prec`, each element multiplied by scale[r]
+ * (scale may be NULL = 1).  Conversions round to nearest even. */
+int tm_pack(tm_ctx *ctx, void *even, void *odd, const double *full, int nrhs, int prec,
+            const double *scale_host, tm_stream stream);
+/* Inverse of tm_pack (exact for FP64). */
+int tm_unpack(tm_ctx *ctx, double *full, const void *even, const void *odd, int nrhs,
+              int prec, tm_stream stream);
+
+/* Solver schemes. */
+typedef enum {
+    TM_CG_F64 = 0,   /* plain FP64 CGNR on the even-odd system */
+    TM_CG_MIXED = 1, /* CGNR with FP32 arithmetic and inner_prec storage, FP64
+                        reliable updates (true residual recomputed in FP64) */
+    TM_CG_LOW = 2    /* truncated low-precision CGNR (TSM low-precision solve):
+                        inner_prec storage, FP32 arithmetic, no reliable update;
+                        stops on the iterated residual */
+} tm_solver;
+
+typedef struct {
+    double tol;       /* target |b - M x| / |b| per right-hand side (> 0)        */
+    int maxiter;      /* iteration cap (CG iterations, > 0)                      */
+    int solver;       /* tm_solver                                               */
+    int inner_prec;   /* TM_F32, TM_F16 or TM_BF16 storage (MIXED, LOW)          */
+    double delta;     /* reliable-update trigger: update when the iterated Schur
+                         residual falls below delta x its value at the last
+                         update (MIXED; 0 selects 0.1)                           */
+    int mu_sign;      /* +1 u flavour, -1 d flavour                              */
+    int check_every;  /* iterations between host convergence checks (0 = 8)      */
+} tm_solve_params;
+
+typedef struct {
+    int iters;            /* CG iterations                                      */
+    int n_reliable;       /* reliable updates performed                         */
+    int converged;        /* 1 when |b - M x| <= tol |b| at exit                 */
+    int reserved;
+    double true_rel_res;  /* |b - M x| / |b| recomputed in FP64 at exit         */
+    double iter_rel_res;  /* the solver's own (iterated) residual at exit       */
+    double seconds;       /* wall time of the whole call                        */
+} tm_solve_stats;
+
+/* Solve M(mu_sign) x = b for nrhs right-hand sides at once.
+ *   x, b   device, canonical full FP64 [nrhs][V][4][3]; x is output only.
+ *   stats  host array of nrhs entries (may be NULL).
+ * Returns TM_ERR_NOCONV if any right-hand side missed tol within maxiter
+ * (x then holds the last iterates), TM_ERR_NAN on NaN/Inf. */
+int tm_solve(tm_ctx *ctx, double *x, const double *b, int nrhs, const tm_solve_params *p,
+             tm_solve_stats *stats, tm_stream stream);
+
+/* Z4 noise vector number r (sec. II.A: entries from {1, i, -1, -i}) as
+ * canonical full FP64 spinors; entry (site s, spin a, colour c) is i^k with k
+ * the top two bits of SplitMix64 output ((r*V + s)*4 + a)*3 + c of the stream
+ * seeded with `seed` (Steele, Lea & Flood 2014: output n is the finaliser of
+ * seed + (n+1)*0x9e3779b97f4a7c15).  dilution = TM_DIL_SPIN_COLOUR writes
+ * 12 sources, source d = 3a + c keeping only that component (sec. II.D).
+ *   out  device, [1 or 12][V][4][3] complex double. */
+int tm_noise(tm_ctx *ctx, double *out, uint64_t seed, long r, int dilution, tm_stream stream);
+
+/* Loop estimators (bit mask). */
+enum {
+    TM_EST_STD = 1,     /* sum_x eta^dag Gamma_n s            (eq. loopSt)       */
+    TM_EST_ONE_END = 2, /* 2 i eps sum_x s^dag gamma5 Gamma_n s  (eq. loopVv);
+                           estimates Tr_t(Gamma M_d^-1) - Tr_t(Gamma M_u^-1)
+                           for s = M_u^-1 eta (mu_sign = +1)                    */
+    TM_EST_HPE = 4      /* exact part + sum_x eta^dag Gamma_n (BH)^4 s (eqs. HPE,
+                           loopHPE1); requires every L_mu >= 4                  */
+};
+
+typedef enum { TM_DIL_NONE = 0, TM_DIL_SPIN_COLOUR = 1 } tm_dilution;
+
+typedef struct {
+    uint64_t seed;        /* Z4 noise stream seed                                 */
+    int n_hp;             /* noises 0..n_hp-1 get high-precision solves           */
+    int n_lp;             /* noises n_hp..n_hp+n_lp-1 get low-precision solves only;
+                             noises 0..n_hp-1 also get a low-precision solve when
+                             n_lp > 0 (TSM, eq. estiTSM).  n_lp = 0: plain HP.   */
+    int noise_offset;     /* index of the first noise vector (resume support)     */
+    int dilution;         /* tm_dilution                                          */
+    int estimators;       /* TM_EST_* mask                                        */
+    int mu_sign;          /* flavour inverted: +1 u, -1 d                         */
+    int reserved;
+    tm_solve_params hp;   /* high-precision solve parameters                      */
+    tm_solve_params lp;   /* low-precision solve parameters (n_lp > 0)            */
+} tm_loop_params;
+
+typedef struct {
+    int n_solves_hp, n_solves_lp;
+    int iters_hp, iters_lp;      /* summed CG iterations                          */
+    double max_res_hp, max_res_lp; /* worst true relative residual               */
+    double seconds;
+} tm_loop_stats;
+
+/* Estimate the disconnected loops L_n(t) for the 16 Gamma_n at every time
+ * slice t from Z4 volume noise.  Noise vector r has entries i^k, k the top two
+ * bits of SplitMix64 output ((r*V + s)*4 + spin)*3 + colour of `seed`.
+ *   loops      host, [n_est][16][Lt] complex double, estimators in mask order
+ *              (STD, ONE_END, HPE); the TSM combination (or plain mean).
+ *   per_noise  host or NULL: [n_noise][2][n_est][16][Lt] complex double,
+ *              index 0 = high precision, 1 = low precision (zero when absent),
+ *              n_noise = n_hp + n_lp.  The HPE entries hold only the
+ *              stochastic part; its exact part is added to `loops` once.
+ *   stats      host or NULL.
+ * Returns TM_ERR_NOCONV when a high-precision solve missed its tolerance. */
+int tm_loops(tm_ctx *ctx, const tm_loop_params *p, double *loops, double *per_noise,
+             tm_loop_stats *stats, tm_stream stream);
+
+/* Contract given full FP64 spinors (device, canonical, nrhs each) into
+ * per-time-slice loops for the estimators in `estimators` (STD uses eta and s,
+ * ONE_END uses s only; HPE is not accepted here).  Sums over the nrhs pairs.
+ * out: host [n_est][16][Lt] complex double. */
+int tm_contract(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int estimators,
+                int mu_sign, double *out, tm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TM_H */

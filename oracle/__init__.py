@@ -66,6 +66,8 @@ def lib():
                                   dp, dp, dp, ctypes.c_int]
         L.or_hpe_exact.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    dp, dp]
+        L.or_schur_at.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                  dp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
         L.or_site_parity.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_int)]
         L.or_neighbours.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_long)]
         _lib = L
@@ -151,6 +153,16 @@ def schur(L, kappa, eps, t_bc, U, psi, adj=False, form=0):
     out = np.empty_like(psi)
     lib().or_schur(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(psi), _p(out),
                    int(adj), int(form))
+    return out
+
+
+def schur_at(L, kappa, eps, t_bc, U, psi, sites):
+    """(Ahat psi)(s) for the even sites s in `sites` -> (n, 4, 3); for large lattices."""
+    U, psi = _links(L, U), _spinor(L, psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int_)
+    out = np.empty((len(sites), 4, 3), dtype=np.complex128)
+    lib().or_schur_at(_L(L), float(kappa), float(eps), int(t_bc), _p(U), _p(psi),
+                      sites.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(sites), _p(out))
     return out
 
 

@@ -712,3 +712,80 @@ void or_hpe_exact(const int L[4], double kappa, double eps, int t_bc, const doub
         }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* sampled evaluation for large lattices                               */
+/* ------------------------------------------------------------------ */
+
+/* one row block of H applied to psi at site s: (H psi)(s) (adj = 0) */
+static void hop_at(const int L[4], double kappa, int t_bc, const cplx *U, const cplx *psi, long s,
+                   cplx out[12], const cplx Pm[4][4][4], const cplx Pp[4][4][4], long V)
+{
+    cplx acc[12] = {0};
+    for (int mu = 0; mu < 4; mu++) {
+        double phf, phb;
+        long sf = step(L, t_bc, s, mu, +1, &phf);
+        long sb = step(L, t_bc, s, mu, -1, &phb);
+        add_block(acc, -kappa * phf, (const cplx(*)[4])Pm[mu], U + 9 * ((long)mu * V + s), 0, psi + 12 * sf);
+        add_block(acc, -kappa * phb, (const cplx(*)[4])Pp[mu], U + 9 * ((long)mu * V + sb), 1, psi + 12 * sb);
+    }
+    memcpy(out, acc, sizeof(acc));
+}
+
+/*
+ * (Ahat x)(s) = R x(s) - sum_y H[s][y] R^-1 (H x)(y) at the even sites listed
+ * in `sites` (form A.2), evaluated row by row from the definition, for
+ * lattices too large for the full-vector routines; x is a full vector whose
+ * odd sites are ignored.  out: [nsites][12].
+ */
+void or_schur_at(const int L[4], double kappa, double eps, int t_bc, const double *Ud,
+                 const double *xd, const long *sites, long nsites, double *outd)
+{
+    const cplx *U = (const cplx *)Ud, *x = (const cplx *)xd;
+    cplx *out = (cplx *)outd;
+    long V = vol(L);
+    cplx Pm[4][4][4], Pp[4][4][4], R[4][4], Ri[4][4];
+    for (int mu = 0; mu < 4; mu++) {
+        cplx g[4][4];
+        gamma_mu(mu, g);
+        for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++) {
+                Pm[mu][i][j] = (i == j) - g[i][j];
+                Pp[mu][i][j] = (i == j) + g[i][j];
+            }
+    }
+    twist_matrix(eps, 0, R);
+    twist_matrix(eps, 2, Ri);
+#pragma omp parallel for schedule(dynamic)
+    for (long n = 0; n < nsites; n++) {
+        long s = sites[n];
+        /* x restricted to even sites, read through a masked copy of the
+         * neighbourhood: the odd values needed are (R^-1 H x_e)(y) for the 8
+         * odd neighbours y of s */
+        cplx acc[12] = {0};
+        for (int mu = 0; mu < 4; mu++)
+            for (int d = 0; d < 2; d++) {
+                double ph;
+                long y = step(L, t_bc, s, mu, d ? -1 : +1, &ph);
+                /* (H x_e)(y): every neighbour of the odd site y is even */
+                cplx hy[12], ry[12];
+                hop_at(L, kappa, t_bc, U, x, y, hy, (const cplx(*)[4][4])Pm, (const cplx(*)[4][4])Pp, V);
+                for (int a = 0; a < 4; a++)
+                    for (int c = 0; c < 3; c++) {
+                        cplx t = 0;
+                        for (int b = 0; b < 4; b++) t += Ri[a][b] * hy[3 * b + c];
+                        ry[3 * a + c] = t;
+                    }
+                /* block H[s][y] applied to ry */
+                const cplx *Ublk = d ? U + 9 * ((long)mu * V + y) : U + 9 * ((long)mu * V + s);
+                add_block(acc, -kappa * ph, d ? (const cplx(*)[4])Pp[mu] : (const cplx(*)[4])Pm[mu], Ublk, d,
+                          ry);
+            }
+        for (int a = 0; a < 4; a++)
+            for (int c = 0; c < 3; c++) {
+                cplx t = 0;
+                for (int b = 0; b < 4; b++) t += R[a][b] * x[12 * s + 3 * b + c];
+                out[12 * n + 3 * a + c] = t - acc[3 * a + c];
+            }
+    }
+}

@@ -34,4 +34,6 @@ void or_bh_power(const int L[4], double kappa, double eps, int t_bc, const doubl
                  const double *in, double *out, int k);
 void or_hpe_exact(const int L[4], double kappa, double eps, int t_bc, const double *U,
                   double *out);
+void or_schur_at(const int L[4], double kappa, double eps, int t_bc, const double *U,
+                 const double *x, const long *sites, long nsites, double *out);
 #endif

@@ -1,0 +1,203 @@
+"""ctypes binding of the C-ABI in include/tm.h (argument marshalling only).
+
+Every function here forwards to libtm.so, the gfx950 HIP library built from
+csrc/; there is no fallback path: importing this module raises if the
+library is missing.  Device buffers are passed as torch tensors (their
+data_ptr()) and the work is enqueued on torch's current HIP stream unless a
+stream handle is given.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libtm.so is not built (run paper_1309_2256_amd/build.py or "
+                      "__graft_entry__.build()); there is no non-HIP fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants (tm.h)
+TM_OK, TM_ERR_ARG, TM_ERR_HIP, TM_ERR_OOM, TM_ERR_NOCONV, TM_ERR_NAN, TM_ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+TM_F64, TM_F32, TM_F16, TM_BF16 = 0, 1, 2, 3
+(TM_HOP_EO, TM_HOP_OE, TM_RINV_HOP_OE, TM_SCHUR, TM_SCHUR_DAG, TM_NORMAL, TM_FULL, TM_FULL_DAG,
+ TM_RINV_HOP_EO) = range(9)
+TM_CG_F64, TM_CG_MIXED, TM_CG_LOW = 0, 1, 2
+TM_EST_STD, TM_EST_ONE_END, TM_EST_HPE = 1, 2, 4
+TM_DIL_NONE, TM_DIL_SPIN_COLOUR = 0, 1
+
+STATUS_NAMES = {0: "TM_OK", -1: "TM_ERR_ARG", -2: "TM_ERR_HIP", -3: "TM_ERR_OOM",
+                -4: "TM_ERR_NOCONV", -5: "TM_ERR_NAN", -6: "TM_ERR_UNSUPPORTED"}
+PREC_BYTES = {TM_F64: 16, TM_F32: 8, TM_F16: 4, TM_BF16: 4}
+
+
+class tm_lattice(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 4), ("kappa", ctypes.c_double),
+                ("two_kappa_mu", ctypes.c_double), ("t_bc", ctypes.c_int)]
+
+
+class tm_solve_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("solver", ctypes.c_int),
+                ("inner_prec", ctypes.c_int), ("delta", ctypes.c_double),
+                ("mu_sign", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class tm_solve_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("n_reliable", ctypes.c_int), ("converged", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("true_rel_res", ctypes.c_double),
+                ("iter_rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class tm_loop_params(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_hp", ctypes.c_int), ("n_lp", ctypes.c_int),
+                ("noise_offset", ctypes.c_int), ("dilution", ctypes.c_int),
+                ("estimators", ctypes.c_int), ("mu_sign", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("hp", tm_solve_params), ("lp", tm_solve_params)]
+
+
+class tm_loop_stats(ctypes.Structure):
+    _fields_ = [("n_solves_hp", ctypes.c_int), ("n_solves_lp", ctypes.c_int),
+                ("iters_hp", ctypes.c_int), ("iters_lp", ctypes.c_int),
+                ("max_res_hp", ctypes.c_double), ("max_res_lp", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "tm_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(tm_lattice), ctypes.c_int]),
+    "tm_destroy": (None, [_vp]),
+    "tm_last_error": (ctypes.c_char_p, [_vp]),
+    "tm_set_gauge": (ctypes.c_int, [_vp, _vp, _vp]),
+    "tm_dslash": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, _vp]),
+    "tm_pack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _dp, _vp]),
+    "tm_unpack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "tm_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(tm_solve_params),
+                                ctypes.POINTER(tm_solve_stats), _vp]),
+    "tm_loops": (ctypes.c_int, [_vp, ctypes.POINTER(tm_loop_params), _dp, _dp,
+                                ctypes.POINTER(tm_loop_stats), _vp]),
+    "tm_noise": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, ctypes.c_long, ctypes.c_int, _vp]),
+    "tm_contract": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                   _vp]),
+}
+EXPORTED = tuple(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+class TMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def solve_params(tol=1e-9, maxiter=100000, solver=TM_CG_F64, inner_prec=TM_F32, delta=0.1,
+                 mu_sign=1, check_every=8):
+    return tm_solve_params(tol, maxiter, solver, inner_prec, delta, mu_sign, check_every)
+
+
+class Context:
+    """One library context (lattice + gauge field) on one HIP device."""
+
+    def __init__(self, L, kappa, two_kappa_mu, t_bc=-1, device=0):
+        self.L = tuple(int(v) for v in L)
+        self.V = int(np.prod(self.L))
+        self.vh = self.V // 2
+        lat = tm_lattice((ctypes.c_int * 4)(*self.L), kappa, two_kappa_mu, t_bc)
+        h = ctypes.c_void_p()
+        st = tm_create(ctypes.byref(h), ctypes.byref(lat), device)
+        if st != TM_OK:
+            raise TMError(st, "tm_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            tm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=()):
+        if st != TM_OK and st not in allow:
+            raise TMError(st, tm_last_error(self.h).decode())
+        return st
+
+    def half_numel(self, prec, nrhs=1):
+        """Bytes of a half-lattice field of nrhs right-hand sides."""
+        return PREC_BYTES[prec] * 12 * self.vh * nrhs
+
+    def set_gauge(self, U, stream=None):
+        self._check(tm_set_gauge(self.h, _ptr(U), _stream(stream)))
+
+    def dslash(self, out, inp, nrhs, kind, mu_sign=1, spinor_prec=TM_F64, link_prec=None,
+               stream=None):
+        if link_prec is None:
+            link_prec = TM_F64 if spinor_prec == TM_F64 else TM_F32
+        self._check(tm_dslash(self.h, _ptr(out), _ptr(inp), nrhs, kind, mu_sign, spinor_prec,
+                              link_prec, _stream(stream)))
+
+    def pack(self, even, odd, full, nrhs, prec, scale=None, stream=None):
+        sc = None
+        if scale is not None:
+            arr = (ctypes.c_double * nrhs)(*scale)
+            sc = ctypes.cast(arr, _dp)
+        self._check(tm_pack(self.h, _ptr(even), _ptr(odd), _ptr(full), nrhs, prec, sc,
+                            _stream(stream)))
+
+    def unpack(self, full, even, odd, nrhs, prec, stream=None):
+        self._check(tm_unpack(self.h, _ptr(full), _ptr(even), _ptr(odd), nrhs, prec,
+                              _stream(stream)))
+
+    def solve(self, x, b, nrhs, params, stream=None, allow_noconv=False):
+        stats = (tm_solve_stats * nrhs)()
+        st = tm_solve(self.h, _ptr(x), _ptr(b), nrhs, ctypes.byref(params), stats,
+                      _stream(stream))
+        self._check(st, allow=(TM_ERR_NOCONV,) if allow_noconv else ())
+        return st, list(stats)
+
+    def loops(self, params, per_noise=False, stream=None, allow_noconv=False):
+        n_est = bin(params.estimators).count("1")
+        Lt = self.L[3]
+        out = np.zeros((n_est, 16, Lt), dtype=np.complex128)
+        n_noise = params.n_hp + params.n_lp
+        pn = np.zeros((n_noise, 2, n_est, 16, Lt), dtype=np.complex128) if per_noise else None
+        stats = tm_loop_stats()
+        st = tm_loops(self.h, ctypes.byref(params), out.ctypes.data_as(_dp),
+                      pn.ctypes.data_as(_dp) if pn is not None else None, ctypes.byref(stats),
+                      _stream(stream))
+        self._check(st, allow=(TM_ERR_NOCONV,) if allow_noconv else ())
+        return out, pn, stats, st
+
+    def noise(self, out, seed, r, dilution=TM_DIL_NONE, stream=None):
+        self._check(tm_noise(self.h, _ptr(out), ctypes.c_uint64(seed), r, dilution,
+                             _stream(stream)))
+
+    def contract(self, eta, s, nrhs, estimators, mu_sign=1, stream=None):
+        n_est = bin(estimators).count("1")
+        out = np.zeros((n_est, 16, self.L[3]), dtype=np.complex128)
+        self._check(tm_contract(self.h, _ptr(eta), _ptr(s), nrhs, estimators, mu_sign,
+                                out.ctypes.data_as(_dp), _stream(stream)))
+        return out

@@ -1,0 +1,338 @@
+// C-ABI entry points (declared in include/tm.h).  Every function validates its
+// arguments before launching, converts internal errors to tm_status codes and
+// records a message retrievable with tm_last_error.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "runtime.h"
+
+// ---------------------------------------------------------------- context helpers
+
+void *ws_get(tm_ctx *c, const std::string &name, size_t bytes)
+{
+    DevBuf &b = c->ws[name];
+    if (b.p && b.bytes >= bytes) return b.p;
+    if (b.p) {
+        TM_HIP(hipDeviceSynchronize());
+        TM_HIP(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        throw TmError{TM_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed (" + name + ")"};
+    }
+    b.p = p;
+    b.bytes = bytes;
+    return p;
+}
+
+void *host_stage(tm_ctx *c, size_t bytes)
+{
+    if (c->host_pinned && c->host_pinned_bytes >= bytes) return c->host_pinned;
+    if (c->host_pinned) TM_HIP(hipHostFree(c->host_pinned));
+    c->host_pinned = nullptr;
+    size_t n = bytes < 4096 ? 4096 : bytes;
+    TM_HIP(hipHostMalloc(&c->host_pinned, n, hipHostMallocDefault));
+    c->host_pinned_bytes = n;
+    return c->host_pinned;
+}
+
+void ensure_links32(tm_ctx *c, hipStream_t s)
+{
+    if (c->have_links32) return;
+    for (int p = 0; p < 2; p++)
+        if (!c->links32[p]) c->links32[p] = ws_get(c, p ? "links32_1" : "links32_0", (size_t)72 * c->geo.vh * 8);
+    launch_links_to_f32(c, s);
+    c->have_links32 = true;
+}
+
+namespace {
+
+template <typename F>
+int guarded(tm_ctx *c, F &&f)
+{
+    if (!c) return TM_ERR_ARG;
+    try {
+        c->err.clear();
+        TM_HIP(hipSetDevice(c->device));
+        return f();
+    } catch (const TmError &e) {
+        c->err = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        c->err = "host allocation failed";
+        return TM_ERR_OOM;
+    } catch (...) {
+        c->err = "unexpected internal error";
+        return TM_ERR_HIP;
+    }
+}
+
+hipStream_t hs(tm_stream s) { return (hipStream_t)s; }
+
+size_t half_bytes(tm_ctx *c, int prec, int nrhs) { return prec_bytes(prec) * 12 * (size_t)c->geo.vh * nrhs; }
+
+bool valid_prec(int p) { return p == TM_F64 || p == TM_F32 || p == TM_F16 || p == TM_BF16; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- lifecycle
+
+extern "C" int tm_create(tm_ctx **out, const tm_lattice *lat, int device)
+{
+    if (!out || !lat) return TM_ERR_ARG;
+    *out = nullptr;
+    long V = 1;
+    for (int mu = 0; mu < 4; mu++) {
+        if (lat->L[mu] < 2 || (lat->L[mu] & 1)) return TM_ERR_ARG;
+        V *= lat->L[mu];
+    }
+    if (V / 2 > (1L << 30)) return TM_ERR_ARG;
+    if (!std::isfinite(lat->kappa) || !std::isfinite(lat->two_kappa_mu)) return TM_ERR_ARG;
+    if (lat->t_bc != 1 && lat->t_bc != -1) return TM_ERR_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TM_ERR_HIP;
+    tm_ctx *c = new (std::nothrow) tm_ctx();
+    if (!c) return TM_ERR_OOM;
+    c->device = device;
+    c->lat = *lat;
+    for (int mu = 0; mu < 4; mu++) c->geo.L[mu] = lat->L[mu];
+    c->V = V;
+    c->geo.lxh = lat->L[0] / 2;
+    c->geo.vh = (int)(V / 2);
+    c->geo.vsh = lat->L[0] * lat->L[1] * lat->L[2] / 2;
+    c->kappa = lat->kappa;
+    c->eps = lat->two_kappa_mu;
+    c->t_bc = lat->t_bc;
+    *out = c;
+    return TM_OK;
+}
+
+extern "C" void tm_destroy(tm_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->ws)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    for (int p = 0; p < 2; p++)
+        if (c->links64[p]) (void)hipFree(c->links64[p]);
+    if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    delete c;
+}
+
+extern "C" const char *tm_last_error(const tm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(U != nullptr, "null gauge field");
+        for (int p = 0; p < 2; p++)
+            if (!c->links64[p]) {
+                void *q = nullptr;
+                if (hipMalloc(&q, (size_t)72 * c->geo.vh * 16) != hipSuccess) {
+                    (void)hipGetLastError();
+                    throw TmError{TM_ERR_OOM, "link allocation failed"};
+                }
+                c->links64[p] = q;
+            }
+        launch_gauge_ingest(c, U, hs(stream));
+        c->have_gauge = true;
+        c->have_links32 = false;
+        return TM_OK;
+    });
+}
+
+// ---------------------------------------------------------------- dslash
+
+extern "C" int tm_dslash(tm_ctx *c, void *out, const void *in, int nrhs, int kind, int mu_sign, int spinor_prec,
+                         int link_prec, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(out && in && out != in, "out and in must be distinct non-null pointers");
+        TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
+        TM_REQUIRE(valid_prec(spinor_prec), "bad spinor precision");
+        TM_REQUIRE(c->have_gauge, "no gauge field set");
+        if (spinor_prec == TM_F64)
+            TM_REQUIRE(link_prec == TM_F64, "FP64 spinors need FP64 links");
+        else
+            TM_REQUIRE(link_prec == TM_F32, "FP32/FP16/BF16 spinors use FP32 links");
+        hipStream_t s = hs(stream);
+        const double epsp = eps_of(c, mu_sign), k = c->kappa;
+        switch (kind) {
+        case TM_HOP_EO:
+        case TM_HOP_OE:
+            op_dslash(c, out, in, nullptr, nrhs, spinor_prec, kind == TM_HOP_OE, 0, sd_scalar(-k), sd_scalar(0), s);
+            break;
+        case TM_RINV_HOP_OE:
+        case TM_RINV_HOP_EO:
+            op_dslash(c, out, in, nullptr, nrhs, spinor_prec, kind == TM_RINV_HOP_OE, 0,
+                      sd_mul(sd_scalar(-k), sd_twist_inv(epsp)), sd_scalar(0), s);
+            break;
+        case TM_SCHUR:
+            op_schur(c, out, in, ws_get(c, "d_tmp", half_bytes(c, spinor_prec, nrhs)), nrhs, spinor_prec, epsp, s);
+            break;
+        case TM_SCHUR_DAG:
+            op_schur_dag(c, out, in, ws_get(c, "d_tmp", half_bytes(c, spinor_prec, nrhs)), nrhs, spinor_prec, epsp,
+                         s);
+            break;
+        case TM_NORMAL: {
+            void *tmp = ws_get(c, "d_tmp", half_bytes(c, spinor_prec, nrhs));
+            void *mid = ws_get(c, "d_mid", half_bytes(c, spinor_prec, nrhs));
+            op_schur(c, mid, in, tmp, nrhs, spinor_prec, epsp, s);
+            op_schur_dag(c, out, mid, tmp, nrhs, spinor_prec, epsp, s);
+            break;
+        }
+        case TM_FULL:
+        case TM_FULL_DAG: {
+            TM_REQUIRE(spinor_prec == TM_F64, "full-lattice kinds take canonical FP64 spinors");
+            const size_t b = half_bytes(c, TM_F64, nrhs);
+            void *ie = ws_get(c, "d_ie", b), *io = ws_get(c, "d_io", b);
+            void *oe = ws_get(c, "d_oe", b), *oo = ws_get(c, "d_oo", b);
+            launch_pack(c, ie, io, (const double *)in, nrhs, TM_F64, nullptr, s);
+            const int dag = kind == TM_FULL_DAG;
+            // M = R(eps) + H;  M^dag = R(-eps) + H^dag
+            const SpinDiag tw = sd_twist(dag ? -epsp : epsp);
+            op_dslash(c, oe, io, ie, nrhs, TM_F64, 0, dag, sd_scalar(-k), tw, s);
+            op_dslash(c, oo, ie, io, nrhs, TM_F64, 1, dag, sd_scalar(-k), tw, s);
+            launch_unpack(c, (double *)out, oe, oo, nrhs, TM_F64, s);
+            break;
+        }
+        default: throw TmError{TM_ERR_ARG, "unknown dslash kind"};
+        }
+        return TM_OK;
+    });
+}
+
+// ---------------------------------------------------------------- layout
+
+extern "C" int tm_pack(tm_ctx *c, void *even, void *odd, const double *full, int nrhs, int prec,
+                       const double *scale_host, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(even && odd && full, "null pointer");
+        TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        TM_REQUIRE(valid_prec(prec), "bad precision");
+        double *ds = nullptr;
+        if (scale_host) {
+            ds = (double *)ws_get(c, "pack_scale", sizeof(double) * nrhs);
+            TM_HIP(hipMemcpyAsync(ds, scale_host, sizeof(double) * nrhs, hipMemcpyHostToDevice, hs(stream)));
+            TM_HIP(hipStreamSynchronize(hs(stream)));
+        }
+        launch_pack(c, even, odd, full, nrhs, prec, ds, hs(stream));
+        return TM_OK;
+    });
+}
+
+extern "C" int tm_unpack(tm_ctx *c, double *full, const void *even, const void *odd, int nrhs, int prec,
+                         tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(even && odd && full, "null pointer");
+        TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        TM_REQUIRE(valid_prec(prec), "bad precision");
+        launch_unpack(c, full, even, odd, nrhs, prec, hs(stream));
+        return TM_OK;
+    });
+}
+
+// ---------------------------------------------------------------- solve
+
+extern "C" int tm_solve(tm_ctx *c, double *x, const double *b, int nrhs, const tm_solve_params *p,
+                        tm_solve_stats *stats, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        const auto t0 = std::chrono::steady_clock::now();
+        TM_REQUIRE(x && b && p, "null pointer");
+        TM_REQUIRE(x != b, "x and b must differ");
+        TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        TM_REQUIRE(c->have_gauge, "no gauge field set");
+        hipStream_t s = hs(stream);
+        const size_t hb = half_bytes(c, TM_F64, nrhs);
+        void *be = ws_get(c, "a_be", hb), *bo = ws_get(c, "a_bo", hb);
+        void *xe = ws_get(c, "a_xe", hb), *xo = ws_get(c, "a_xo", hb);
+        launch_pack(c, be, bo, b, nrhs, TM_F64, nullptr, s);
+        SolveOut r = solve_halves(c, xe, xo, be, bo, nrhs, *p, s);
+        launch_unpack(c, x, xe, xo, nrhs, TM_F64, s);
+        TM_HIP(hipStreamSynchronize(s));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats)
+            for (int i = 0; i < nrhs; i++) {
+                stats[i] = r.st[i];
+                stats[i].seconds = secs;
+            }
+        if (r.status == TM_ERR_NOCONV) c->err = "a right-hand side missed the tolerance within maxiter";
+        if (r.status == TM_ERR_NAN) c->err = "NaN/Inf in the solution";
+        return r.status;
+    });
+}
+
+// ---------------------------------------------------------------- noise and loops
+
+extern "C" int tm_noise(tm_ctx *c, double *out, uint64_t seed, long r, int dilution, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(out != nullptr, "null pointer");
+        TM_REQUIRE(r >= 0, "noise index must be >= 0");
+        TM_REQUIRE(dilution == TM_DIL_NONE || dilution == TM_DIL_SPIN_COLOUR, "bad dilution");
+        const int nrhs = dilution ? 12 : 1;
+        const size_t hb = half_bytes(c, TM_F64, nrhs);
+        void *ee = ws_get(c, "n_e", hb), *eo = ws_get(c, "n_o", hb);
+        launch_noise(c, ee, eo, seed, r, dilution, hs(stream));
+        launch_unpack(c, out, ee, eo, nrhs, TM_F64, hs(stream));
+        return TM_OK;
+    });
+}
+
+extern "C" int tm_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noise, tm_loop_stats *stats,
+                        tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(c->have_gauge, "no gauge field set");
+        int st = run_loops(c, p, loops, per_noise, stats, hs(stream));
+        TM_HIP(hipStreamSynchronize(hs(stream)));
+        if (st == TM_ERR_NOCONV) c->err = "a high-precision solve missed its tolerance";
+        return st;
+    });
+}
+
+extern "C" int tm_contract(tm_ctx *c, const double *eta, const double *s_, int nrhs, int estimators, int mu_sign,
+                           double *out, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(s_ && out, "null pointer");
+        TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        TM_REQUIRE(estimators > 0 && (estimators & ~(TM_EST_STD | TM_EST_ONE_END)) == 0,
+                   "tm_contract accepts TM_EST_STD and TM_EST_ONE_END");
+        TM_REQUIRE(!(estimators & TM_EST_STD) || eta, "STD needs eta");
+        TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
+        hipStream_t s = hs(stream);
+        const size_t hb = half_bytes(c, TM_F64, nrhs);
+        void *se = ws_get(c, "c_se", hb), *so = ws_get(c, "c_so", hb);
+        launch_pack(c, se, so, s_, nrhs, TM_F64, nullptr, s);
+        void *ee = nullptr, *eo = nullptr;
+        if (estimators & TM_EST_STD) {
+            ee = ws_get(c, "c_ee", hb);
+            eo = ws_get(c, "c_eo", hb);
+            launch_pack(c, ee, eo, eta, nrhs, TM_F64, nullptr, s);
+        }
+        const int Lt = c->geo.L[3];
+        const size_t per = (size_t)16 * Lt;
+        std::vector<cx<double>> C;
+        int k = 0;
+        if (estimators & TM_EST_STD) {
+            outer_slices_host(c, se, so, ee, eo, nrhs, C, s);
+            loops_from_outer(c, C, false, cx<double>{1, 0}, (cx<double> *)out + per * k++);
+        }
+        if (estimators & TM_EST_ONE_END) {
+            outer_slices_host(c, se, so, se, so, nrhs, C, s);
+            loops_from_outer(c, C, true, cx<double>{0, 2.0 * eps_of(c, mu_sign)}, (cx<double> *)out + per * k++);
+        }
+        return TM_OK;
+    });
+}

@@ -1,0 +1,408 @@
+// Vector kernels of the solvers: spin-diagonal scaling, precision conversion,
+// axpy forms and per-right-hand-side norms.  Reductions are deterministic:
+// each block writes one FP64 partial per right-hand side (fixed grid, fixed
+// wave-then-LDS tree) and a single block per right-hand side sums the
+// partials in a fixed order.  Products are formed in the arithmetic precision
+// and accumulated in FP64.
+#include "tm_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxPart = 1024;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// sum over the block; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double red[kBlock / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; k++) s += red[k];
+    }
+    __syncthreads();
+    return s;
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_spin_diag(S *out, const S *in, int vh, cx<float> fu,
+                                                      cx<float> fl, cx<double> du, cx<double> dl)
+{
+    using T = typename StoreTraits<S>::real;
+    const size_t n = (size_t)12 * vh;
+    const size_t base = (size_t)blockIdx.y * n;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        const int k = (int)(e / vh);
+        cx<T> f;
+        if (sizeof(T) == 8) {
+            cx<double> d = k < 6 ? du : dl;
+            f = {(T)d.r, (T)d.i};
+        } else {
+            cx<float> d = k < 6 ? fu : fl;
+            f = {(T)d.r, (T)d.i};
+        }
+        stT<T>(out, base + e, f * ldT<T>(in, base + e));
+    }
+}
+
+template <typename SO, typename SI>
+__global__ __launch_bounds__(kBlock) void k_convert(SO *out, const SI *in, size_t n, const double *scale)
+{
+    const size_t base = (size_t)blockIdx.y * n;
+    const double sc = scale ? scale[blockIdx.y] : 1.0;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        cx<double> v = ldT<double>(in, base + e);
+        stT<double>(out, base + e, sc * v);
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_axpby(S *y, const S *x, size_t n, double a, double b)
+{
+    using T = typename StoreTraits<S>::real;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        cx<T> xv = ldT<T>(x, e), yv = ldT<T>(y, e);
+        stT<T>(y, e, (T)a * xv + (T)b * yv);
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_zero(S *y, size_t n)
+{
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock)
+        stT<double>(y, e, cx<double>{0.0, 0.0});
+}
+
+// y[r] += a[r] * x[r] with per-rhs device scalars (x may be a lower precision)
+template <typename SY, typename SX>
+__global__ __launch_bounds__(kBlock) void k_axpy_dev(SY *y, const SX *x, size_t n, const double *a)
+{
+    using T = typename StoreTraits<SY>::real;
+    const size_t base = (size_t)blockIdx.y * n;
+    const T av = (T)a[blockIdx.y];
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        const size_t k = base + e;
+        stT<T>(y, k, ldT<T>(y, k) + av * ldT<T>(x, k));
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_partial_norm2(const S *v, size_t n, double *part, int nblk)
+{
+    using T = typename StoreTraits<S>::real;
+    const size_t base = (size_t)blockIdx.y * n;
+    double acc = 0;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        cx<T> a = ldT<T>(v, base + e);
+        acc += (double)(a.r * a.r + a.i * a.i);
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * nblk + blockIdx.x] = s;
+}
+
+// out[r] = sum_b part[(r * nslot + slot) * nblk + b] for the given slot
+__device__ double sum_partials(const double *part, int nblk, int idx)
+{
+    double acc = 0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += part[(size_t)idx * nblk + b];
+    return block_sum(acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_sum(const double *part, int nblk, double *out)
+{
+    double s = sum_partials(part, nblk, blockIdx.x);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0; }
+
+// part layout: [rhs][nblk] (one slot)
+__global__ __launch_bounds__(kBlock) void k_finish_alpha(CGScalars *sc, const double *part, int nblk)
+{
+    const int r = blockIdx.x;
+    double qq = sum_partials(part, nblk, r);
+    if (threadIdx.x == 0) {
+        CGScalars &s = sc[r];
+        s.qq = qq;
+        if (!finite(qq) || !finite(s.rr)) s.bad = 1;
+        s.alpha = (s.active && qq > 0 && finite(qq)) ? s.rr / qq : 0.0;
+    }
+}
+
+// part layout: [slot 0: |r|^2 for all rhs][slot 1: |rho|^2 for all rhs]
+__global__ __launch_bounds__(kBlock) void k_finish_beta(CGScalars *sc, const double *part, int nblk,
+                                                        int nrhs, double delta)
+{
+    const int r = blockIdx.x;
+    double rr = sum_partials(part, nblk, r);
+    double rho2 = sum_partials(part, nblk, nrhs + r);
+    if (threadIdx.x == 0) {
+        CGScalars &s = sc[r];
+        if (!finite(rr) || !finite(rho2)) s.bad = 1;
+        if (s.active) {
+            s.beta = (s.rr > 0) ? rr / s.rr : 0.0;
+            s.rr = rr;
+            s.rho2 = rho2;
+            s.iters += 1;
+            if (delta > 0) {
+                // reliable-update solver: converged estimate or residual fallen
+                // by delta since the last update -> request an update
+                if (rho2 <= s.target2 || rho2 < delta * delta * s.rho2_ref) s.want_update = 1;
+            } else if (rho2 <= s.target2) {
+                s.active = 0;
+            }
+        } else {
+            s.beta = 0.0;
+        }
+    }
+}
+
+// x += alpha p (x in XS), rho -= alpha q, partial |rho|^2
+template <typename S, typename XS>
+__global__ __launch_bounds__(kBlock) void k_update_xrho(XS *x, S *rho, const S *p, const S *q, size_t n,
+                                                        const CGScalars *sc, double xs, double *part,
+                                                        int nblk)
+{
+    using T = typename StoreTraits<S>::real;
+    using TX = typename StoreTraits<XS>::real;
+    const int r = blockIdx.y;
+    const double alpha = sc[r].alpha;
+    const T a = (T)alpha;
+    const TX ax = (TX)(alpha * xs);
+    const size_t base = (size_t)r * n;
+    double acc = 0;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        const size_t k = base + e;
+        cx<T> pv = ldT<T>(p, k), qv = ldT<T>(q, k), rv = ldT<T>(rho, k);
+        cx<TX> xv = ldT<TX>(x, k);
+        xv = xv + ax * cx<TX>{(TX)pv.r, (TX)pv.i};
+        rv = rv - a * qv;
+        stT<TX>(x, k, xv);
+        stT<T>(rho, k, rv);
+        // the stored (rounded) value is what later iterations see
+        cx<T> rs = ldT<T>(rho, k);
+        acc += (double)(rs.r * rs.r + rs.i * rs.i);
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) part[(size_t)r * nblk + blockIdx.x] = s;
+}
+
+// r -= alpha s, partial |r|^2 into slot 0 ([rhs][nblk])
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_update_r(S *rv, const S *sv, size_t n, const CGScalars *sc,
+                                                     double *part, int nblk)
+{
+    using T = typename StoreTraits<S>::real;
+    const int r = blockIdx.y;
+    const T a = (T)sc[r].alpha;
+    const size_t base = (size_t)r * n;
+    double acc = 0;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        const size_t k = base + e;
+        cx<T> v = ldT<T>(rv, k) - a * ldT<T>(sv, k);
+        stT<T>(rv, k, v);
+        cx<T> vs = ldT<T>(rv, k);
+        acc += (double)(vs.r * vs.r + vs.i * vs.i);
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) part[(size_t)r * nblk + blockIdx.x] = s;
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_update_p(S *p, const S *rv, size_t n, const CGScalars *sc)
+{
+    using T = typename StoreTraits<S>::real;
+    const int r = blockIdx.y;
+    if (!sc[r].active) return;
+    const T b = (T)sc[r].beta;
+    const size_t base = (size_t)r * n;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        const size_t k = base + e;
+        stT<T>(p, k, ldT<T>(rv, k) + b * ldT<T>(p, k));
+    }
+}
+
+size_t half_elems(tm_ctx *c) { return (size_t)12 * c->geo.vh; }
+
+int grid_for(size_t n)
+{
+    size_t g = (n + kBlock * 4 - 1) / (kBlock * 4);
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+template <typename F>
+void dispatch_prec(int prec, F &&f)
+{
+    switch (prec) {
+    case TM_F64: f((double2 *)nullptr); break;
+    case TM_F32: f((float2 *)nullptr); break;
+    case TM_F16: f((h2 *)nullptr); break;
+    case TM_BF16: f((b2 *)nullptr); break;
+    default: throw TmError{TM_ERR_ARG, "bad precision"};
+    }
+}
+
+}  // namespace
+
+int reduce_blocks(tm_ctx *c)
+{
+    size_t n = half_elems(c);
+    size_t g = (n + kBlock * 8 - 1) / (kBlock * 8);
+    if (g < 1) g = 1;
+    if (g > kMaxPart) g = kMaxPart;
+    return (int)g;
+}
+
+void launch_spin_diag(tm_ctx *c, void *out, const void *in, int prec, int nrhs, SpinDiag d, hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dim3 grid(grid_for(n), nrhs);
+    cx<float> fu{(float)d.u.r, (float)d.u.i}, fl{(float)d.l.r, (float)d.l.i};
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_spin_diag<S>, grid, dim3(kBlock), 0, s, (S *)out, (const S *)in, c->geo.vh, fu,
+                           fl, d.u, d.l);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_copy_convert(tm_ctx *c, void *out, int out_prec, const void *in, int in_prec, int nrhs,
+                         const double *dscale, hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dim3 grid(grid_for(n), nrhs);
+    dispatch_prec(out_prec, [&](auto *to) {
+        using SO = std::remove_pointer_t<decltype(to)>;
+        dispatch_prec(in_prec, [&](auto *ti) {
+            using SI = std::remove_pointer_t<decltype(ti)>;
+            hipLaunchKernelGGL((k_convert<SO, SI>), grid, dim3(kBlock), 0, s, (SO *)out, (const SI *)in, n,
+                               dscale);
+        });
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_axpby_host(tm_ctx *c, void *y, const void *x, int prec, int nrhs, double a, double b,
+                       hipStream_t s)
+{
+    size_t n = half_elems(c) * nrhs;
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_axpby<S>, dim3(grid_for(n)), dim3(kBlock), 0, s, (S *)y, (const S *)x, n, a, b);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *part, int nblk, hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_partial_norm2<S>, dim3(nblk, nrhs), dim3(kBlock), 0, s, (const S *)v, n, part,
+                           nblk);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *dev_out, hipStream_t s)
+{
+    int nblk = reduce_blocks(c);
+    double *part = (double *)ws_get(c, "norm_part", sizeof(double) * nblk * nrhs);
+    partial_norm2(c, v, prec, nrhs, part, nblk, s);
+    hipLaunchKernelGGL(k_finish_sum, dim3(nrhs), dim3(kBlock), 0, s, (const double *)part, nblk, dev_out);
+    TM_HIP(hipGetLastError());
+}
+
+void cg_finish_alpha(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish_alpha, dim3(nrhs), dim3(kBlock), 0, s, sc, part, nblk);
+    TM_HIP(hipGetLastError());
+}
+
+void cg_finish_beta(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int nrhs, double delta,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish_beta, dim3(nrhs), dim3(kBlock), 0, s, sc, part, nblk, nrhs, delta);
+    TM_HIP(hipGetLastError());
+}
+
+void cg_update_xrho(tm_ctx *c, void *x, int xprec, void *rho, const void *p, const void *q, int prec,
+                    int nrhs, const CGScalars *sc, double *part, int nblk, double xs, hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dim3 grid(nblk, nrhs);
+    if (prec == TM_F64) {
+        TM_REQUIRE(xprec == TM_F64, "FP64 CG needs an FP64 solution vector");
+        hipLaunchKernelGGL((k_update_xrho<double2, double2>), grid, dim3(kBlock), 0, s, (double2 *)x,
+                           (double2 *)rho, (const double2 *)p, (const double2 *)q, n, sc, xs, part, nblk);
+    } else {
+        TM_REQUIRE(xprec == TM_F32, "low-precision CG accumulates in FP32");
+        dispatch_prec(prec, [&](auto *tag) {
+            using S = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((k_update_xrho<S, float2>), grid, dim3(kBlock), 0, s, (float2 *)x, (S *)rho,
+                               (const S *)p, (const S *)q, n, sc, xs, part, nblk);
+        });
+    }
+    TM_HIP(hipGetLastError());
+}
+
+void cg_update_r(tm_ctx *c, void *r, const void *sv, int prec, int nrhs, const CGScalars *sc, double *part,
+                 int nblk, hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_update_r<S>, dim3(nblk, nrhs), dim3(kBlock), 0, s, (S *)r, (const S *)sv, n, sc,
+                           part, nblk);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void cg_update_p(tm_ctx *c, void *p, const void *r, int prec, int nrhs, const CGScalars *sc, hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_update_p<S>, dim3(grid_for(n), nrhs), dim3(kBlock), 0, s, (S *)p, (const S *)r,
+                           n, sc);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_zero(tm_ctx *c, void *y, int prec, int nrhs, hipStream_t s)
+{
+    size_t n = half_elems(c) * nrhs;
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_zero<S>, dim3(grid_for(n)), dim3(kBlock), 0, s, (S *)y, n);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_axpy_dev(tm_ctx *c, void *y, int yprec, const void *x, int xprec, int nrhs, const double *a_dev,
+                     hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dim3 grid(grid_for(n), nrhs);
+    dispatch_prec(yprec, [&](auto *ty) {
+        using SY = std::remove_pointer_t<decltype(ty)>;
+        dispatch_prec(xprec, [&](auto *tx) {
+            using SX = std::remove_pointer_t<decltype(tx)>;
+            hipLaunchKernelGGL((k_axpy_dev<SY, SX>), grid, dim3(kBlock), 0, s, (SY *)y, (const SX *)x, n, a_dev);
+        });
+    });
+    TM_HIP(hipGetLastError());
+}

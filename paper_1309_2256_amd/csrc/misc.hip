@@ -1,0 +1,285 @@
+// Layout conversion, gauge ingest, Z4 noise and the loop contraction kernel.
+#include "tm_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ long lex_site(const Geo &g, int x, int y, int z, int t)
+{
+    return x + (long)g.L[0] * (y + (long)g.L[1] * (z + (long)g.L[2] * t));
+}
+
+// ---------------------------------------------------------------- pack / unpack
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_pack(S *even, S *odd, const double2 *full, Geo g, long V,
+                                                 const double *scale)
+{
+    const long s = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= V) return;
+    const int r = blockIdx.y;
+    int q = (int)(s / g.L[0]);
+    int x = (int)(s - (long)q * g.L[0]);
+    int y = q % g.L[1];
+    int q2 = q / g.L[1];
+    int z = q2 % g.L[2];
+    int t = q2 / g.L[2];
+    const int p = (x + y + z + t) & 1;
+    const int i = (int)(s >> 1);
+    S *dst = p ? odd : even;
+    const double sc = scale ? scale[r] : 1.0;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        double2 v = full[((size_t)r * V + s) * 12 + k];
+        stT<double>(dst, (size_t)(r * 12 + k) * g.vh + i, cx<double>{sc * v.x, sc * v.y});
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_unpack(double2 *full, const S *even, const S *odd, Geo g, long V)
+{
+    const long s = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= V) return;
+    const int r = blockIdx.y;
+    int q = (int)(s / g.L[0]);
+    int x = (int)(s - (long)q * g.L[0]);
+    int y = q % g.L[1];
+    int q2 = q / g.L[1];
+    int z = q2 % g.L[2];
+    int t = q2 / g.L[2];
+    const int p = (x + y + z + t) & 1;
+    const int i = (int)(s >> 1);
+    const S *src = p ? odd : even;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        cx<double> v = ldT<double>(src, (size_t)(r * 12 + k) * g.vh + i);
+        full[((size_t)r * V + s) * 12 + k] = make_double2(v.r, v.i);
+    }
+}
+
+// ---------------------------------------------------------------- gauge
+
+// links[p][d][k][i]: d < 4 forward U_d(x), d >= 4 backward U_{d-4}(x - e)^dag,
+// times the time-boundary phase on hops that cross t = Lt-1 <-> 0
+__global__ __launch_bounds__(kBlock) void k_gauge_ingest(double2 *l0, double2 *l1, const double2 *U, Geo g,
+                                                         long V, int t_bc)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.vh) return;
+    const int p = blockIdx.y;
+    double2 *dst = p ? l1 : l0;
+    int x, y, z, t;
+    eo_coords(g, p, i, x, y, z, t);
+    const long s = lex_site(g, x, y, z, t);
+    for (int mu = 0; mu < 4; mu++) {
+        double ph = (mu == 3 && t == g.L[3] - 1) ? (double)t_bc : 1.0;
+        for (int k = 0; k < 9; k++) {
+            double2 u = U[((size_t)mu * V + s) * 9 + k];
+            dst[(size_t)(mu * 9 + k) * g.vh + i] = make_double2(ph * u.x, ph * u.y);
+        }
+        int c[4] = {x, y, z, t};
+        c[mu] = (c[mu] == 0) ? g.L[mu] - 1 : c[mu] - 1;
+        const long sb = lex_site(g, c[0], c[1], c[2], c[3]);
+        double phb = (mu == 3 && t == 0) ? (double)t_bc : 1.0;
+        for (int row = 0; row < 3; row++)
+            for (int col = 0; col < 3; col++) {
+                // (U^dag)[row][col] = conj(U[col][row])
+                double2 u = U[((size_t)mu * V + sb) * 9 + 3 * col + row];
+                dst[(size_t)((4 + mu) * 9 + 3 * row + col) * g.vh + i] = make_double2(phb * u.x, -phb * u.y);
+            }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_d2f(float2 *out, const double2 *in, size_t n)
+{
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        double2 v = in[e];
+        out[e] = make_float2((float)v.x, (float)v.y);  // round to nearest even
+    }
+}
+
+// ---------------------------------------------------------------- noise
+
+// SplitMix64 (Steele, Lea & Flood 2014): output c of the stream seeded with
+// `seed` is the finaliser applied to seed + (c + 1) * golden-gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1) * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+// Z4 noise number r: entry (site s, spin a, colour c) is i^k, k = top two bits
+// of output ((r*V + s)*4 + a)*3 + c.  dilution = 1 writes 12 right-hand sides,
+// source d = 3a + c holding only that component.
+__global__ __launch_bounds__(kBlock) void k_noise(double2 *even, double2 *odd, Geo g, long V, uint64_t seed,
+                                                  long r, int dilution)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.vh) return;
+    const int p = blockIdx.y;
+    double2 *dst = p ? odd : even;
+    int x, y, z, t;
+    eo_coords(g, p, i, x, y, z, t);
+    const long s = lex_site(g, x, y, z, t);
+    double2 eta[12];
+    for (int k = 0; k < 12; k++) {
+        uint64_t cnt = (uint64_t)((r * V + s) * 12 + k);
+        unsigned q = (unsigned)(splitmix64_at(seed, cnt) >> 62);
+        // i^q
+        eta[k] = q == 0 ? make_double2(1, 0) : q == 1 ? make_double2(0, 1) : q == 2 ? make_double2(-1, 0)
+                                                                                   : make_double2(0, -1);
+    }
+    if (!dilution) {
+        for (int k = 0; k < 12; k++) dst[(size_t)k * g.vh + i] = eta[k];
+    } else {
+        for (int d = 0; d < 12; d++)
+            for (int k = 0; k < 12; k++)
+                dst[(size_t)(d * 12 + k) * g.vh + i] = (k == d) ? eta[k] : make_double2(0, 0);
+    }
+}
+
+// ---------------------------------------------------------------- contraction
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Per time slice and block: C[b][a] = sum_{x, rhs, colour} v_{b c}(x) conj(w_{a c}(x)),
+// both parities, FP64; partial[t][blk][32].
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_outer(const S *ve, const S *vo, const S *we, const S *wo, Geo g,
+                                                  int nrhs, double *part)
+{
+    const int t = blockIdx.y;
+    const int il = blockIdx.x * kBlock + threadIdx.x;
+    cx<double> C[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) C[k] = {0, 0};
+    if (il < g.vsh) {
+        const int i = t * g.vsh + il;
+        for (int p = 0; p < 2; p++) {
+            const S *v = p ? vo : ve;
+            const S *w = p ? wo : we;
+            for (int r = 0; r < nrhs; r++) {
+                cx<double> a[12], b[12];
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    a[k] = ldT<double>(v, (size_t)(r * 12 + k) * g.vh + i);
+                    b[k] = ldT<double>(w, (size_t)(r * 12 + k) * g.vh + i);
+                }
+#pragma unroll
+                for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+                    for (int sa = 0; sa < 4; sa++)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) cmac_conj(C[sb * 4 + sa], b[sa * 3 + c], a[sb * 3 + c]);
+            }
+        }
+    }
+    __shared__ double red[kBlock / 64][32];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        double re = wave_sum(C[k].r), im = wave_sum(C[k].i);
+        if (lane == 0) {
+            red[wv][2 * k] = re;
+            red[wv][2 * k + 1] = im;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double s = 0;
+        for (int k = 0; k < kBlock / 64; k++) s += red[k][threadIdx.x];
+        part[((size_t)t * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_outer_finish(const double *part, int nblk, double *out)
+{
+    const int t = blockIdx.x;
+    const int j = threadIdx.x;  // 32 values
+    double s = 0;
+    for (int b = 0; b < nblk; b++) s += part[((size_t)t * nblk + b) * 32 + j];
+    out[(size_t)t * 32 + j] = s;
+}
+
+template <typename F>
+void dispatch_prec(int prec, F &&f)
+{
+    switch (prec) {
+    case TM_F64: f((double2 *)nullptr); break;
+    case TM_F32: f((float2 *)nullptr); break;
+    case TM_F16: f((h2 *)nullptr); break;
+    case TM_BF16: f((b2 *)nullptr); break;
+    default: throw TmError{TM_ERR_ARG, "bad precision"};
+    }
+}
+
+}  // namespace
+
+void launch_pack(tm_ctx *c, void *even, void *odd, const double *full, int nrhs, int prec,
+                 const double *dscale, hipStream_t s)
+{
+    dim3 grid((unsigned)((c->V + kBlock - 1) / kBlock), nrhs);
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_pack<S>, grid, dim3(kBlock), 0, s, (S *)even, (S *)odd, (const double2 *)full,
+                           c->geo, c->V, dscale);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_unpack(tm_ctx *c, double *full, const void *even, const void *odd, int nrhs, int prec,
+                   hipStream_t s)
+{
+    dim3 grid((unsigned)((c->V + kBlock - 1) / kBlock), nrhs);
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_unpack<S>, grid, dim3(kBlock), 0, s, (double2 *)full, (const S *)even,
+                           (const S *)odd, c->geo, c->V);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_gauge_ingest(tm_ctx *c, const double *U, hipStream_t s)
+{
+    dim3 grid((c->geo.vh + kBlock - 1) / kBlock, 2);
+    hipLaunchKernelGGL(k_gauge_ingest, grid, dim3(kBlock), 0, s, (double2 *)c->links64[0],
+                       (double2 *)c->links64[1], (const double2 *)U, c->geo, c->V, c->t_bc);
+    TM_HIP(hipGetLastError());
+}
+
+void launch_links_to_f32(tm_ctx *c, hipStream_t s)
+{
+    size_t n = (size_t)72 * c->geo.vh;
+    for (int p = 0; p < 2; p++)
+        hipLaunchKernelGGL(k_d2f, dim3(2048), dim3(kBlock), 0, s, (float2 *)c->links32[p],
+                           (const double2 *)c->links64[p], n);
+    TM_HIP(hipGetLastError());
+}
+
+void launch_noise(tm_ctx *c, void *even, void *odd, uint64_t seed, long r, int dilution, hipStream_t s)
+{
+    dim3 grid((c->geo.vh + kBlock - 1) / kBlock, 2);
+    hipLaunchKernelGGL(k_noise, grid, dim3(kBlock), 0, s, (double2 *)even, (double2 *)odd, c->geo, c->V, seed,
+                       r, dilution);
+    TM_HIP(hipGetLastError());
+}
+
+void launch_outer_slices(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
+                         double *dev_out, hipStream_t s)
+{
+    const int nblk = (c->geo.vsh + kBlock - 1) / kBlock;
+    const int Lt = c->geo.L[3];
+    double *part = (double *)ws_get(c, "outer_part", sizeof(double) * 32 * nblk * Lt);
+    hipLaunchKernelGGL(k_outer<double2>, dim3(nblk, Lt), dim3(kBlock), 0, s, (const double2 *)ve,
+                       (const double2 *)vo, (const double2 *)we, (const double2 *)wo, c->geo, nrhs, part);
+    hipLaunchKernelGGL(k_outer_finish, dim3(Lt), dim3(32), 0, s, (const double *)part, nblk, dev_out);
+    TM_HIP(hipGetLastError());
+}

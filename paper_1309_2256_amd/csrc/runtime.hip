@@ -1,0 +1,553 @@
+// Host runtime: operators on half-lattice fields, CG solvers on the even-odd
+// normal equations (plain FP64, mixed precision with reliable updates, and the
+// truncated low-precision solve of the Truncated Solver Method), and the
+// disconnected-loop driver.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+void upload(void *dev, const void *host, size_t bytes, hipStream_t s)
+{
+    TM_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s));
+    TM_HIP(hipStreamSynchronize(s));
+}
+
+void download(tm_ctx *c, void *host, const void *dev, size_t bytes, hipStream_t s)
+{
+    void *stage = host_stage(c, bytes);
+    TM_HIP(hipMemcpyAsync(stage, dev, bytes, hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    memcpy(host, stage, bytes);
+}
+
+std::vector<double> norms_host(tm_ctx *c, const void *v, int prec, int nrhs, hipStream_t s)
+{
+    double *d = (double *)ws_get(c, "norms_out", sizeof(double) * nrhs);
+    launch_norm2(c, v, prec, nrhs, d, s);
+    std::vector<double> h(nrhs);
+    download(c, h.data(), d, sizeof(double) * nrhs, s);
+    return h;
+}
+
+size_t field_bytes(tm_ctx *c, int prec, int nrhs) { return prec_bytes(prec) * 12 * (size_t)c->geo.vh * nrhs; }
+
+void copy_field(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    TM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+}
+
+// chiral-basis Dirac matrices gamma_1..gamma_4 (x, y, z, t)
+const cx<double> kGamma[4][4][4] = {
+    {{{0, 0}, {0, 0}, {0, 0}, {0, -1}}, {{0, 0}, {0, 0}, {0, -1}, {0, 0}},
+     {{0, 0}, {0, 1}, {0, 0}, {0, 0}}, {{0, 1}, {0, 0}, {0, 0}, {0, 0}}},
+    {{{0, 0}, {0, 0}, {0, 0}, {-1, 0}}, {{0, 0}, {0, 0}, {1, 0}, {0, 0}},
+     {{0, 0}, {1, 0}, {0, 0}, {0, 0}}, {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},
+    {{{0, 0}, {0, 0}, {0, -1}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}, {0, 1}},
+     {{0, 1}, {0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {0, -1}, {0, 0}, {0, 0}}},
+    {{{0, 0}, {0, 0}, {1, 0}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}, {1, 0}},
+     {{1, 0}, {0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {1, 0}, {0, 0}, {0, 0}}},
+};
+
+// Gamma_n = gamma_1^n0 gamma_2^n1 gamma_3^n2 gamma_4^n3
+void gamma_n(int n, cx<double> G[4][4])
+{
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) G[a][b] = {a == b ? 1.0 : 0.0, 0.0};
+    for (int mu = 0; mu < 4; mu++) {
+        if (!((n >> mu) & 1)) continue;
+        cx<double> T[4][4];
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                cx<double> acc{0, 0};
+                for (int k = 0; k < 4; k++) acc = acc + G[a][k] * kGamma[mu][k][b];
+                T[a][b] = acc;
+            }
+        memcpy(G, T, sizeof(T));
+    }
+}
+
+}  // namespace
+
+double eps_of(tm_ctx *c, int mu_sign) { return mu_sign >= 0 ? c->eps : -c->eps; }
+
+void op_dslash(tm_ctx *c, void *out, const void *in, const void *own, int nrhs, int prec, int out_par, int dag,
+               SpinDiag dhop, SpinDiag down, hipStream_t s)
+{
+    DslashCall dc{};
+    dc.out = out;
+    dc.in = in;
+    dc.own = own;
+    dc.nrhs = nrhs;
+    dc.out_parity = out_par;
+    dc.dag = dag;
+    dc.spinor_prec = prec;
+    dc.d_own = down;
+    dc.d_hop = dhop;
+    dc.d_in = sd_scalar(1.0);
+    dc.has_own = own != nullptr;
+    dc.has_in = false;
+    launch_dslash(c, dc, s);
+}
+
+// Ahat x = R x - H_eo R^-1 H_oe x, with H = -kappa Hop
+void op_schur(tm_ctx *c, void *out, const void *in, void *tmp, int nrhs, int prec, double epsp, hipStream_t s)
+{
+    const double k = c->kappa;
+    op_dslash(c, tmp, in, nullptr, nrhs, prec, 1, 0, sd_mul(sd_scalar(-k), sd_twist_inv(epsp)), sd_scalar(0), s);
+    op_dslash(c, out, tmp, in, nrhs, prec, 0, 0, sd_scalar(k), sd_twist(epsp), s);
+}
+
+// Ahat^dag x = gamma5 Ahat(-eps) gamma5 x
+//            = R(-eps) x - gamma5 H_eo t,  t = R^-1(-eps) H_oe gamma5 x = R^-1(-eps) gamma5 H^dag_oe x
+void op_schur_dag(tm_ctx *c, void *out, const void *in, void *tmp, int nrhs, int prec, double epsp,
+                  hipStream_t s)
+{
+    const double k = c->kappa;
+    op_dslash(c, tmp, in, nullptr, nrhs, prec, 1, 1,
+              sd_mul(sd_scalar(-k), sd_mul(sd_twist_inv(-epsp), sd_gamma5())), sd_scalar(0), s);
+    op_dslash(c, out, tmp, in, nrhs, prec, 0, 0, sd_mul(sd_scalar(k), sd_gamma5()), sd_twist(-epsp), s);
+}
+
+void op_bh_power(tm_ctx *c, void *se, void *so, int nrhs, double epsp, int kpow, hipStream_t s)
+{
+    size_t bytes = field_bytes(c, TM_F64, nrhs);
+    void *te = ws_get(c, "bh_e", bytes), *to = ws_get(c, "bh_o", bytes);
+    SpinDiag d = sd_mul(sd_scalar(-c->kappa), sd_twist_inv(epsp));
+    for (int i = 0; i < kpow; i++) {
+        op_dslash(c, to, se, nullptr, nrhs, TM_F64, 1, 0, d, sd_scalar(0), s);
+        op_dslash(c, te, so, nullptr, nrhs, TM_F64, 0, 0, d, sd_scalar(0), s);
+        copy_field(se, te, bytes, s);
+        copy_field(so, to, bytes, s);
+    }
+}
+
+// ---------------------------------------------------------------- CG
+
+namespace {
+
+struct CGWork {
+    int nrhs, prec, nblk;
+    void *q, *sv, *p, *r, *rho, *tmp;
+    void *x;  // solution accumulator: FP64 (plain) or FP32 (low precision)
+    int xprec;
+    CGScalars *dsc;
+    double *partq, *partb;
+};
+
+// Run CG iterations until every right-hand side is inactive, maxiter is
+// reached, or (reliable-update mode) some right-hand side asks for an update.
+// Returns the iteration count of this call.
+int cg_iterate(tm_ctx *c, CGWork &w, double epsp, double delta, int maxiter, int check_every,
+               std::vector<CGScalars> &hsc, hipStream_t s, bool &stop_update)
+{
+    int it = 0;
+    stop_update = false;
+    while (it < maxiter) {
+        op_schur(c, w.q, w.p, w.tmp, w.nrhs, w.prec, epsp, s);
+        partial_norm2(c, w.q, w.prec, w.nrhs, w.partq, w.nblk, s);
+        cg_finish_alpha(c, w.dsc, w.partq, w.nblk, w.nrhs, s);
+        cg_update_xrho(c, w.x, w.xprec, w.rho, w.p, w.q, w.prec, w.nrhs, w.dsc, w.partb + (size_t)w.nrhs * w.nblk,
+                       w.nblk, 1.0, s);
+        op_schur_dag(c, w.sv, w.q, w.tmp, w.nrhs, w.prec, epsp, s);
+        cg_update_r(c, w.r, w.sv, w.prec, w.nrhs, w.dsc, w.partb, w.nblk, s);
+        cg_finish_beta(c, w.dsc, w.partb, w.nblk, w.nrhs, delta, s);
+        cg_update_p(c, w.p, w.r, w.prec, w.nrhs, w.dsc, s);
+        it++;
+        if (it % check_every == 0 || it == maxiter) {
+            download(c, hsc.data(), w.dsc, sizeof(CGScalars) * w.nrhs, s);
+            bool any_active = false, any_update = false, any_bad = false;
+            for (auto &q : hsc) {
+                any_active |= q.active != 0;
+                any_update |= (q.active && q.want_update);
+                any_bad |= q.bad != 0;
+            }
+            if (any_bad) throw TmError{TM_ERR_NAN, "NaN/Inf in a solver reduction"};
+            if (!any_active) break;
+            if (any_update) {
+                stop_update = true;
+                break;
+            }
+        }
+    }
+    return it;
+}
+
+}  // namespace
+
+SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,
+                      const tm_solve_params &p, hipStream_t s)
+{
+    const double t0 = now_s();
+    TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    TM_REQUIRE(p.tol > 0 && std::isfinite(p.tol), "tol must be > 0");
+    TM_REQUIRE(p.maxiter > 0, "maxiter must be > 0");
+    TM_REQUIRE(p.solver >= TM_CG_F64 && p.solver <= TM_CG_LOW, "unknown solver");
+    TM_REQUIRE(p.mu_sign == 1 || p.mu_sign == -1, "mu_sign must be +1 or -1");
+    const int low_prec = p.solver == TM_CG_F64 ? TM_F64 : p.inner_prec;
+    TM_REQUIRE(low_prec == TM_F64 || low_prec == TM_F32 || low_prec == TM_F16 || low_prec == TM_BF16,
+               "bad inner precision");
+    TM_REQUIRE(p.solver == TM_CG_F64 || low_prec != TM_F64, "MIXED/LOW need a FP32/FP16/BF16 inner precision");
+    const int check_every = p.check_every > 0 ? p.check_every : 8;
+    const double delta = p.solver == TM_CG_MIXED ? (p.delta > 0 ? p.delta : 0.1) : 0.0;
+    const double epsp = eps_of(c, p.mu_sign);
+    const double kap = c->kappa;
+    const int nblk = reduce_blocks(c);
+    const size_t f64 = field_bytes(c, TM_F64, nrhs);
+
+    void *bh = ws_get(c, "s_bh", f64);
+    void *t64 = ws_get(c, "s_t64", f64);
+    void *rho64 = ws_get(c, "s_rho64", f64);
+    void *r64 = ws_get(c, "s_r64", f64);
+    void *q64 = ws_get(c, "s_q64", f64);
+
+    // |b|^2 over the full lattice
+    std::vector<double> bn2 = norms_host(c, be, TM_F64, nrhs, s);
+    {
+        std::vector<double> bo2 = norms_host(c, bo, TM_F64, nrhs, s);
+        for (int r = 0; r < nrhs; r++) bn2[r] += bo2[r];
+    }
+    for (int r = 0; r < nrhs; r++)
+        if (!std::isfinite(bn2[r])) throw TmError{TM_ERR_NAN, "NaN/Inf in the source"};
+
+    // bhat_e = b_e - H_eo R_oo^-1 b_o
+    launch_spin_diag(c, t64, bo, TM_F64, nrhs, sd_twist_inv(epsp), s);
+    op_dslash(c, bh, t64, be, nrhs, TM_F64, 0, 0, sd_scalar(kap), sd_scalar(1.0), s);
+
+    SolveOut out;
+    out.st.assign(nrhs, tm_solve_stats{});
+    std::vector<CGScalars> hsc(nrhs);
+    std::vector<int> n_rel(nrhs, 0);
+    std::vector<double> iter_res(nrhs, 0.0);
+    CGScalars *dsc = (CGScalars *)ws_get(c, "s_sc", sizeof(CGScalars) * nrhs);
+    double *partq = (double *)ws_get(c, "s_partq", sizeof(double) * nblk * nrhs);
+    double *partb = (double *)ws_get(c, "s_partb", sizeof(double) * nblk * nrhs * 2);
+
+    if (p.solver == TM_CG_F64) {
+        CGWork w{nrhs, TM_F64, nblk};
+        w.x = xe;
+        w.xprec = TM_F64;
+        w.rho = rho64;
+        w.r = r64;
+        w.q = q64;
+        w.tmp = t64;
+        w.p = ws_get(c, "s_p64", f64);
+        w.sv = ws_get(c, "s_s64", f64);
+        w.dsc = dsc;
+        w.partq = partq;
+        w.partb = partb;
+        launch_zero(c, xe, TM_F64, nrhs, s);
+        copy_field(rho64, bh, f64, s);
+        op_schur_dag(c, r64, rho64, t64, nrhs, TM_F64, epsp, s);
+        copy_field(w.p, r64, f64, s);
+        std::vector<double> rr = norms_host(c, r64, TM_F64, nrhs, s);
+        std::vector<double> rho2 = norms_host(c, rho64, TM_F64, nrhs, s);
+        for (int r = 0; r < nrhs; r++) {
+            CGScalars &q = hsc[r];
+            memset(&q, 0, sizeof(q));
+            q.rr = rr[r];
+            q.rho2 = rho2[r];
+            q.rho2_ref = rho2[r];
+            q.target2 = p.tol * p.tol * bn2[r];
+            q.sigma = 1.0;
+            q.active = rho2[r] > q.target2 ? 1 : 0;
+        }
+        upload(dsc, hsc.data(), sizeof(CGScalars) * nrhs, s);
+        bool upd;
+        cg_iterate(c, w, epsp, 0.0, p.maxiter, check_every, hsc, s, upd);
+        download(c, hsc.data(), dsc, sizeof(CGScalars) * nrhs, s);
+        for (int r = 0; r < nrhs; r++) iter_res[r] = std::sqrt(hsc[r].rho2 / bn2[r]);
+    } else {
+        // low-precision CG on vectors scaled to unit RMS per element; FP64
+        // solution, residual and (MIXED) reliable updates
+        const int lp = low_prec;
+        const size_t fl = field_bytes(c, lp, nrhs);
+        CGWork w{nrhs, lp, nblk};
+        w.x = ws_get(c, "s_y32", field_bytes(c, TM_F32, nrhs));
+        w.xprec = TM_F32;
+        w.rho = ws_get(c, "s_rho_lo", fl);
+        w.r = ws_get(c, "s_r_lo", fl);
+        w.q = ws_get(c, "s_q_lo", fl);
+        w.p = ws_get(c, "s_p_lo", fl);
+        w.sv = ws_get(c, "s_s_lo", fl);
+        w.tmp = ws_get(c, "s_t_lo", fl);
+        w.dsc = dsc;
+        w.partq = partq;
+        w.partb = partb;
+        double *dscale = (double *)ws_get(c, "s_scale", sizeof(double) * nrhs);
+        const double nel = 12.0 * c->geo.vh;
+        std::vector<double> sigma(nrhs, 1.0), hscale(nrhs);
+
+        launch_zero(c, xe, TM_F64, nrhs, s);
+        copy_field(rho64, bh, f64, s);
+        // (re)start from the FP64 residual rho64 = bhat - Ahat x: r = Ahat^dag rho
+        auto restart = [&](bool first) {
+            op_schur_dag(c, r64, rho64, t64, nrhs, TM_F64, epsp, s);
+            std::vector<double> nr = norms_host(c, r64, TM_F64, nrhs, s);
+            std::vector<double> nrho = norms_host(c, rho64, TM_F64, nrhs, s);
+            std::vector<double> sig_new(nrhs);
+            for (int r = 0; r < nrhs; r++) {
+                sig_new[r] = nr[r] > 0 ? std::sqrt(nel / nr[r]) : 1.0;
+                if (!std::isfinite(sig_new[r])) sig_new[r] = 1.0;
+            }
+            if (!first) {
+                for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r] / sigma[r];
+                upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+                launch_copy_convert(c, w.p, lp, w.p, lp, nrhs, dscale, s);
+            }
+            for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r];
+            upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+            launch_copy_convert(c, w.r, lp, r64, TM_F64, nrhs, dscale, s);
+            launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
+            if (first) copy_field(w.p, w.r, fl, s);
+            launch_zero(c, w.x, TM_F32, nrhs, s);
+            std::vector<double> rr = norms_host(c, w.r, lp, nrhs, s);
+            std::vector<double> rho2 = norms_host(c, w.rho, lp, nrhs, s);
+            if (!first) download(c, hsc.data(), dsc, sizeof(CGScalars) * nrhs, s);
+            for (int r = 0; r < nrhs; r++) {
+                CGScalars &q = hsc[r];
+                if (first) {
+                    memset(&q, 0, sizeof(q));
+                    q.active = 1;
+                }
+                q.rr = rr[r];
+                q.rho2 = rho2[r];
+                q.rho2_ref = rho2[r];
+                q.target2 = p.tol * p.tol * bn2[r] * sig_new[r] * sig_new[r];
+                q.sigma = sig_new[r];
+                q.want_update = 0;
+                // converged on the true FP64 residual
+                if (nrho[r] <= p.tol * p.tol * bn2[r]) q.active = 0;
+                iter_res[r] = std::sqrt(nrho[r] / bn2[r]);
+            }
+            sigma = sig_new;
+            upload(dsc, hsc.data(), sizeof(CGScalars) * nrhs, s);
+        };
+        // x_hi += y / sigma
+        auto accumulate = [&]() {
+            for (int r = 0; r < nrhs; r++) hscale[r] = 1.0 / sigma[r];
+            upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+            launch_axpy_dev(c, xe, TM_F64, w.x, TM_F32, nrhs, dscale, s);
+        };
+        restart(true);
+        int total = 0;
+        while (total < p.maxiter) {
+            bool upd = false;
+            int done = cg_iterate(c, w, epsp, delta, p.maxiter - total, check_every, hsc, s, upd);
+            total += done;
+            accumulate();
+            if (p.solver == TM_CG_LOW) {
+                for (int r = 0; r < nrhs; r++) iter_res[r] = std::sqrt(hsc[r].rho2 / bn2[r]) / hsc[r].sigma;
+                break;
+            }
+            // reliable update: FP64 true residual of the accumulated solution
+            op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s);
+            copy_field(rho64, bh, f64, s);
+            launch_axpby_host(c, rho64, q64, TM_F64, nrhs, -1.0, 1.0, s);
+            for (int r = 0; r < nrhs; r++)
+                if (hsc[r].active) n_rel[r]++;
+            restart(false);
+            bool any = false;
+            for (auto &q : hsc) any |= q.active != 0;
+            if (!any) break;
+        }
+    }
+
+    // odd reconstruction psi_o = R^-1 (b_o - H_oe psi_e)
+    op_dslash(c, xo, xe, bo, nrhs, TM_F64, 1, 0, sd_mul(sd_scalar(kap), sd_twist_inv(epsp)), sd_twist_inv(epsp),
+              s);
+    // true residual b - M x, both parities
+    op_dslash(c, rho64, xo, xe, nrhs, TM_F64, 0, 0, sd_scalar(-kap), sd_twist(epsp), s);
+    launch_axpby_host(c, rho64, be, TM_F64, nrhs, -1.0, 1.0, s);
+    op_dslash(c, t64, xe, xo, nrhs, TM_F64, 1, 0, sd_scalar(-kap), sd_twist(epsp), s);
+    launch_axpby_host(c, t64, bo, TM_F64, nrhs, -1.0, 1.0, s);
+    std::vector<double> re = norms_host(c, rho64, TM_F64, nrhs, s);
+    std::vector<double> ro = norms_host(c, t64, TM_F64, nrhs, s);
+    const double t1 = now_s();
+    for (int r = 0; r < nrhs; r++) {
+        tm_solve_stats &st = out.st[r];
+        st.iters = hsc[r].iters;
+        st.n_reliable = n_rel[r];
+        st.true_rel_res = bn2[r] > 0 ? std::sqrt((re[r] + ro[r]) / bn2[r]) : 0.0;
+        st.iter_rel_res = iter_res[r];
+        st.converged = st.true_rel_res <= p.tol ? 1 : 0;
+        st.seconds = t1 - t0;
+        if (!std::isfinite(st.true_rel_res)) out.status = TM_ERR_NAN;
+        if (!st.converged && p.solver != TM_CG_LOW && out.status == TM_OK) out.status = TM_ERR_NOCONV;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------- loops
+
+void outer_slices_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
+                       std::vector<cx<double>> &out, hipStream_t s)
+{
+    const int Lt = c->geo.L[3];
+    double *d = (double *)ws_get(c, "outer_out", sizeof(double) * 32 * Lt);
+    launch_outer_slices(c, ve, vo, we, wo, nrhs, d, s);
+    out.resize((size_t)16 * Lt);
+    download(c, out.data(), d, sizeof(double) * 32 * Lt, s);
+}
+
+void loops_from_outer(tm_ctx *c, const std::vector<cx<double>> &C, bool g5pre, cx<double> coef, cx<double> *out)
+{
+    const int Lt = c->geo.L[3];
+    cx<double> g5[4][4];
+    gamma_n(15, g5);
+    for (int n = 0; n < 16; n++) {
+        cx<double> G[4][4], X[4][4];
+        gamma_n(n, G);
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                if (!g5pre) {
+                    X[a][b] = G[a][b];
+                } else {
+                    cx<double> acc{0, 0};
+                    for (int k = 0; k < 4; k++) acc = acc + g5[a][k] * G[k][b];
+                    X[a][b] = acc;
+                }
+            }
+        for (int t = 0; t < Lt; t++) {
+            cx<double> acc{0, 0};
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) acc = acc + X[a][b] * C[(size_t)t * 16 + b * 4 + a];
+            out[(size_t)n * Lt + t] = coef * acc;
+        }
+    }
+}
+
+// Per site, tr[Gamma_n (B + (BH)^2 B)] is gauge independent when every L_mu >= 3
+// (only back-and-forth hop pairs return to the site); in the chiral basis
+// with b0 = 1/(1+eps^2), b1 = i eps/(1+eps^2) ... it is non-zero only for
+// Gamma = 1 and Gamma = gamma5:
+//   n = 0:  12/(1+eps^2) - 384 kappa^2 eps^2/(1+eps^2)^3
+//   n = 15: -12 i eps/(1+eps^2) - 192 i kappa^2 eps (1-eps^2)/(1+eps^2)^3
+void hpe_exact_part(tm_ctx *c, double e, cx<double> *out)
+{
+    const int Lt = c->geo.L[3];
+    const double Vs = (double)c->geo.L[0] * c->geo.L[1] * c->geo.L[2];
+    const double k2 = c->kappa * c->kappa, d = 1.0 + e * e;
+    cx<double> c0{Vs * (12.0 / d - 384.0 * k2 * e * e / (d * d * d)), 0.0};
+    cx<double> c15{0.0, Vs * (-12.0 * e / d - 192.0 * k2 * e * (1.0 - e * e) / (d * d * d))};
+    for (int n = 0; n < 16; n++)
+        for (int t = 0; t < Lt; t++) out[(size_t)n * Lt + t] = n == 0 ? c0 : n == 15 ? c15 : cx<double>{0, 0};
+}
+
+int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noise, tm_loop_stats *stats,
+              hipStream_t s)
+{
+    const double t0 = now_s();
+    TM_REQUIRE(p != nullptr && loops != nullptr, "null argument");
+    TM_REQUIRE(p->n_hp >= 0 && p->n_lp >= 0 && p->n_hp + p->n_lp >= 1, "need at least one noise vector");
+    TM_REQUIRE(p->estimators > 0 && p->estimators < 8, "bad estimator mask");
+    TM_REQUIRE(p->dilution == TM_DIL_NONE || p->dilution == TM_DIL_SPIN_COLOUR, "bad dilution");
+    TM_REQUIRE(p->mu_sign == 1 || p->mu_sign == -1, "mu_sign must be +1 or -1");
+    TM_REQUIRE(p->noise_offset >= 0, "noise_offset must be >= 0");
+    if (p->estimators & TM_EST_HPE)
+        for (int mu = 0; mu < 4; mu++)
+            TM_REQUIRE(c->geo.L[mu] >= 4, "HPE needs every L_mu >= 4");
+    const int Lt = c->geo.L[3];
+    const int nrhs = p->dilution == TM_DIL_SPIN_COLOUR ? 12 : 1;
+    const int n_noise = p->n_hp + p->n_lp;
+    const double epsp = eps_of(c, p->mu_sign);
+    int n_est = 0;
+    int est_ids[3];
+    for (int b = 0; b < 3; b++)
+        if (p->estimators & (1 << b)) est_ids[n_est++] = 1 << b;
+    const size_t f64 = field_bytes(c, TM_F64, nrhs);
+    void *ee = ws_get(c, "l_eta_e", f64), *eo = ws_get(c, "l_eta_o", f64);
+    void *se = ws_get(c, "l_s_e", f64), *so = ws_get(c, "l_s_o", f64);
+    void *he = ws_get(c, "l_h_e", f64), *ho = ws_get(c, "l_h_o", f64);
+    const size_t per = (size_t)16 * Lt;
+    // per-noise loops [noise][prec 0 hp, 1 lp][est][16][Lt]
+    std::vector<cx<double>> pn((size_t)n_noise * 2 * n_est * per, cx<double>{0, 0});
+    tm_loop_stats st{};
+    int status = TM_OK;
+    std::vector<cx<double>> C;
+
+    auto contract = [&](int noise, int slot) {
+        for (int k = 0; k < n_est; k++) {
+            cx<double> *dst = &pn[(((size_t)noise * 2 + slot) * n_est + k) * per];
+            if (est_ids[k] == TM_EST_STD) {
+                outer_slices_host(c, se, so, ee, eo, nrhs, C, s);
+                loops_from_outer(c, C, false, cx<double>{1, 0}, dst);
+            } else if (est_ids[k] == TM_EST_ONE_END) {
+                outer_slices_host(c, se, so, se, so, nrhs, C, s);
+                loops_from_outer(c, C, true, cx<double>{0, 2.0 * epsp}, dst);
+            } else {
+                copy_field(he, se, f64, s);
+                copy_field(ho, so, f64, s);
+                op_bh_power(c, he, ho, nrhs, epsp, 4, s);
+                outer_slices_host(c, he, ho, ee, eo, nrhs, C, s);
+                loops_from_outer(c, C, false, cx<double>{1, 0}, dst);
+            }
+        }
+    };
+
+    for (int k = 0; k < n_noise; k++) {
+        const long r = (long)p->noise_offset + k;
+        launch_noise(c, ee, eo, p->seed, r, p->dilution, s);
+        if (k < p->n_hp) {
+            tm_solve_params hp = p->hp;
+            hp.mu_sign = p->mu_sign;
+            SolveOut so_ = solve_halves(c, se, so, ee, eo, nrhs, hp, s);
+            for (auto &q : so_.st) {
+                st.n_solves_hp++;
+                st.iters_hp += q.iters;
+                st.max_res_hp = std::max(st.max_res_hp, q.true_rel_res);
+            }
+            if (so_.status != TM_OK && status == TM_OK) status = so_.status;
+            contract(k, 0);
+        }
+        if (p->n_lp > 0) {
+            tm_solve_params lp = p->lp;
+            lp.mu_sign = p->mu_sign;
+            SolveOut so_ = solve_halves(c, se, so, ee, eo, nrhs, lp, s);
+            for (auto &q : so_.st) {
+                st.n_solves_lp++;
+                st.iters_lp += q.iters;
+                st.max_res_lp = std::max(st.max_res_lp, q.true_rel_res);
+            }
+            if (so_.status == TM_ERR_NAN) status = TM_ERR_NAN;
+            contract(k, 1);
+        }
+    }
+
+    // TSM combination (eq. estiTSM) or the plain mean, per estimator
+    std::vector<cx<double>> ex(per);
+    if (p->estimators & TM_EST_HPE) hpe_exact_part(c, epsp, ex.data());
+    for (int k = 0; k < n_est; k++) {
+        cx<double> *dst = (cx<double> *)loops + (size_t)k * per;
+        for (size_t j = 0; j < per; j++) {
+            cx<double> acc{0, 0};
+            if (p->n_lp == 0) {
+                for (int r = 0; r < p->n_hp; r++) acc = acc + pn[(((size_t)r * 2 + 0) * n_est + k) * per + j];
+                acc = (1.0 / p->n_hp) * acc;
+            } else {
+                cx<double> corr{0, 0}, lpm{0, 0};
+                for (int r = 0; r < p->n_hp; r++)
+                    corr = corr + pn[(((size_t)r * 2 + 0) * n_est + k) * per + j] -
+                           pn[(((size_t)r * 2 + 1) * n_est + k) * per + j];
+                for (int r = p->n_hp; r < n_noise; r++) lpm = lpm + pn[(((size_t)r * 2 + 1) * n_est + k) * per + j];
+                if (p->n_hp > 0) acc = (1.0 / p->n_hp) * corr;
+                acc = acc + (1.0 / p->n_lp) * lpm;
+            }
+            if (est_ids[k] == TM_EST_HPE) acc = acc + ex[j];
+            dst[j] = acc;
+        }
+    }
+    if (per_noise) memcpy(per_noise, pn.data(), pn.size() * sizeof(cx<double>));
+    st.seconds = now_s() - t0;
+    if (stats) *stats = st;
+    return status;
+}

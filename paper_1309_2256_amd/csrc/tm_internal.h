@@ -1,0 +1,359 @@
+// Internal definitions of the gfx950 twisted-mass library: complex arithmetic,
+// storage precisions, lattice geometry, the context and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "tm.h"
+
+// ---------------------------------------------------------------- errors
+
+struct TmError {
+    int status;
+    std::string msg;
+};
+
+#define TM_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw TmError{TM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define TM_REQUIRE(cond, msg)                                 \
+    do {                                                      \
+        if (!(cond)) throw TmError{TM_ERR_ARG, (msg)};        \
+    } while (0)
+
+// ---------------------------------------------------------------- complex
+
+template <typename T>
+struct cx {
+    T r, i;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+// a * i
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.r, -a.i}; }
+// acc += a * b
+template <typename T>
+__host__ __device__ __forceinline__ void cmac(cx<T> &acc, cx<T> a, cx<T> b)
+{
+    acc.r = fma(a.r, b.r, acc.r);
+    acc.r = fma(-a.i, b.i, acc.r);
+    acc.i = fma(a.r, b.i, acc.i);
+    acc.i = fma(a.i, b.r, acc.i);
+}
+// acc += conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ void cmac_conj(cx<T> &acc, cx<T> a, cx<T> b)
+{
+    acc.r = fma(a.r, b.r, acc.r);
+    acc.r = fma(a.i, b.i, acc.r);
+    acc.i = fma(a.r, b.i, acc.i);
+    acc.i = fma(-a.i, b.r, acc.i);
+}
+
+// ---------------------------------------------------------------- storage types
+
+// IEEE binary16 pair and bfloat16 pair, 4 bytes per complex value.
+struct alignas(4) h2 {
+    _Float16 x, y;
+};
+struct alignas(4) b2 {
+    uint16_t x, y;
+};
+
+__host__ __device__ __forceinline__ float bf16_to_f32(uint16_t v)
+{
+    union { uint32_t u; float f; } c;
+    c.u = ((uint32_t)v) << 16;
+    return c.f;
+}
+// round to nearest even; NaN stays NaN
+__host__ __device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    union { uint32_t u; float f; } c;
+    c.f = f;
+    if ((c.u & 0x7f800000u) == 0x7f800000u && (c.u & 0x007fffffu)) return (uint16_t)((c.u >> 16) | 0x40);
+    uint32_t lsb = (c.u >> 16) & 1u;
+    c.u += 0x7fffu + lsb;
+    return (uint16_t)(c.u >> 16);
+}
+
+template <typename S>
+struct StoreTraits;
+template <>
+struct StoreTraits<double2> {
+    using real = double;
+    __device__ __forceinline__ static cx<double> ld(const double2 *p, size_t k)
+    {
+        double2 v = p[k];
+        return {v.x, v.y};
+    }
+    __device__ __forceinline__ static void st(double2 *p, size_t k, cx<double> v) { p[k] = make_double2(v.r, v.i); }
+};
+template <>
+struct StoreTraits<float2> {
+    using real = float;
+    __device__ __forceinline__ static cx<float> ld(const float2 *p, size_t k)
+    {
+        float2 v = p[k];
+        return {v.x, v.y};
+    }
+    __device__ __forceinline__ static void st(float2 *p, size_t k, cx<float> v) { p[k] = make_float2(v.r, v.i); }
+};
+template <>
+struct StoreTraits<h2> {
+    using real = float;
+    __device__ __forceinline__ static cx<float> ld(const h2 *p, size_t k)
+    {
+        h2 v = p[k];
+        return {(float)v.x, (float)v.y};
+    }
+    __device__ __forceinline__ static void st(h2 *p, size_t k, cx<float> v)
+    {
+        h2 o;
+        o.x = (_Float16)v.r;
+        o.y = (_Float16)v.i;
+        p[k] = o;
+    }
+};
+template <>
+struct StoreTraits<b2> {
+    using real = float;
+    __device__ __forceinline__ static cx<float> ld(const b2 *p, size_t k)
+    {
+        b2 v = p[k];
+        return {bf16_to_f32(v.x), bf16_to_f32(v.y)};
+    }
+    __device__ __forceinline__ static void st(b2 *p, size_t k, cx<float> v)
+    {
+        b2 o;
+        o.x = f32_to_bf16(v.r);
+        o.y = f32_to_bf16(v.i);
+        p[k] = o;
+    }
+};
+
+// load a complex of storage S converted to arithmetic type T
+template <typename T, typename S>
+__device__ __forceinline__ cx<T> ldT(const S *p, size_t k)
+{
+    auto v = StoreTraits<S>::ld(p, k);
+    return {(T)v.r, (T)v.i};
+}
+template <typename T, typename S>
+__device__ __forceinline__ void stT(S *p, size_t k, cx<T> v)
+{
+    using R = typename StoreTraits<S>::real;
+    StoreTraits<S>::st(p, k, cx<R>{(R)v.r, (R)v.i});
+}
+
+static inline size_t prec_bytes(int prec)
+{
+    switch (prec) {
+    case TM_F64: return 16;
+    case TM_F32: return 8;
+    case TM_F16: return 4;
+    case TM_BF16: return 4;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- geometry
+
+// Lattice geometry for kernels (passed by value).  Half-site index i of parity
+// p is s >> 1 with s = x + Lx*(y + Ly*(z + Lz*t)); the row q = y + Ly*(z + Lz*t)
+// gives i = (x >> 1) + (Lx/2) * q.
+struct Geo {
+    int L[4];
+    int lxh;   // Lx / 2
+    int vh;    // V / 2
+    int vsh;   // half-sites per time slice, Lx*Ly*Lz / 2
+};
+
+__device__ __forceinline__ void eo_coords(const Geo &g, int p, int i, int &x, int &y, int &z, int &t)
+{
+    int q = i / g.lxh;
+    int xh = i - q * g.lxh;
+    y = q % g.L[1];
+    int q2 = q / g.L[1];
+    z = q2 % g.L[2];
+    t = q2 / g.L[2];
+    x = 2 * xh + ((p ^ (y + z + t)) & 1);
+}
+
+__device__ __forceinline__ int eo_index(const Geo &g, int x, int y, int z, int t)
+{
+    return (x >> 1) + g.lxh * (y + g.L[1] * (z + g.L[2] * t));
+}
+
+// Logical block index with contiguous chunks of blocks on each of the 8 XCDs:
+// hardware dispatches consecutive workgroups round-robin over the XCDs, so
+// block b runs on XCD b % 8; mapping it to chunk (b % 8) keeps lattice
+// neighbours (nearby half-site indices) inside one XCD's L2.
+__host__ __device__ __forceinline__ int xcd_block(int b, int nblk)
+{
+    // XCD k receives hardware blocks k, k+8, ...: base + (k < rem) of them
+    int base = nblk >> 3, rem = nblk & 7;
+    int k = b & 7, m = b >> 3;
+    return k * base + (k < rem ? k : rem) + m;
+}
+
+// ---------------------------------------------------------------- context
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct tm_ctx {
+    int device = 0;
+    tm_lattice lat{};
+    Geo geo{};
+    long V = 0;
+    double kappa = 0, eps = 0;
+    int t_bc = -1;
+    // internal links per parity of the output site: [8 directions][9][vh]
+    // direction d < 4: U_d(x) (forward hop); d >= 4: U_{d-4}(x - d)^dag
+    // (backward hop), boundary phase folded in
+    void *links64[2] = {nullptr, nullptr};
+    void *links32[2] = {nullptr, nullptr};
+    bool have_gauge = false;
+    bool have_links32 = false;
+    std::map<std::string, DevBuf> ws;
+    std::string err;
+    // pinned host staging for scalar read-back
+    void *host_pinned = nullptr;
+    size_t host_pinned_bytes = 0;
+};
+
+void *ws_get(tm_ctx *c, const std::string &name, size_t bytes);
+void *host_stage(tm_ctx *c, size_t bytes);
+void ensure_links32(tm_ctx *c, hipStream_t s);
+
+// ---------------------------------------------------------------- dslash
+
+// spin-diagonal operator: diag(u, u, l, l) in the chiral basis (R(eps),
+// R^-1, gamma5 and their products are all of this form)
+struct SpinDiag {
+    cx<double> u, l;
+};
+
+static inline SpinDiag sd_scalar(double a) { return {{a, 0}, {a, 0}}; }
+static inline SpinDiag sd_mul(SpinDiag a, SpinDiag b) { return {a.u * b.u, a.l * b.l}; }
+static inline SpinDiag sd_twist(double eps)  // R = 1 + i eps gamma5
+{
+    return {{1.0, eps}, {1.0, -eps}};
+}
+static inline SpinDiag sd_twist_inv(double eps)  // R^-1 = (1 - i eps gamma5)/(1 + eps^2)
+{
+    double d = 1.0 / (1.0 + eps * eps);
+    return {{d, -eps * d}, {d, eps * d}};
+}
+static inline SpinDiag sd_gamma5() { return {{1.0, 0}, {-1.0, 0}}; }
+
+// out(x) = D_own own(x) + D_hop (Hop[in'])(x),  in' = D_in in,
+// x over the half sites of parity out_parity; Hop is the hopping sum without
+// the -kappa factor (fold it into D_hop).  dag selects the adjoint projector
+// placement ((1+gamma) forward, (1-gamma) backward), i.e. Hop^dag.
+struct DslashCall {
+    void *out;
+    const void *in;
+    const void *own;  // may be null when D_own = 0
+    int nrhs;
+    int out_parity;
+    int dag;
+    int spinor_prec;  // TM_F64 with FP64 links, else FP32 links
+    SpinDiag d_own, d_hop, d_in;
+    bool has_own, has_in;
+};
+
+void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s);
+
+// ---------------------------------------------------------------- blas
+
+// All vectors: half layout [nrhs][12][vh] of the given precision.
+// Per-RHS scalars live in device memory (double).
+void launch_spin_diag(tm_ctx *c, void *out, const void *in, int prec, int nrhs, SpinDiag d,
+                      hipStream_t s);
+void launch_copy_convert(tm_ctx *c, void *out, int out_prec, const void *in, int in_prec, int nrhs,
+                         const double *dscale /* device per-rhs or null */, hipStream_t s);
+// y = a*x + b*y with host scalars (same prec)
+void launch_axpby_host(tm_ctx *c, void *y, const void *x, int prec, int nrhs, double a, double b,
+                       hipStream_t s);
+void launch_zero(tm_ctx *c, void *y, int prec, int nrhs, hipStream_t s);
+// y[r] += a_dev[r] * x[r]
+void launch_axpy_dev(tm_ctx *c, void *y, int yprec, const void *x, int xprec, int nrhs, const double *a_dev,
+                     hipStream_t s);
+// per-rhs |v|^2 into dev_out[nrhs] (device doubles), deterministic
+void launch_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *dev_out, hipStream_t s);
+
+// CG building blocks (see solver.hip)
+struct CGScalars {
+    double rr;       // |r|^2 (normal residual)
+    double qq;       // |Ahat p|^2
+    double alpha, beta;
+    double rho2;     // |rho|^2, iterated Schur residual
+    double rho2_ref; // |rho|^2 at the last reliable update
+    double target2;  // (tol |b|)^2 in the units of the vectors
+    double sigma;    // scale of the low-precision vectors (MIXED/LOW)
+    int active;
+    int iters;
+    int want_update; // reliable update requested
+    int bad;         // NaN/Inf seen
+};
+
+void cg_finish_alpha(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int nrhs, hipStream_t s);
+void cg_finish_beta(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int nrhs, double delta,
+                    hipStream_t s);
+// x += alpha p (x in xprec), rho -= alpha q, partial |rho|^2
+void cg_update_xrho(tm_ctx *c, void *x, int xprec, void *rho, const void *p, const void *q, int prec,
+                    int nrhs, const CGScalars *sc, double *part, int nblk, double xscale_by_sigma,
+                    hipStream_t s);
+// r -= alpha s, partial |r|^2
+void cg_update_r(tm_ctx *c, void *r, const void *sv, int prec, int nrhs, const CGScalars *sc,
+                 double *part, int nblk, hipStream_t s);
+// p = r + beta p
+void cg_update_p(tm_ctx *c, void *p, const void *r, int prec, int nrhs, const CGScalars *sc,
+                 hipStream_t s);
+// partial |v|^2 only
+void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *part, int nblk, hipStream_t s);
+int reduce_blocks(tm_ctx *c);
+
+// ---------------------------------------------------------------- misc kernels
+
+void launch_pack(tm_ctx *c, void *even, void *odd, const double *full, int nrhs, int prec,
+                 const double *dscale, hipStream_t s);
+void launch_unpack(tm_ctx *c, double *full, const void *even, const void *odd, int nrhs, int prec,
+                   hipStream_t s);
+void launch_gauge_ingest(tm_ctx *c, const double *U, hipStream_t s);
+void launch_links_to_f32(tm_ctx *c, hipStream_t s);
+// Z4 noise for noise index r into FP64 half fields; dilution 1: 12 rhs
+void launch_noise(tm_ctx *c, void *even, void *odd, uint64_t seed, long r, int dilution, hipStream_t s);
+// per time slice 4x4 colour-traced outer products C[b][a](t) = sum_x sum_c v_{bc} w*_{ac}
+// accumulated over nrhs pairs and both parities, FP64; out device [Lt][16] complex
+void launch_outer_slices(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo,
+                         int nrhs, double *dev_out /* [Lt][16][2] */, hipStream_t s);

@@ -1,0 +1,62 @@
+"""Host-side checks of the C-ABI library: it loads, exports every entry point
+declared in include/tm.h, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(tm_\w+)\s*\(", src,
+                                 flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("tm_create", "tm_destroy", "tm_last_error", "tm_set_gauge", "tm_dslash",
+              "tm_solve", "tm_loops", "tm_pack", "tm_unpack", "tm_noise", "tm_contract"):
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1309_2256_amd as P
+    lib = ctypes.CDLL(P.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(P.EXPORTED) == set(declared_functions())
+
+
+def test_binding_struct_sizes_match_header():
+    """ctypes mirrors of the parameter structs have the C layout sizes."""
+    import paper_1309_2256_amd as P
+    assert ctypes.sizeof(P.tm_lattice) == 4 * 4 + 8 + 8 + 4 + 4  # padded to 8
+    assert ctypes.sizeof(P.tm_solve_params) == 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4
+    assert ctypes.sizeof(P.tm_solve_stats) == 4 * 4 + 3 * 8
+    assert ctypes.sizeof(P.tm_loop_params) == 8 + 7 * 4 + 4 + 2 * ctypes.sizeof(P.tm_solve_params)
+
+
+@pytest.mark.parametrize("L", [(3, 4, 4, 4), (4, 4, 4, 5), (0, 4, 4, 4), (4, 4, -2, 4)])
+def test_create_rejects_bad_lattices(L):
+    import paper_1309_2256_amd as P
+    lat = P.tm_lattice((ctypes.c_int * 4)(*L), 0.124, 0.01, -1)
+    h = ctypes.c_void_p()
+    assert P.tm_create(ctypes.byref(h), ctypes.byref(lat), 0) == P.TM_ERR_ARG
+    assert not h.value
+
+
+def test_create_rejects_bad_bc_and_nulls():
+    import paper_1309_2256_amd as P
+    lat = P.tm_lattice((ctypes.c_int * 4)(4, 4, 4, 4), 0.124, 0.01, 0)
+    h = ctypes.c_void_p()
+    assert P.tm_create(ctypes.byref(h), ctypes.byref(lat), 0) == P.TM_ERR_ARG
+    assert P.tm_create(None, ctypes.byref(lat), 0) == P.TM_ERR_ARG
+    assert P.tm_create(ctypes.byref(h), None, 0) == P.TM_ERR_ARG
+    # calls on a null context fail cleanly
+    assert P.tm_dslash(None, None, None, 1, 0, 1, 0, 0, None) == P.TM_ERR_ARG
+    assert P.tm_last_error(None) == b"null context"
+    P.tm_destroy(None)
