@@ -233,6 +233,28 @@ __global__ __launch_bounds__(kBlock) void k_update_p(S *p, const S *rv, size_t n
     }
 }
 
+// x += alpha p; p = r + beta p  (the solution update of this iteration folded
+// into the search-direction update; both use the p that produced q)
+template <typename S, typename XS>
+__global__ __launch_bounds__(kBlock) void k_update_px(S *p, const S *rv, XS *x, size_t n, const CGScalars *sc)
+{
+    using T = typename StoreTraits<S>::real;
+    using TX = typename StoreTraits<XS>::real;
+    const int r = blockIdx.y;
+    if (!sc[r].active && sc[r].alpha == 0.0) return;
+    const T b = sc[r].active ? (T)sc[r].beta : (T)0;
+    const TX ax = (TX)sc[r].alpha;
+    const bool upd_p = sc[r].active != 0;
+    const size_t base = (size_t)r * n;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        const size_t k = base + e;
+        cx<T> pv = ldT<T>(p, k);
+        cx<TX> xv = ldT<TX>(x, k);
+        stT<TX>(x, k, xv + ax * cx<TX>{(TX)pv.r, (TX)pv.i});
+        if (upd_p) stT<T>(p, k, ldT<T>(rv, k) + b * pv);
+    }
+}
+
 size_t half_elems(tm_ctx *c) { return (size_t)12 * c->geo.vh; }
 
 int grid_for(size_t n)
@@ -404,5 +426,25 @@ void launch_axpy_dev(tm_ctx *c, void *y, int yprec, const void *x, int xprec, in
             hipLaunchKernelGGL((k_axpy_dev<SY, SX>), grid, dim3(kBlock), 0, s, (SY *)y, (const SX *)x, n, a_dev);
         });
     });
+    TM_HIP(hipGetLastError());
+}
+
+void cg_update_px(tm_ctx *c, void *p, const void *r, void *x, int prec, int xprec, int nrhs, const CGScalars *sc,
+                  hipStream_t s)
+{
+    size_t n = half_elems(c);
+    dim3 grid(grid_for(n), nrhs);
+    if (prec == TM_F64) {
+        TM_REQUIRE(xprec == TM_F64, "FP64 CG needs an FP64 solution vector");
+        hipLaunchKernelGGL((k_update_px<double2, double2>), grid, dim3(kBlock), 0, s, (double2 *)p,
+                           (const double2 *)r, (double2 *)x, n, sc);
+    } else {
+        TM_REQUIRE(xprec == TM_F32, "low-precision CG accumulates in FP32");
+        dispatch_prec(prec, [&](auto *tag) {
+            using S = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((k_update_px<S, float2>), grid, dim3(kBlock), 0, s, (S *)p, (const S *)r,
+                               (float2 *)x, n, sc);
+        });
+    }
     TM_HIP(hipGetLastError());
 }

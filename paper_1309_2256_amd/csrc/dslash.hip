@@ -14,6 +14,8 @@
 //   links    [direction 0..7][row*3 + col][vh] for the output parity; the
 //            backward links are stored conjugated and the antiperiodic
 //            boundary phase is folded in, so the kernel has no branch on it.
+#include <cstdlib>
+
 #include "tm_internal.h"
 
 namespace {
@@ -23,7 +25,7 @@ constexpr int kBlock = 256;
 // per lane to 512 / waves): one FP64 right-hand side needs ~180 registers,
 // one or two FP32-arithmetic right-hand sides fit in 128
 template <typename T, int R>
-constexpr int waves_for() { return sizeof(T) == 8 ? 2 : 4; }
+constexpr int waves_for() { return sizeof(T) == 8 ? 2 : (R <= 2 ? 4 : 3); }
 
 template <typename T>
 struct DParams {
@@ -34,45 +36,90 @@ struct DParams {
     Geo g;
     int p;          // output parity
     int nrhs;
-    cx<T> own_u, own_l, hop_u, hop_l, in_u, in_l;
-    int has_own, has_in;
+    int ngroups;    // nrhs / R right-hand-side groups
+    cx<T> own_u, own_l, hop_u, hop_l;
+    // +1, passed at run time so that the +-1 factors of the spin projection
+    // stay FMAs (which take the FP16 inputs directly) instead of being folded
+    // into adds that need separate conversions
+    T one;
+    // fused epilogues: partial sums [quantity][rhs][site block]
+    void *r;        // EPI_CG: normal residual, updated in place
+    void *rho;      // EPI_CG: Schur residual, updated in place
+    const CGScalars *sc;
+    double *part;
+    int nblk;       // site blocks
+    int nb_t;       // site blocks per time slice (tiled traversal) or 0
 };
 
-// (w0, w1) = i sigma_k (v0, v1) for k = 0, 1, 2 (sigma_1, sigma_2, sigma_3)
-template <int K, typename T>
-__device__ __forceinline__ void isigma(cx<T> v0, cx<T> v1, cx<T> &w0, cx<T> &w1)
+// Block -> (site block, right-hand-side group).  Hardware dispatches
+// workgroup b to XCD b % 8.  Tiled traversal (when each time slice is a
+// whole number of site blocks and of 8-block spatial chunks): XCD k owns the
+// k-th eighth of every time slice and walks t slowest, so a site's t +- 1
+// neighbours were loaded about eight site blocks earlier / later on the same
+// XCD (its L2), z +- 1 two blocks away; the right-hand-side groups sharing a
+// site block (and its links) are adjacent.  Otherwise: contiguous chunks of
+// the natural order per XCD.
+__device__ __forceinline__ int map_block(int b, int nblk_hw, int ngroups, int nb_t, int &grp)
 {
-    if (K == 0) {            // i sigma_1 = [[0, i], [i, 0]]
-        w0 = times_i(v1);
-        w1 = times_i(v0);
-    } else if (K == 1) {     // i sigma_2 = [[0, 1], [-1, 0]]
-        w0 = v1;
-        w1 = cx<T>{-v0.r, -v0.i};
-    } else {                 // i sigma_3 = [[i, 0], [0, -i]]
-        w0 = times_i(v0);
-        w1 = cx<T>{v1.i, -v1.r};
+    if (nb_t) {
+        const int k = b & 7, m = b >> 3;
+        grp = m % ngroups;
+        const int m2 = m / ngroups, w = nb_t >> 3;
+        const int t = m2 / w;
+        return t * nb_t + k * w + (m2 - t * w);
     }
+    const int lb = xcd_block(b, nblk_hw);
+    grp = lb % ngroups;
+    return lb / ngroups;
 }
 
-// acc += (1 - S gamma_MU) (W (x) 1) psi  for S = +1 or -1, using the
-// half-spinor form: h = P psi (2 spins), w = W h, lower spins rebuilt from w.
-// Spatial gamma_k = [[0, -i s_k], [i s_k, 0]]:  h = u + S i s_k l,
-//   lower = -S i s_k h.   gamma_4 = [[0, 1], [1, 0]]:  h = u - S l, lower = -S h.
-template <int MU, int S, typename T>
-__device__ __forceinline__ void hop_dir(cx<T> acc[12], const cx<T> W[9], const cx<T> psi[12])
+// A stored complex value as loaded: components in the storage type (FP16
+// stays FP16 so that the projection below folds the conversion into a
+// mixed-precision FMA), converted to T where they are combined.
+template <typename L>
+struct rawc {
+    L r, i;
+};
+
+// h = u + S*l, h = u + S*i*l and h = u - S*i*l in arithmetic type T, each real
+// part one FMA on the raw stored components
+template <typename T, typename L>
+__device__ __forceinline__ cx<T> p_add(rawc<L> u, rawc<L> l, T s)
 {
-    const T s = (T)S;
+    return {fma(s, (T)l.r, (T)u.r), fma(s, (T)l.i, (T)u.i)};
+}
+template <typename T, typename L>
+__device__ __forceinline__ cx<T> p_addi(rawc<L> u, rawc<L> l, T s)
+{
+    return {fma(-s, (T)l.i, (T)u.r), fma(s, (T)l.r, (T)u.i)};
+}
+
+// acc += (1 - S gamma_MU) (W (x) 1) psi  for S = +1 or -1 in the half-spinor
+// form: h = P psi (two spins), w = W h, the lower spins rebuilt from w.
+// gamma_k = [[0, -i s_k], [i s_k, 0]]:  h = u + S (i s_k) l,  lower = -S (i s_k) w
+// gamma_4 = [[0, 1], [1, 0]]:           h = u - S l,          lower = -S w
+// with i s_1 = [[0, i], [i, 0]], i s_2 = [[0, 1], [-1, 0]], i s_3 = [[i, 0], [0, -i]].
+// psi[3*spin + colour]; u = spins 0, 1 and l = spins 2, 3.
+template <int MU, int S, typename T, typename L>
+__device__ __forceinline__ void hop_dir(cx<T> acc[12], const cx<T> W[9], const rawc<L> psi[12], T one)
+{
+    const T s = (T)S * one;
     cx<T> h0[3], h1[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        if (MU == 3) {
-            h0[c] = psi[c] - s * psi[6 + c];
-            h1[c] = psi[3 + c] - s * psi[9 + c];
-        } else {
-            cx<T> a, b;
-            isigma<MU>(psi[6 + c], psi[9 + c], a, b);
-            h0[c] = psi[c] + s * a;
-            h1[c] = psi[3 + c] + s * b;
+        const rawc<L> u0 = psi[c], u1 = psi[3 + c], l0 = psi[6 + c], l1 = psi[9 + c];
+        if (MU == 0) {          // h0 = u0 + S i l1, h1 = u1 + S i l0
+            h0[c] = p_addi(u0, l1, s);
+            h1[c] = p_addi(u1, l0, s);
+        } else if (MU == 1) {   // h0 = u0 + S l1,   h1 = u1 - S l0
+            h0[c] = p_add(u0, l1, s);
+            h1[c] = p_add(u1, l0, -s);
+        } else if (MU == 2) {   // h0 = u0 + S i l0, h1 = u1 - S i l1
+            h0[c] = p_addi(u0, l0, s);
+            h1[c] = p_addi(u1, l1, -s);
+        } else {                // h0 = u0 - S l0,   h1 = u1 - S l1
+            h0[c] = p_add(u0, l0, -s);
+            h1[c] = p_add(u1, l1, -s);
         }
     }
     cx<T> w0[3], w1[3];
@@ -89,16 +136,23 @@ __device__ __forceinline__ void hop_dir(cx<T> acc[12], const cx<T> W[9], const c
     }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        acc[c] = acc[c] + w0[c];
-        acc[3 + c] = acc[3 + c] + w1[c];
-        if (MU == 3) {
-            acc[6 + c] = acc[6 + c] - s * w0[c];
-            acc[9 + c] = acc[9 + c] - s * w1[c];
-        } else {
-            cx<T> a, b;
-            isigma<MU>(w0[c], w1[c], a, b);
-            acc[6 + c] = acc[6 + c] - s * a;
-            acc[9 + c] = acc[9 + c] - s * b;
+        acc[c].r += w0[c].r;
+        acc[c].i += w0[c].i;
+        acc[3 + c].r += w1[c].r;
+        acc[3 + c].i += w1[c].i;
+        cx<T> &l0 = acc[6 + c], &l1 = acc[9 + c];
+        if (MU == 0) {          // lower = -S (i w1, i w0)
+            l0.r += s * w1[c].i; l0.i -= s * w1[c].r;
+            l1.r += s * w0[c].i; l1.i -= s * w0[c].r;
+        } else if (MU == 1) {   // lower = -S (w1, -w0)
+            l0.r -= s * w1[c].r; l0.i -= s * w1[c].i;
+            l1.r += s * w0[c].r; l1.i += s * w0[c].i;
+        } else if (MU == 2) {   // lower = -S (i w0, -i w1)
+            l0.r += s * w0[c].i; l0.i -= s * w0[c].r;
+            l1.r -= s * w1[c].i; l1.i += s * w1[c].r;
+        } else {                // lower = -S (w0, w1)
+            l0.r -= s * w0[c].r; l0.i -= s * w0[c].i;
+            l1.r -= s * w1[c].r; l1.i -= s * w1[c].i;
         }
     }
 }
@@ -124,6 +178,19 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, size_t bytes)
 
 template <typename S>
 struct BufIO;
+// component type of a raw load
+template <typename S>
+struct RawT {
+    using L = float;
+};
+template <>
+struct RawT<double2> {
+    using L = double;
+};
+template <>
+struct RawT<h2> {
+    using L = _Float16;
+};
 struct F2 {
     float x, y;
 };
@@ -137,6 +204,11 @@ struct BufIO<double2> {
     {
         D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
         return {(T)v.x, (T)v.y};
+    }
+    __device__ __forceinline__ static rawc<double> ldraw(rsrc_t r, int voff, int soff)
+    {
+        D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        return {v.x, v.y};
     }
     template <typename T>
     __device__ __forceinline__ static void st(rsrc_t r, int voff, int soff, cx<T> c)
@@ -153,6 +225,11 @@ struct BufIO<float2> {
         F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
         return {(T)v.x, (T)v.y};
     }
+    __device__ __forceinline__ static rawc<float> ldraw(rsrc_t r, int voff, int soff)
+    {
+        F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return {v.x, v.y};
+    }
     template <typename T>
     __device__ __forceinline__ static void st(rsrc_t r, int voff, int soff, cx<T> c)
     {
@@ -168,6 +245,11 @@ struct BufIO<h2> {
         unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
         h2 h = __builtin_bit_cast(h2, v);
         return {(T)(float)h.x, (T)(float)h.y};
+    }
+    __device__ __forceinline__ static rawc<_Float16> ldraw(rsrc_t r, int voff, int soff)
+    {
+        h2 h = __builtin_bit_cast(h2, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return {h.x, h.y};
     }
     template <typename T>
     __device__ __forceinline__ static void st(rsrc_t r, int voff, int soff, cx<T> c)
@@ -186,6 +268,11 @@ struct BufIO<b2> {
         unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
         return {(T)__builtin_bit_cast(float, v << 16), (T)__builtin_bit_cast(float, v & 0xffff0000u)};
     }
+    __device__ __forceinline__ static rawc<float> ldraw(rsrc_t r, int voff, int soff)
+    {
+        unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        return {__builtin_bit_cast(float, v << 16), __builtin_bit_cast(float, v & 0xffff0000u)};
+    }
     template <typename T>
     __device__ __forceinline__ static void st(rsrc_t r, int voff, int soff, cx<T> c)
     {
@@ -201,17 +288,11 @@ __device__ __forceinline__ void load_link(cx<T> W[9], rsrc_t lr, int vbytes, int
     for (int k = 0; k < 9; k++) W[k] = BufIO<LS>::template ld<T>(lr, voff, k * vbytes);
 }
 
-template <typename SS, typename T>
-__device__ __forceinline__ void load_spinor(cx<T> psi[12], rsrc_t sr, int vbytes, int voff, const DParams<T> &a)
+template <typename SS>
+__device__ __forceinline__ void load_spinor(rawc<typename RawT<SS>::L> psi[12], rsrc_t sr, int vbytes, int voff)
 {
 #pragma unroll
-    for (int k = 0; k < 12; k++) psi[k] = BufIO<SS>::template ld<T>(sr, voff, k * vbytes);
-    if (a.has_in) {
-#pragma unroll
-        for (int k = 0; k < 6; k++) psi[k] = a.in_u * psi[k];
-#pragma unroll
-        for (int k = 6; k < 12; k++) psi[k] = a.in_l * psi[k];
-    }
+    for (int k = 0; k < 12; k++) psi[k] = BufIO<SS>::ldraw(sr, voff, k * vbytes);
 }
 
 template <int MU, int S, typename SS, typename LS, typename T, int R>
@@ -224,22 +305,62 @@ __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, co
     load_link<LS>(W, lr, a.g.vh * (int)sizeof(LS), i * (int)sizeof(LS));
 #pragma unroll
     for (int rr = 0; rr < R; rr++) {
-        cx<T> psi[12];
-        load_spinor<SS>(psi, sr[rr], a.g.vh * (int)sizeof(SS), j * (int)sizeof(SS), a);
-        hop_dir<MU, S>(acc[rr], W, psi);
+        rawc<typename RawT<SS>::L> psi[12];
+        load_spinor<SS>(psi, sr[rr], a.g.vh * (int)sizeof(SS), j * (int)sizeof(SS));
+        hop_dir<MU, S>(acc[rr], W, psi, a.one);
     }
     // keep the loads of one direction from being hoisted above the previous
     // direction's arithmetic: bounds the live registers to one direction
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <typename SS, typename LS, typename T, int R, int DAG>
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// value as stored in precision SS (what later kernels will read)
+template <typename SS, typename T>
+__device__ __forceinline__ cx<T> stored(cx<T> v)
+{
+    if constexpr (std::is_same<SS, double2>::value) {
+        return v;
+    } else if constexpr (std::is_same<SS, float2>::value) {
+        return {(T)(float)v.r, (T)(float)v.i};
+    } else if constexpr (std::is_same<SS, h2>::value) {
+        return {(T)(float)(_Float16)(float)v.r, (T)(float)(_Float16)(float)v.i};
+    } else {
+        return {(T)bf16_to_f32(f32_to_bf16((float)v.r)), (T)bf16_to_f32(f32_to_bf16((float)v.i))};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double norm2c(cx<T> v)
+{
+    return (double)(v.r * v.r + v.i * v.i);
+}
+
+// Epilogue forms:
+//   EPI_STORE  out = D_hop Hop[in] (+ D_own own)
+//   EPI_NORM   as EPI_STORE, plus per-block partial |out|^2 per right-hand side
+//   EPI_CG     s = D_hop Hop[in] + D_own q (own = q); then r -= alpha s,
+//              rho -= alpha q in place (s is never stored), partial |r|^2 and
+//              |rho|^2 -- the last half of Ahat^dag q fused with the CG updates
+enum { EPI_STORE = 0, EPI_NORM = 1, EPI_CG = 2 };
+
+// Block order: see map_block.
+template <typename SS, typename LS, typename T, int R, int DAG, int OWN, int EPI>
 __global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash(DParams<T> a)
 {
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int i = b * kBlock + threadIdx.x;
-    if (i >= a.g.vh) return;
-    const int r0 = blockIdx.y * R;
+    int grp;
+    const int sblk = map_block(blockIdx.x, gridDim.x, a.ngroups, a.nb_t, grp);
+    const int r0 = grp * R;
+    const int i_raw = sblk * kBlock + threadIdx.x;
+    const bool valid = i_raw < a.g.vh;
+    if (EPI == EPI_STORE && !valid) return;
+    const int i = valid ? i_raw : a.g.vh - 1;  // idle lanes join the block reduction
     const size_t fbytes = (size_t)12 * a.g.vh * sizeof(SS);  // one right-hand side
     rsrc_t sr[R];
 #pragma unroll
@@ -281,18 +402,61 @@ __global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash(DParams<
     }
 
     const int vb = a.g.vh * (int)sizeof(SS), vo = i * (int)sizeof(SS);
+    constexpr int NQ = EPI == EPI_CG ? 2 : 1;
+    double nrm[R][NQ];
 #pragma unroll
     for (int rr = 0; rr < R; rr++) {
         const rsrc_t outr = make_rsrc((char *)a.out + (r0 + rr) * fbytes, fbytes);
         const rsrc_t ownr = make_rsrc((const char *)a.own + (r0 + rr) * fbytes, fbytes);
+        const rsrc_t rr_r = make_rsrc((char *)a.r + (r0 + rr) * fbytes, fbytes);
+        const rsrc_t rho_r = make_rsrc((char *)a.rho + (r0 + rr) * fbytes, fbytes);
+        T alpha = 0;
+        if constexpr (EPI == EPI_CG) alpha = (T)a.sc[r0 + rr].alpha;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) nrm[rr][q] = 0;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             cx<T> v = (k < 6 ? a.hop_u : a.hop_l) * acc[rr][k];
-            if (a.has_own) {
-                cx<T> o = BufIO<SS>::template ld<T>(ownr, vo, k * vb);
+            cx<T> o = {0, 0};
+            if (OWN) {
+                o = BufIO<SS>::template ld<T>(ownr, vo, k * vb);
                 v = v + (k < 6 ? a.own_u : a.own_l) * o;
             }
-            BufIO<SS>::template st<T>(outr, vo, k * vb, v);
+            if constexpr (EPI == EPI_CG) {
+                cx<T> rv = BufIO<SS>::template ld<T>(rr_r, vo, k * vb) - alpha * v;
+                cx<T> hv = BufIO<SS>::template ld<T>(rho_r, vo, k * vb) - alpha * o;
+                if (valid) {
+                    BufIO<SS>::template st<T>(rr_r, vo, k * vb, rv);
+                    BufIO<SS>::template st<T>(rho_r, vo, k * vb, hv);
+                    nrm[rr][0] += norm2c(stored<SS>(rv));
+                    nrm[rr][1] += norm2c(stored<SS>(hv));
+                }
+            } else {
+                if (valid) {
+                    BufIO<SS>::template st<T>(outr, vo, k * vb, v);
+                    if constexpr (EPI == EPI_NORM) nrm[rr][0] += norm2c(stored<SS>(v));
+                }
+            }
+        }
+    }
+    if constexpr (EPI != EPI_STORE) {
+        // deterministic block reduction: wave shuffles, then the 4 waves in order
+        __shared__ double red[kBlock / 64][R * NQ];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int rr = 0; rr < R; rr++)
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                double v = wave_sum(nrm[rr][q]);
+                if (lane == 0) red[w][rr * NQ + q] = v;
+            }
+        __syncthreads();
+        if (threadIdx.x < R * NQ) {
+            const int rr = threadIdx.x / NQ, q = threadIdx.x % NQ;
+            double s = 0;
+#pragma unroll
+            for (int k = 0; k < kBlock / 64; k++) s += red[k][threadIdx.x];
+            a.part[((size_t)q * a.nrhs + r0 + rr) * a.nblk + sblk] = s;
         }
     }
 }
@@ -301,6 +465,21 @@ template <typename T>
 cx<T> cvt(cx<double> v)
 {
     return cx<T>{(T)v.r, (T)v.i};
+}
+
+template <typename SS, typename LS, typename T, int R, int DAG, int OWN>
+void launch_epi(const DslashCall &dc, dim3 grid, hipStream_t s, const DParams<T> &a)
+{
+    switch (dc.epi) {
+    case EPI_NORM: hipLaunchKernelGGL((k_dslash<SS, LS, T, R, DAG, OWN, EPI_NORM>), grid, dim3(kBlock), 0, s, a); break;
+    case EPI_CG:
+        if constexpr (OWN == 1)
+            hipLaunchKernelGGL((k_dslash<SS, LS, T, R, DAG, OWN, EPI_CG>), grid, dim3(kBlock), 0, s, a);
+        else
+            throw TmError{TM_ERR_ARG, "fused CG epilogue needs the own-site term"};
+        break;
+    default: hipLaunchKernelGGL((k_dslash<SS, LS, T, R, DAG, OWN, EPI_STORE>), grid, dim3(kBlock), 0, s, a);
+    }
 }
 
 template <typename SS, typename LS, typename T, int R>
@@ -314,38 +493,105 @@ void launch_t(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     a.g = c->geo;
     a.p = dc.out_parity;
     a.nrhs = dc.nrhs;
+    a.ngroups = dc.nrhs / R;
     a.own_u = cvt<T>(dc.d_own.u);
     a.own_l = cvt<T>(dc.d_own.l);
     a.hop_u = cvt<T>(dc.d_hop.u);
     a.hop_l = cvt<T>(dc.d_hop.l);
-    a.in_u = cvt<T>(dc.d_in.u);
-    a.in_l = cvt<T>(dc.d_in.l);
-    a.has_own = dc.has_own ? 1 : 0;
-    a.has_in = dc.has_in ? 1 : 0;
-    dim3 grid((c->geo.vh + kBlock - 1) / kBlock, dc.nrhs / R);
-    if (dc.dag)
-        hipLaunchKernelGGL((k_dslash<SS, LS, T, R, 1>), grid, dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_dslash<SS, LS, T, R, 0>), grid, dim3(kBlock), 0, s, a);
+    a.one = (T)1;
+    a.r = dc.r;
+    a.rho = dc.rho;
+    a.sc = dc.sc;
+    a.part = dc.part;
+    a.nblk = dslash_site_blocks(c);
+    a.nb_t = (c->geo.vsh % kBlock == 0 && (c->geo.vsh / kBlock) % 8 == 0) ? c->geo.vsh / kBlock : 0;
+    dim3 grid((unsigned)(a.nblk * a.ngroups));
+    // separate kernels per projector placement and per presence of the
+    // own-site term (the x - H y forms read one more field)
+    if (dc.dag) {
+        if (dc.has_own)
+            launch_epi<SS, LS, T, R, 1, 1>(dc, grid, s, a);
+        else
+            launch_epi<SS, LS, T, R, 1, 0>(dc, grid, s, a);
+    } else {
+        if (dc.has_own)
+            launch_epi<SS, LS, T, R, 0, 1>(dc, grid, s, a);
+        else
+            launch_epi<SS, LS, T, R, 0, 0>(dc, grid, s, a);
+    }
     TM_HIP(hipGetLastError());
 }
 
 template <typename SS, typename LS, typename T>
+void launch_r(tm_ctx *c, const DslashCall &dc, int R, hipStream_t s)
+{
+    switch (R) {
+    case 3: launch_t<SS, LS, T, 3>(c, dc, s); break;
+    case 2: launch_t<SS, LS, T, 2>(c, dc, s); break;
+    default: launch_t<SS, LS, T, 1>(c, dc, s);
+    }
+}
+
+// Right-hand sides per thread (each loaded link serves R spinors).  The first
+// side-effect-free launch for a (precision, nrhs) pair times every tile that
+// divides nrhs and keeps the fastest; results are bit-identical across tiles.
+template <typename SS, typename LS, typename T>
 void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 {
-    // right-hand sides per thread: reuse each loaded link for two spinors
-    const int n = dc.nrhs;
     if constexpr (std::is_same<T, double>::value) {
         launch_t<SS, LS, T, 1>(c, dc, s);
     } else {
-        if (n % 2 == 0)
-            launch_t<SS, LS, T, 2>(c, dc, s);
-        else
-            launch_t<SS, LS, T, 1>(c, dc, s);
+        const int n = dc.nrhs;
+        const auto key = std::make_pair(dc.spinor_prec, n);
+        auto it = c->rhs_tile.find(key);
+        if (it != c->rhs_tile.end()) {
+            launch_r<SS, LS, T>(c, dc, it->second, s);
+            return;
+        }
+        int fixed = 0;
+        if (const char *e = getenv("TM_DSLASH_RHS_TILE")) fixed = atoi(e);
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        TM_HIP(hipStreamIsCapturing(s, &cs));
+        const int def = n % 2 == 0 ? 2 : 1;
+        if (fixed > 0 && n % fixed == 0) {
+            c->rhs_tile[key] = fixed;
+        } else if (dc.epi != 0 || cs != hipStreamCaptureStatusNone || n == 1) {
+            launch_r<SS, LS, T>(c, dc, def, s);  // tune on a later plain launch
+            return;
+        } else {
+            hipEvent_t e0, e1;
+            TM_HIP(hipEventCreate(&e0));
+            TM_HIP(hipEventCreate(&e1));
+            float best = 1e30f;
+            int bestR = def;
+            // 4 or more right-hand sides per thread exceed the register
+            // budget of 3 resident waves and spill
+            for (int R : {1, 2, 3}) {
+                if (n % R) continue;
+                launch_r<SS, LS, T>(c, dc, R, s);  // warm
+                TM_HIP(hipEventRecord(e0, s));
+                launch_r<SS, LS, T>(c, dc, R, s);
+                launch_r<SS, LS, T>(c, dc, R, s);
+                TM_HIP(hipEventRecord(e1, s));
+                TM_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                TM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    bestR = R;
+                }
+            }
+            TM_HIP(hipEventDestroy(e0));
+            TM_HIP(hipEventDestroy(e1));
+            c->rhs_tile[key] = bestR;
+        }
+        launch_r<SS, LS, T>(c, dc, c->rhs_tile[key], s);
     }
 }
 
 }  // namespace
+
+int dslash_site_blocks(tm_ctx *c) { return (c->geo.vh + kBlock - 1) / kBlock; }
 
 void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 {

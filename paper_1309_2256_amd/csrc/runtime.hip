@@ -93,9 +93,7 @@ void op_dslash(tm_ctx *c, void *out, const void *in, const void *own, int nrhs, 
     dc.spinor_prec = prec;
     dc.d_own = down;
     dc.d_hop = dhop;
-    dc.d_in = sd_scalar(1.0);
     dc.has_own = own != nullptr;
-    dc.has_in = false;
     launch_dslash(c, dc, s);
 }
 
@@ -150,18 +148,55 @@ struct CGWork {
 int cg_iterate(tm_ctx *c, CGWork &w, double epsp, double delta, int maxiter, int check_every,
                std::vector<CGScalars> &hsc, hipStream_t s, bool &stop_update)
 {
+    const double k = c->kappa;
+    const int nsb = dslash_site_blocks(c);
     int it = 0;
     stop_update = false;
     while (it < maxiter) {
-        op_schur(c, w.q, w.p, w.tmp, w.nrhs, w.prec, epsp, s);
-        partial_norm2(c, w.q, w.prec, w.nrhs, w.partq, w.nblk, s);
-        cg_finish_alpha(c, w.dsc, w.partq, w.nblk, w.nrhs, s);
-        cg_update_xrho(c, w.x, w.xprec, w.rho, w.p, w.q, w.prec, w.nrhs, w.dsc, w.partb + (size_t)w.nrhs * w.nblk,
-                       w.nblk, 1.0, s);
-        op_schur_dag(c, w.sv, w.q, w.tmp, w.nrhs, w.prec, epsp, s);
-        cg_update_r(c, w.r, w.sv, w.prec, w.nrhs, w.dsc, w.partb, w.nblk, s);
-        cg_finish_beta(c, w.dsc, w.partb, w.nblk, w.nrhs, delta, s);
-        cg_update_p(c, w.p, w.r, w.prec, w.nrhs, w.dsc, s);
+        // q = Ahat p  (second half also forms the partial |q|^2)
+        op_dslash(c, w.tmp, w.p, nullptr, w.nrhs, w.prec, 1, 0, sd_mul(sd_scalar(-k), sd_twist_inv(epsp)),
+                  sd_scalar(0), s);
+        {
+            DslashCall dc{};
+            dc.out = w.q;
+            dc.in = w.tmp;
+            dc.own = w.p;
+            dc.nrhs = w.nrhs;
+            dc.out_parity = 0;
+            dc.dag = 0;
+            dc.spinor_prec = w.prec;
+            dc.d_own = sd_twist(epsp);
+            dc.d_hop = sd_scalar(k);
+            dc.has_own = true;
+            dc.epi = 1;
+            dc.part = w.partq;
+            launch_dslash(c, dc, s);
+        }
+        cg_finish_alpha(c, w.dsc, w.partq, nsb, w.nrhs, s);
+        // s = Ahat^dag q fused with r -= alpha s, rho -= alpha q and their norms
+        op_dslash(c, w.tmp, w.q, nullptr, w.nrhs, w.prec, 1, 1,
+                  sd_mul(sd_scalar(-k), sd_mul(sd_twist_inv(-epsp), sd_gamma5())), sd_scalar(0), s);
+        {
+            DslashCall dc{};
+            dc.out = nullptr;
+            dc.in = w.tmp;
+            dc.own = w.q;
+            dc.nrhs = w.nrhs;
+            dc.out_parity = 0;
+            dc.dag = 0;
+            dc.spinor_prec = w.prec;
+            dc.d_own = sd_twist(-epsp);
+            dc.d_hop = sd_mul(sd_scalar(k), sd_gamma5());
+            dc.has_own = true;
+            dc.epi = 2;
+            dc.r = w.r;
+            dc.rho = w.rho;
+            dc.sc = w.dsc;
+            dc.part = w.partb;
+            launch_dslash(c, dc, s);
+        }
+        cg_finish_beta(c, w.dsc, w.partb, nsb, w.nrhs, delta, s);
+        cg_update_px(c, w.p, w.r, w.x, w.prec, w.xprec, w.nrhs, w.dsc, s);
         it++;
         if (it % check_every == 0 || it == maxiter) {
             download(c, hsc.data(), w.dsc, sizeof(CGScalars) * w.nrhs, s);
@@ -229,8 +264,9 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
     std::vector<int> n_rel(nrhs, 0);
     std::vector<double> iter_res(nrhs, 0.0);
     CGScalars *dsc = (CGScalars *)ws_get(c, "s_sc", sizeof(CGScalars) * nrhs);
-    double *partq = (double *)ws_get(c, "s_partq", sizeof(double) * nblk * nrhs);
-    double *partb = (double *)ws_get(c, "s_partb", sizeof(double) * nblk * nrhs * 2);
+    const int nsb = dslash_site_blocks(c);
+    double *partq = (double *)ws_get(c, "s_partq", sizeof(double) * nsb * nrhs);
+    double *partb = (double *)ws_get(c, "s_partb", sizeof(double) * nsb * nrhs * 2);
 
     if (p.solver == TM_CG_F64) {
         CGWork w{nrhs, TM_F64, nblk};

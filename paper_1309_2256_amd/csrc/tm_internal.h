@@ -244,6 +244,8 @@ struct tm_ctx {
     bool have_gauge = false;
     bool have_links32 = false;
     std::map<std::string, DevBuf> ws;
+    // autotuned right-hand sides per Dslash thread, keyed by (precision, nrhs)
+    std::map<std::pair<int, int>, int> rhs_tile;
     std::string err;
     // pinned host staging for scalar read-back
     void *host_pinned = nullptr;
@@ -275,7 +277,7 @@ static inline SpinDiag sd_twist_inv(double eps)  // R^-1 = (1 - i eps gamma5)/(1
 }
 static inline SpinDiag sd_gamma5() { return {{1.0, 0}, {-1.0, 0}}; }
 
-// out(x) = D_own own(x) + D_hop (Hop[in'])(x),  in' = D_in in,
+// out(x) = D_own own(x) + D_hop (Hop[in])(x),
 // x over the half sites of parity out_parity; Hop is the hopping sum without
 // the -kappa factor (fold it into D_hop).  dag selects the adjoint projector
 // placement ((1+gamma) forward, (1-gamma) backward), i.e. Hop^dag.
@@ -287,11 +289,18 @@ struct DslashCall {
     int out_parity;
     int dag;
     int spinor_prec;  // TM_F64 with FP64 links, else FP32 links
-    SpinDiag d_own, d_hop, d_in;
-    bool has_own, has_in;
+    SpinDiag d_own, d_hop;
+    bool has_own;
+    // fused epilogue (0 store, 1 store + partial |out|^2, 2 CG update of r and
+    // rho with partial |r|^2, |rho|^2; see dslash.hip)
+    int epi = 0;
+    void *r = nullptr, *rho = nullptr;
+    const struct CGScalars *sc = nullptr;
+    double *part = nullptr;  // [quantity][nrhs][dslash_site_blocks]
 };
 
 void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s);
+int dslash_site_blocks(tm_ctx *c);
 
 // ---------------------------------------------------------------- blas
 
@@ -339,6 +348,9 @@ void cg_update_r(tm_ctx *c, void *r, const void *sv, int prec, int nrhs, const C
 // p = r + beta p
 void cg_update_p(tm_ctx *c, void *p, const void *r, int prec, int nrhs, const CGScalars *sc,
                  hipStream_t s);
+// x += alpha p; p = r + beta p
+void cg_update_px(tm_ctx *c, void *p, const void *r, void *x, int prec, int xprec, int nrhs, const CGScalars *sc,
+                  hipStream_t s);
 // partial |v|^2 only
 void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *part, int nblk, hipStream_t s);
 int reduce_blocks(tm_ctx *c);
