@@ -235,6 +235,39 @@ int tm_loops(tm_ctx *ctx, const tm_loop_params *p, double *loops, double *per_no
 int tm_contract(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int estimators,
                 int mu_sign, double *out, tm_stream stream);
 
+/* ---------------------------------------------------------------- batches
+ * Uneven batches: several lattices (one context each, gauge set, same
+ * device, distinct contexts) advanced together.  Each CG iteration of all
+ * instances is one launch per half-Dslash stage over every lattice, and a
+ * group of check_every iterations is captured once as a HIP graph and
+ * replayed; per-RHS scalars stay on the device between groups.  Reliable
+ * updates and convergence are decided per instance with the cadence of
+ * tm_solve, so each instance gets the result of its own tm_solve bit for bit.
+ * The batch owns a private HIP stream; calls synchronise the given stream on
+ * entry and return after all work is complete. */
+typedef struct tm_batch tm_batch;
+
+/* ctxs: n >= 1 distinct contexts on one device (not retained beyond
+ * tm_batch_destroy; they must outlive the batch). */
+int tm_batch_create(tm_batch **batch, tm_ctx *const *ctxs, int n);
+void tm_batch_destroy(tm_batch *batch);
+const char *tm_batch_last_error(const tm_batch *batch);
+
+/* Solve M_i(mu_sign) x_i = b_i for every instance i, nrhs[i] right-hand sides
+ * each (canonical full FP64 device arrays).  One parameter set for all
+ * instances (same solver, precision and check cadence).  stats[i]: host array
+ * of nrhs[i] entries or NULL (stats itself may be NULL). */
+int tm_batch_solve(tm_batch *batch, double *const *x, const double *const *b, const int *nrhs,
+                   const tm_solve_params *p, tm_solve_stats *const *stats, tm_stream stream);
+
+/* Per-instance loops (sec. II, as tm_loops) with p[i].n_hp noise vectors of
+ * high-precision solves each (n_lp must be 0), all instances' sources solved
+ * in one batch; p[i].hp must agree across instances in solver, inner_prec and
+ * check_every.  loops[i]: host [n_est_i][16][Lt_i] complex double; stats:
+ * host array of n entries or NULL. */
+int tm_batch_loops(tm_batch *batch, const tm_loop_params *p, double *const *loops,
+                   tm_loop_stats *stats, tm_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,4 +5,4 @@ package holds its sources (csrc/), the build script and a ctypes binding
 with the same entry-point names.
 """
 from .binding import *  # noqa: F401,F403
-from .binding import Context, TMError, solve_params  # noqa: F401
+from .binding import Batch, Context, TMError, solve_params  # noqa: F401

@@ -84,6 +84,14 @@ _SIGS = {
     "tm_noise": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, ctypes.c_long, ctypes.c_int, _vp]),
     "tm_contract": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                    _vp]),
+    "tm_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int]),
+    "tm_batch_destroy": (None, [_vp]),
+    "tm_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "tm_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(tm_solve_params),
+                                      ctypes.POINTER(ctypes.POINTER(tm_solve_stats)), _vp]),
+    "tm_batch_loops": (ctypes.c_int, [_vp, ctypes.POINTER(tm_loop_params), ctypes.POINTER(_dp),
+                                      ctypes.POINTER(tm_loop_stats), _vp]),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -201,3 +209,56 @@ class Context:
         self._check(tm_contract(self.h, _ptr(eta), _ptr(s), nrhs, estimators, mu_sign,
                                 out.ctypes.data_as(_dp), _stream(stream)))
         return out
+
+
+class Batch:
+    """Several contexts (lattices) solved together (tm_batch_*)."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        arr = (_vp * len(self.contexts))(*[c.h for c in self.contexts])
+        h = ctypes.c_void_p()
+        st = tm_batch_create(ctypes.byref(h), arr, len(self.contexts))
+        if st != TM_OK:
+            raise TMError(st, "tm_batch_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            tm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=()):
+        if st != TM_OK and st not in allow:
+            raise TMError(st, tm_batch_last_error(self.h).decode())
+        return st
+
+    def solve(self, xs, bs, nrhs, params, stream=None, allow_noconv=False):
+        n = len(self.contexts)
+        xa = (_vp * n)(*[x.data_ptr() for x in xs])
+        ba = (_vp * n)(*[b.data_ptr() for b in bs])
+        na = (ctypes.c_int * n)(*nrhs)
+        stats = [(tm_solve_stats * k)() for k in nrhs]
+        sp = (ctypes.POINTER(tm_solve_stats) * n)(*[ctypes.cast(s, ctypes.POINTER(tm_solve_stats))
+                                                    for s in stats])
+        st = tm_batch_solve(self.h, xa, ba, na, ctypes.byref(params), sp, _stream(stream))
+        self._check(st, allow=(TM_ERR_NOCONV,) if allow_noconv else ())
+        return st, [list(s) for s in stats]
+
+    def loops(self, params_list, stream=None, allow_noconv=False):
+        n = len(self.contexts)
+        pa = (tm_loop_params * n)(*params_list)
+        outs = []
+        for c, p in zip(self.contexts, params_list):
+            outs.append(np.zeros((bin(p.estimators).count("1"), 16, c.L[3]), dtype=np.complex128))
+        la = (_dp * n)(*[o.ctypes.data_as(_dp) for o in outs])
+        stats = (tm_loop_stats * n)()
+        st = tm_batch_loops(self.h, pa, la, stats, _stream(stream))
+        self._check(st, allow=(TM_ERR_NOCONV,) if allow_noconv else ())
+        return outs, list(stats), st

@@ -1,0 +1,352 @@
+// Uneven batches: several lattices (contexts) solved together.  Every CG
+// iteration of all instances is four multi-instance half-Dslash launches
+// (one kernel each, all lattices in one grid) plus per-instance scalar and
+// vector kernels; a group of `check_every` iterations is captured once into a
+// HIP graph and replayed, so the host issues one graph launch per group and
+// reads the convergence scalars only between groups.  Reliable updates and
+// convergence decisions are per instance, with the same cadence as a single
+// solve, so each instance follows exactly the arithmetic of its own solve.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "runtime.h"
+
+struct tm_batch {
+    std::vector<tm_ctx *> ctx;
+    int device = 0;
+    std::string err;
+    hipStream_t stream = nullptr;  // own stream (graph capture needs a non-null stream)
+    MultiDslash md[4];
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> graph_set;  // instances captured in the current graph
+    int graph_iters = 0, graph_R = 0;
+    std::map<std::vector<int>, int> tuned_R;  // (prec, nrhs...) -> RHS per thread
+};
+
+namespace {
+
+void drop_graph(tm_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_set.clear();
+}
+
+template <typename F>
+int bguard(tm_batch *b, F &&f)
+{
+    if (!b) return TM_ERR_ARG;
+    try {
+        b->err.clear();
+        TM_HIP(hipSetDevice(b->device));
+        return f();
+    } catch (const TmError &e) {
+        b->err = e.msg;
+        drop_graph(b);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        b->err = "host allocation failed";
+        drop_graph(b);
+        return TM_ERR_OOM;
+    } catch (...) {
+        b->err = "unexpected internal error";
+        drop_graph(b);
+        return TM_ERR_HIP;
+    }
+}
+
+void prepare_stages(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set, int R)
+{
+    std::vector<tm_ctx *> cs;
+    for (int i : set) cs.push_back(S[i].c);
+    for (int k = 0; k < 4; k++) {
+        std::vector<DslashCall> dcs;
+        for (int i : set) dcs.push_back(S[i].stage(k + 1));
+        multi_dslash_prepare(b->md[k], cs, dcs, R, b->stream);
+    }
+}
+
+void launch_iteration(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set)
+{
+    hipStream_t s = b->stream;
+    multi_dslash_launch(b->md[0], s);
+    multi_dslash_launch(b->md[1], s);
+    for (int i : set) cg_finish_alpha(S[i].c, S[i].w.dsc, S[i].w.partq, S[i].nsb, S[i].nrhs, s);
+    multi_dslash_launch(b->md[2], s);
+    multi_dslash_launch(b->md[3], s);
+    for (int i : set) S[i].iteration_tail(s);
+}
+
+// right-hand sides per Dslash thread for the batch: the fastest (timed on the
+// side-effect-free first stage) among the tiles that divide every nrhs
+int choose_R(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set)
+{
+    const int prec = S[set[0]].lp;
+    if (prec == TM_F64) return 1;
+    std::vector<int> key{prec};
+    for (int i : set) key.push_back(S[i].nrhs);
+    auto it = b->tuned_R.find(key);
+    if (it != b->tuned_R.end()) return it->second;
+    hipEvent_t e0, e1;
+    TM_HIP(hipEventCreate(&e0));
+    TM_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestR = 1;
+    for (int R : {1, 2, 3}) {
+        bool ok = true;
+        for (int i : set) ok &= S[i].nrhs % R == 0;
+        if (!ok) continue;
+        prepare_stages(b, S, set, R);
+        multi_dslash_launch(b->md[0], b->stream);
+        TM_HIP(hipEventRecord(e0, b->stream));
+        multi_dslash_launch(b->md[0], b->stream);
+        multi_dslash_launch(b->md[0], b->stream);
+        TM_HIP(hipEventRecord(e1, b->stream));
+        TM_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        TM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bestR = R;
+        }
+    }
+    TM_HIP(hipEventDestroy(e0));
+    TM_HIP(hipEventDestroy(e1));
+    b->tuned_R[key] = bestR;
+    return bestR;
+}
+
+void build_graph(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set, int iters)
+{
+    drop_graph(b);
+    const int R = choose_R(b, S, set);
+    prepare_stages(b, S, set, R);
+    TM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int k = 0; k < iters; k++) launch_iteration(b, S, set);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(b->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    TM_HIP(hipStreamEndCapture(b->stream, &b->graph));
+    TM_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_set = set;
+    b->graph_iters = iters;
+    b->graph_R = R;
+}
+
+// Run all solvers to completion.
+void run_batch(tm_batch *b, std::vector<Solver> &S)
+{
+    const int K = S[0].check_every;
+    for (auto &x : S) TM_REQUIRE(x.check_every == K && x.lp == S[0].lp, "batched solves share precision and cadence");
+    while (true) {
+        std::vector<int> set;
+        for (int i = 0; i < (int)S.size(); i++)
+            if (!S[i].done) set.push_back(i);
+        if (set.empty()) break;
+        int room = K;
+        for (int i : set) room = std::min(room, S[i].p.maxiter - S[i].total);
+        if (room < K) {
+            // the last iterations before maxiter: single-instance launches
+            for (int i : set) {
+                S[i].iteration(b->stream);
+                S[i].count_iteration();
+                if (S[i].due()) S[i].check(b->stream);
+            }
+            continue;
+        }
+        if (b->graph_set != set || b->graph_iters != K) build_graph(b, S, set, K);
+        TM_HIP(hipGraphLaunch(b->exec, b->stream));
+        for (int i : set) {
+            for (int k = 0; k < K; k++) S[i].count_iteration();
+            S[i].check(b->stream);
+        }
+    }
+    drop_graph(b);
+}
+
+}  // namespace
+
+extern "C" int tm_batch_create(tm_batch **out, tm_ctx *const *ctxs, int n)
+{
+    if (!out || !ctxs || n < 1) return TM_ERR_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n; i++) {
+        if (!ctxs[i]) return TM_ERR_ARG;
+        if (ctxs[i]->device != ctxs[0]->device) return TM_ERR_ARG;
+        for (int j = 0; j < i; j++)
+            if (ctxs[j] == ctxs[i]) return TM_ERR_ARG;  // instances need their own work buffers
+    }
+    tm_batch *b = new (std::nothrow) tm_batch();
+    if (!b) return TM_ERR_OOM;
+    b->ctx.assign(ctxs, ctxs + n);
+    b->device = ctxs[0]->device;
+    int st = bguard(b, [&]() {
+        TM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        for (auto &m : b->md) {
+            m.table_bytes = dslash_multi_table_bytes(n);
+            m.table = nullptr;
+            m.start = nullptr;
+            TM_HIP(hipMalloc(&m.table, m.table_bytes));
+            TM_HIP(hipMalloc((void **)&m.start, sizeof(int) * (n + 1)));
+        }
+        return TM_OK;
+    });
+    if (st != TM_OK) {
+        tm_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return TM_OK;
+}
+
+extern "C" void tm_batch_destroy(tm_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    drop_graph(b);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto &m : b->md) {
+        if (m.table) (void)hipFree(m.table);
+        if (m.start) (void)hipFree(m.start);
+    }
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+extern "C" const char *tm_batch_last_error(const tm_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+extern "C" int tm_batch_solve(tm_batch *b, double *const *x, const double *const *src, const int *nrhs,
+                              const tm_solve_params *p, tm_solve_stats *const *stats, tm_stream stream)
+{
+    return bguard(b, [&]() {
+        const int n = (int)b->ctx.size();
+        TM_REQUIRE(x && src && nrhs && p, "null pointer");
+        for (int i = 0; i < n; i++) {
+            TM_REQUIRE(x[i] && src[i] && x[i] != src[i], "bad solution/source pointer");
+            TM_REQUIRE(nrhs[i] >= 1, "nrhs must be >= 1");
+            TM_REQUIRE(b->ctx[i]->have_gauge, "no gauge field set");
+        }
+        TM_HIP(hipStreamSynchronize((hipStream_t)stream));
+        hipStream_t s = b->stream;
+        const auto t0 = std::chrono::steady_clock::now();
+        std::vector<Solver> S(n);
+        std::vector<void *> xe(n), xo(n);
+        for (int i = 0; i < n; i++) {
+            tm_ctx *c = b->ctx[i];
+            const size_t hb = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * nrhs[i];
+            void *be = ws_get(c, "a_be", hb), *bo = ws_get(c, "a_bo", hb);
+            xe[i] = ws_get(c, "a_xe", hb);
+            xo[i] = ws_get(c, "a_xo", hb);
+            launch_pack(c, be, bo, src[i], nrhs[i], TM_F64, nullptr, s);
+            S[i].init(c, xe[i], xo[i], be, bo, nrhs[i], *p, s);
+        }
+        run_batch(b, S);
+        int status = TM_OK;
+        for (int i = 0; i < n; i++) {
+            SolveOut r = S[i].finalize(s);
+            launch_unpack(b->ctx[i], x[i], xe[i], xo[i], nrhs[i], TM_F64, s);
+            TM_HIP(hipStreamSynchronize(s));
+            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (stats && stats[i])
+                for (int k = 0; k < nrhs[i]; k++) {
+                    stats[i][k] = r.st[k];
+                    stats[i][k].seconds = secs;
+                }
+            if (r.status != TM_OK && status == TM_OK) status = r.status;
+        }
+        if (status == TM_ERR_NOCONV) b->err = "a right-hand side missed the tolerance within maxiter";
+        return status;
+    });
+}
+
+extern "C" int tm_batch_loops(tm_batch *b, const tm_loop_params *p, double *const *loops, tm_loop_stats *stats,
+                              tm_stream stream)
+{
+    return bguard(b, [&]() {
+        const int n = (int)b->ctx.size();
+        TM_REQUIRE(p && loops, "null pointer");
+        for (int i = 0; i < n; i++) {
+            TM_REQUIRE(loops[i], "null loop output");
+            TM_REQUIRE(p[i].n_hp >= 1 && p[i].n_lp == 0, "batched loops take high-precision noises only (n_lp = 0)");
+            TM_REQUIRE(p[i].estimators > 0 && p[i].estimators < 8, "bad estimator mask");
+            TM_REQUIRE(p[i].dilution == TM_DIL_NONE || p[i].dilution == TM_DIL_SPIN_COLOUR, "bad dilution");
+            TM_REQUIRE(p[i].mu_sign == 1 || p[i].mu_sign == -1, "mu_sign must be +1 or -1");
+            TM_REQUIRE(p[i].noise_offset >= 0, "noise_offset must be >= 0");
+            TM_REQUIRE(b->ctx[i]->have_gauge, "no gauge field set");
+            if (p[i].estimators & TM_EST_HPE)
+                for (int mu = 0; mu < 4; mu++) TM_REQUIRE(b->ctx[i]->geo.L[mu] >= 4, "HPE needs every L_mu >= 4");
+        }
+        TM_HIP(hipStreamSynchronize((hipStream_t)stream));
+        hipStream_t s = b->stream;
+        const auto t0 = std::chrono::steady_clock::now();
+        std::vector<Solver> S(n);
+        std::vector<int> per_noise(n), nr(n);
+        std::vector<void *> ee(n), eo(n), se(n), so(n);
+        for (int i = 0; i < n; i++) {
+            tm_ctx *c = b->ctx[i];
+            c->stream = s;
+            per_noise[i] = p[i].dilution == TM_DIL_SPIN_COLOUR ? 12 : 1;
+            nr[i] = per_noise[i] * p[i].n_hp;
+            const size_t one = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * per_noise[i];
+            ee[i] = ws_get(c, "b_eta_e", one * p[i].n_hp);
+            eo[i] = ws_get(c, "b_eta_o", one * p[i].n_hp);
+            se[i] = ws_get(c, "b_s_e", one * p[i].n_hp);
+            so[i] = ws_get(c, "b_s_o", one * p[i].n_hp);
+            for (int k = 0; k < p[i].n_hp; k++)
+                launch_noise(c, (char *)ee[i] + one * k, (char *)eo[i] + one * k, p[i].seed,
+                             (long)p[i].noise_offset + k, p[i].dilution, s);
+            tm_solve_params hp = p[i].hp;
+            hp.mu_sign = p[i].mu_sign;
+            S[i].init(c, se[i], so[i], ee[i], eo[i], nr[i], hp, s);
+        }
+        run_batch(b, S);
+        int status = TM_OK;
+        for (int i = 0; i < n; i++) {
+            tm_ctx *c = b->ctx[i];
+            SolveOut r = S[i].finalize(s);
+            if (r.status != TM_OK && status == TM_OK) status = r.status;
+            const int Lt = c->geo.L[3];
+            const size_t per = (size_t)16 * Lt;
+            int n_est = 0;
+            for (int k = 0; k < 3; k++) n_est += (p[i].estimators >> k) & 1;
+            const double epsp = eps_of(c, p[i].mu_sign);
+            const size_t one = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * per_noise[i];
+            std::vector<cx<double>> acc(n_est * per, cx<double>{0, 0}), one_loop(n_est * per);
+            for (int k = 0; k < p[i].n_hp; k++) {
+                contract_noise(c, p[i].estimators, (char *)ee[i] + one * k, (char *)eo[i] + one * k,
+                               (char *)se[i] + one * k, (char *)so[i] + one * k, per_noise[i], epsp, one_loop.data());
+                for (size_t j = 0; j < acc.size(); j++) acc[j] = acc[j] + one_loop[j];
+            }
+            std::vector<cx<double>> ex(per);
+            if (p[i].estimators & TM_EST_HPE) hpe_exact_part(c, epsp, ex.data());
+            cx<double> *dst = (cx<double> *)loops[i];
+            for (int k = 0; k < n_est; k++) {
+                const bool hpe = k == n_est - 1 && (p[i].estimators & TM_EST_HPE);
+                for (size_t j = 0; j < per; j++)
+                    dst[k * per + j] = (1.0 / p[i].n_hp) * acc[k * per + j] + (hpe ? ex[j] : cx<double>{0, 0});
+            }
+            if (stats) {
+                tm_loop_stats &q = stats[i];
+                q = tm_loop_stats{};
+                for (auto &x : r.st) {
+                    q.n_solves_hp++;
+                    q.iters_hp += x.iters;
+                    q.max_res_hp = std::max(q.max_res_hp, x.true_rel_res);
+                }
+                q.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            }
+        }
+        TM_HIP(hipStreamSynchronize(s));
+        if (status == TM_ERR_NOCONV) b->err = "a high-precision solve missed its tolerance";
+        return status;
+    });
+}

@@ -169,6 +169,11 @@ typedef unsigned v2u __attribute__((__vector_size__(2 * sizeof(unsigned))));
 typedef unsigned v4u __attribute__((__vector_size__(4 * sizeof(unsigned))));
 // descriptor word 3 for raw (untyped) access on gfx9-class parts
 constexpr int kRsrcFlags = 0x00020000;
+// cache-policy operand: non-temporal (streaming) hint for data that is not
+// re-read by this launch (outputs) or only by the adjacent right-hand-side
+// groups of the same site block (links), so it does not displace the
+// neighbour spinors in L2
+constexpr int kNT = 2;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, size_t bytes)
 {
@@ -205,6 +210,12 @@ struct BufIO<double2> {
         D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
         return {(T)v.x, (T)v.y};
     }
+    template <typename T>
+    __device__ __forceinline__ static cx<T> ldlink(rsrc_t r, int voff, int soff)
+    {
+        D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kNT));
+        return {(T)v.x, (T)v.y};
+    }
     __device__ __forceinline__ static rawc<double> ldraw(rsrc_t r, int voff, int soff)
     {
         D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
@@ -214,7 +225,7 @@ struct BufIO<double2> {
     __device__ __forceinline__ static void st(rsrc_t r, int voff, int soff, cx<T> c)
     {
         D2 v{(double)c.r, (double)c.i};
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, voff, soff, kNT);
     }
 };
 template <>
@@ -223,6 +234,12 @@ struct BufIO<float2> {
     __device__ __forceinline__ static cx<T> ld(rsrc_t r, int voff, int soff)
     {
         F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return {(T)v.x, (T)v.y};
+    }
+    template <typename T>
+    __device__ __forceinline__ static cx<T> ldlink(rsrc_t r, int voff, int soff)
+    {
+        F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNT));
         return {(T)v.x, (T)v.y};
     }
     __device__ __forceinline__ static rawc<float> ldraw(rsrc_t r, int voff, int soff)
@@ -234,7 +251,7 @@ struct BufIO<float2> {
     __device__ __forceinline__ static void st(rsrc_t r, int voff, int soff, cx<T> c)
     {
         F2 v{(float)c.r, (float)c.i};
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, kNT);
     }
 };
 template <>
@@ -257,7 +274,7 @@ struct BufIO<h2> {
         h2 h;
         h.x = (_Float16)(float)c.r;
         h.y = (_Float16)(float)c.i;
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, voff, soff, kNT);
     }
 };
 template <>
@@ -277,7 +294,7 @@ struct BufIO<b2> {
     __device__ __forceinline__ static void st(rsrc_t r, int voff, int soff, cx<T> c)
     {
         unsigned v = (unsigned)f32_to_bf16((float)c.r) | ((unsigned)f32_to_bf16((float)c.i) << 16);
-        __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, kNT);
     }
 };
 
@@ -285,7 +302,7 @@ template <typename LS, typename T>
 __device__ __forceinline__ void load_link(cx<T> W[9], rsrc_t lr, int vbytes, int voff)
 {
 #pragma unroll
-    for (int k = 0; k < 9; k++) W[k] = BufIO<LS>::template ld<T>(lr, voff, k * vbytes);
+    for (int k = 0; k < 9; k++) W[k] = BufIO<LS>::template ldlink<T>(lr, voff, k * vbytes);
 }
 
 template <typename SS>
@@ -351,11 +368,14 @@ __device__ __forceinline__ double norm2c(cx<T> v)
 enum { EPI_STORE = 0, EPI_NORM = 1, EPI_CG = 2 };
 
 // Block order: see map_block.
+// One block of the launch: bhw is the block's index within its instance's
+// range of nhw blocks (that range starts at a multiple of 8, so bhw % 8 is
+// still the XCD).
 template <typename SS, typename LS, typename T, int R, int DAG, int OWN, int EPI>
-__global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash(DParams<T> a)
+__device__ __forceinline__ void dslash_block(const DParams<T> &a, int bhw, int nhw)
 {
     int grp;
-    const int sblk = map_block(blockIdx.x, gridDim.x, a.ngroups, a.nb_t, grp);
+    const int sblk = map_block(bhw, nhw, a.ngroups, a.nb_t, grp);
     const int r0 = grp * R;
     const int i_raw = sblk * kBlock + threadIdx.x;
     const bool valid = i_raw < a.g.vh;
@@ -461,6 +481,26 @@ __global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash(DParams<
     }
 }
 
+template <typename SS, typename LS, typename T, int R, int DAG, int OWN, int EPI>
+__global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash(DParams<T> a)
+{
+    dslash_block<SS, LS, T, R, DAG, OWN, EPI>(a, blockIdx.x, gridDim.x);
+}
+
+// Several lattices in one launch: instance i owns hardware blocks
+// [start[i], start[i+1]) (padded to multiples of 8; padding blocks exit).
+template <typename SS, typename LS, typename T, int R, int DAG, int OWN, int EPI>
+__global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash_multi(const DParams<T> *P, const int *start,
+                                                                             int n)
+{
+    int i = 0;
+    while (i + 1 < n && (int)blockIdx.x >= start[i + 1]) i++;
+    const int local = (int)blockIdx.x - start[i];
+    const int nreal = P[i].nblk * P[i].ngroups;
+    if (local >= nreal) return;
+    dslash_block<SS, LS, T, R, DAG, OWN, EPI>(P[i], local, nreal);
+}
+
 template <typename T>
 cx<T> cvt(cx<double> v)
 {
@@ -483,7 +523,7 @@ void launch_epi(const DslashCall &dc, dim3 grid, hipStream_t s, const DParams<T>
 }
 
 template <typename SS, typename LS, typename T, int R>
-void launch_t(tm_ctx *c, const DslashCall &dc, hipStream_t s)
+DParams<T> fill_params(tm_ctx *c, const DslashCall &dc)
 {
     DParams<T> a;
     a.out = dc.out;
@@ -505,6 +545,13 @@ void launch_t(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     a.part = dc.part;
     a.nblk = dslash_site_blocks(c);
     a.nb_t = (c->geo.vsh % kBlock == 0 && (c->geo.vsh / kBlock) % 8 == 0) ? c->geo.vsh / kBlock : 0;
+    return a;
+}
+
+template <typename SS, typename LS, typename T, int R>
+void launch_t(tm_ctx *c, const DslashCall &dc, hipStream_t s)
+{
+    const DParams<T> a = fill_params<SS, LS, T, R>(c, dc);
     dim3 grid((unsigned)(a.nblk * a.ngroups));
     // separate kernels per projector placement and per presence of the
     // own-site term (the x - H y forms read one more field)
@@ -589,7 +636,101 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     }
 }
 
+template <typename SS, typename LS, typename T, int R>
+void multi_fill(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, hipStream_t s)
+{
+    std::vector<DParams<T>> tab;
+    std::vector<int> start(1, 0);
+    for (size_t k = 0; k < cs.size(); k++) {
+        TM_REQUIRE(dcs[k].nrhs % R == 0, "RHS tile must divide every instance's nrhs");
+        tab.push_back(fill_params<SS, LS, T, R>(cs[k], dcs[k]));
+        const int nb = tab.back().nblk * tab.back().ngroups;
+        start.push_back(start.back() + (nb + 7) / 8 * 8);
+    }
+    TM_REQUIRE(m.table_bytes >= tab.size() * sizeof(DParams<T>), "multi-instance table too small");
+    TM_HIP(hipMemcpyAsync(m.table, tab.data(), tab.size() * sizeof(DParams<T>), hipMemcpyHostToDevice, s));
+    TM_HIP(hipMemcpyAsync(m.start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    TM_HIP(hipStreamSynchronize(s));
+    m.grid = start.back();
+}
+
+template <typename SS, typename LS, typename T, int R>
+void multi_go(const MultiDslash &m, hipStream_t s)
+{
+    const DParams<T> *P = (const DParams<T> *)m.table;
+    dim3 g(m.grid), b(kBlock);
+    // the four stage forms of a CG iteration on the Schur normal equations
+    if (m.dag == 0 && m.own == 0 && m.epi == EPI_STORE)
+        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 0, EPI_STORE>), g, b, 0, s, P, m.start, m.n);
+    else if (m.dag == 1 && m.own == 0 && m.epi == EPI_STORE)
+        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 1, 0, EPI_STORE>), g, b, 0, s, P, m.start, m.n);
+    else if (m.dag == 0 && m.own == 1 && m.epi == EPI_NORM)
+        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 1, EPI_NORM>), g, b, 0, s, P, m.start, m.n);
+    else if (m.dag == 0 && m.own == 1 && m.epi == EPI_CG)
+        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 1, EPI_CG>), g, b, 0, s, P, m.start, m.n);
+    else
+        throw TmError{TM_ERR_UNSUPPORTED, "multi-instance Dslash form not instantiated"};
+    TM_HIP(hipGetLastError());
+}
+
+template <typename F>
+void multi_dispatch(int prec, int R, F &&f)
+{
+    auto byR = [&](auto *tag) {
+        using P3 = std::remove_pointer_t<decltype(tag)>;
+        if constexpr (std::is_same<typename P3::T, double>::value) {
+            TM_REQUIRE(R == 1, "FP64 uses one right-hand side per thread");
+            f.template operator()<typename P3::SS, typename P3::LS, typename P3::T, 1>();
+        } else {
+            if (R == 3)
+                f.template operator()<typename P3::SS, typename P3::LS, typename P3::T, 3>();
+            else if (R == 2)
+                f.template operator()<typename P3::SS, typename P3::LS, typename P3::T, 2>();
+            else
+                f.template operator()<typename P3::SS, typename P3::LS, typename P3::T, 1>();
+        }
+    };
+    struct PD { using SS = double2; using LS = double2; using T = double; };
+    struct PF { using SS = float2; using LS = float2; using T = float; };
+    struct PH { using SS = h2; using LS = float2; using T = float; };
+    struct PB { using SS = b2; using LS = float2; using T = float; };
+    switch (prec) {
+    case TM_F64: byR((PD *)nullptr); break;
+    case TM_F32: byR((PF *)nullptr); break;
+    case TM_F16: byR((PH *)nullptr); break;
+    case TM_BF16: byR((PB *)nullptr); break;
+    default: throw TmError{TM_ERR_ARG, "bad precision"};
+    }
+}
+
 }  // namespace
+
+size_t dslash_multi_table_bytes(int n) { return (size_t)n * sizeof(DParams<double>); }
+
+void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, int R,
+                          hipStream_t s)
+{
+    TM_REQUIRE(!cs.empty() && cs.size() == dcs.size(), "bad multi-instance call");
+    m.prec = dcs[0].spinor_prec;
+    m.dag = dcs[0].dag;
+    m.own = dcs[0].has_own ? 1 : 0;
+    m.epi = dcs[0].epi;
+    m.R = R;
+    m.n = (int)cs.size();
+    for (size_t k = 0; k < cs.size(); k++) {
+        TM_REQUIRE(dcs[k].spinor_prec == m.prec && dcs[k].dag == m.dag && (dcs[k].has_own ? 1 : 0) == m.own &&
+                       dcs[k].epi == m.epi,
+                   "multi-instance calls must share precision and operator form");
+        TM_REQUIRE(cs[k]->have_gauge, "no gauge field set");
+        if (m.prec != TM_F64) ensure_links32(cs[k], s);
+    }
+    multi_dispatch(m.prec, R, [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs, s); });
+}
+
+void multi_dslash_launch(const MultiDslash &m, hipStream_t s)
+{
+    multi_dispatch(m.prec, m.R, [&]<typename SS, typename LS, typename T, int RR>() { multi_go<SS, LS, T, RR>(m, s); });
+}
 
 int dslash_site_blocks(tm_ctx *c) { return (c->geo.vh + kBlock - 1) / kBlock; }
 

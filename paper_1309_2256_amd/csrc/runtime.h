@@ -23,6 +23,49 @@ struct SolveOut {
     int status = TM_OK;
 };
 
+// CG work vectors of one solve (see runtime.hip)
+struct CGWork {
+    int nrhs = 0, prec = 0;
+    void *q = nullptr, *p = nullptr, *r = nullptr, *rho = nullptr, *tmp = nullptr;
+    void *x = nullptr;  // solution accumulator: FP64 (plain) or FP32 (low precision)
+    int xprec = 0;
+    CGScalars *dsc = nullptr;
+    double *partq = nullptr, *partb = nullptr;
+};
+
+// State of one solve of M x = b on FP64 half fields: init, then iterations
+// (each followed by count_iteration, and check when due), then finalize.
+// The batched driver runs several of these with shared launches.
+struct Solver {
+    tm_ctx *c = nullptr;
+    tm_solve_params p{};
+    int nrhs = 0, lp = 0, check_every = 8, nsb = 0, total = 0, since_check = 0;
+    bool done = false;
+    double delta = 0, epsp = 0, t0 = 0;
+    void *xe = nullptr, *xo = nullptr;
+    const void *be = nullptr, *bo = nullptr;
+    void *bh = nullptr, *t64 = nullptr, *rho64 = nullptr, *r64 = nullptr, *q64 = nullptr;
+    double *dscale = nullptr;
+    CGWork w{};
+    std::vector<double> bn2, sigma, iter_res;
+    std::vector<int> n_rel;
+    std::vector<CGScalars> hsc;
+
+    void init(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs, const tm_solve_params &p,
+              hipStream_t s);
+    void iteration(hipStream_t s);       // one iteration, single-instance launches
+    DslashCall stage(int k) const;       // the k-th (1..4) half-Dslash of an iteration
+    void iteration_tail(hipStream_t s);  // finish_beta + x/p update
+    void count_iteration();
+    bool due() const;
+    void check(hipStream_t s);
+    SolveOut finalize(hipStream_t s);
+
+  private:
+    void restart(bool first, hipStream_t s);
+    void accumulate(hipStream_t s);
+};
+
 // Solve M(mu_sign) x = b with b, x given as FP64 half fields (even, odd).
 SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,
                       const tm_solve_params &p, hipStream_t s);
@@ -37,6 +80,12 @@ void loops_from_outer(tm_ctx *c, const std::vector<cx<double>> &C, bool g5pre, c
                       cx<double> *out);
 // exactly known part of the hopping expansion for ultra-local insertions
 void hpe_exact_part(tm_ctx *c, double epsp, cx<double> *out /* [16][Lt] */);
+
+// per-noise loops of one noise vector's sources (ee, eo) and solutions (se,
+// so), estimators in mask order, into dst [n_est][16][Lt]; uses c->stream
+void contract_noise(tm_ctx *c, int estimators, const void *ee, const void *eo, const void *se, const void *so,
+                    int nrhs, double epsp, cx<double> *dst);
+hipStream_t s_of(tm_ctx *c);
 
 int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noise, tm_loop_stats *stats,
               hipStream_t s);

@@ -78,6 +78,8 @@ void gamma_n(int n, cx<double> G[4][4])
 
 }  // namespace
 
+hipStream_t s_of(tm_ctx *c) { return c->stream; }
+
 double eps_of(tm_ctx *c, int mu_sign) { return mu_sign >= 0 ? c->eps : -c->eps; }
 
 void op_dslash(tm_ctx *c, void *out, const void *in, const void *own, int nrhs, int prec, int out_par, int dag,
@@ -133,120 +135,97 @@ void op_bh_power(tm_ctx *c, void *se, void *so, int nrhs, double epsp, int kpow,
 
 namespace {
 
-struct CGWork {
-    int nrhs, prec, nblk;
-    void *q, *sv, *p, *r, *rho, *tmp;
-    void *x;  // solution accumulator: FP64 (plain) or FP32 (low precision)
-    int xprec;
-    CGScalars *dsc;
-    double *partq, *partb;
-};
-
-// Run CG iterations until every right-hand side is inactive, maxiter is
-// reached, or (reliable-update mode) some right-hand side asks for an update.
-// Returns the iteration count of this call.
-int cg_iterate(tm_ctx *c, CGWork &w, double epsp, double delta, int maxiter, int check_every,
-               std::vector<CGScalars> &hsc, hipStream_t s, bool &stop_update)
+// One CG iteration on the Schur normal equations for one instance, as four
+// half-Dslash launches with fused epilogues plus three small kernels:
+//   t = R^-1 H p;  q = R p - H t   (+ partial |q|^2)          D1, D2
+//   alpha = rr / |q|^2                                          finish
+//   t = R^-1(-eps) g5 H^dag q;  s = R(-eps) q + kappa g5 H t,  D3, D4
+//     r -= alpha s, rho -= alpha q (+ partial |r|^2, |rho|^2)
+//   beta, convergence / update flags                            finish
+//   x += alpha p, p = r + beta p                                update
+DslashCall stage_call(tm_ctx *c, const CGWork &w, double epsp, int stage)
 {
     const double k = c->kappa;
-    const int nsb = dslash_site_blocks(c);
-    int it = 0;
-    stop_update = false;
-    while (it < maxiter) {
-        // q = Ahat p  (second half also forms the partial |q|^2)
-        op_dslash(c, w.tmp, w.p, nullptr, w.nrhs, w.prec, 1, 0, sd_mul(sd_scalar(-k), sd_twist_inv(epsp)),
-                  sd_scalar(0), s);
-        {
-            DslashCall dc{};
-            dc.out = w.q;
-            dc.in = w.tmp;
-            dc.own = w.p;
-            dc.nrhs = w.nrhs;
-            dc.out_parity = 0;
-            dc.dag = 0;
-            dc.spinor_prec = w.prec;
-            dc.d_own = sd_twist(epsp);
-            dc.d_hop = sd_scalar(k);
-            dc.has_own = true;
-            dc.epi = 1;
-            dc.part = w.partq;
-            launch_dslash(c, dc, s);
-        }
-        cg_finish_alpha(c, w.dsc, w.partq, nsb, w.nrhs, s);
-        // s = Ahat^dag q fused with r -= alpha s, rho -= alpha q and their norms
-        op_dslash(c, w.tmp, w.q, nullptr, w.nrhs, w.prec, 1, 1,
-                  sd_mul(sd_scalar(-k), sd_mul(sd_twist_inv(-epsp), sd_gamma5())), sd_scalar(0), s);
-        {
-            DslashCall dc{};
-            dc.out = nullptr;
-            dc.in = w.tmp;
-            dc.own = w.q;
-            dc.nrhs = w.nrhs;
-            dc.out_parity = 0;
-            dc.dag = 0;
-            dc.spinor_prec = w.prec;
-            dc.d_own = sd_twist(-epsp);
-            dc.d_hop = sd_mul(sd_scalar(k), sd_gamma5());
-            dc.has_own = true;
-            dc.epi = 2;
-            dc.r = w.r;
-            dc.rho = w.rho;
-            dc.sc = w.dsc;
-            dc.part = w.partb;
-            launch_dslash(c, dc, s);
-        }
-        cg_finish_beta(c, w.dsc, w.partb, nsb, w.nrhs, delta, s);
-        cg_update_px(c, w.p, w.r, w.x, w.prec, w.xprec, w.nrhs, w.dsc, s);
-        it++;
-        if (it % check_every == 0 || it == maxiter) {
-            download(c, hsc.data(), w.dsc, sizeof(CGScalars) * w.nrhs, s);
-            bool any_active = false, any_update = false, any_bad = false;
-            for (auto &q : hsc) {
-                any_active |= q.active != 0;
-                any_update |= (q.active && q.want_update);
-                any_bad |= q.bad != 0;
-            }
-            if (any_bad) throw TmError{TM_ERR_NAN, "NaN/Inf in a solver reduction"};
-            if (!any_active) break;
-            if (any_update) {
-                stop_update = true;
-                break;
-            }
-        }
+    DslashCall dc{};
+    dc.nrhs = w.nrhs;
+    dc.spinor_prec = w.prec;
+    switch (stage) {
+    case 1:
+        dc.out = w.tmp;
+        dc.in = w.p;
+        dc.out_parity = 1;
+        dc.d_hop = sd_mul(sd_scalar(-k), sd_twist_inv(epsp));
+        dc.d_own = sd_scalar(0);
+        break;
+    case 2:
+        dc.out = w.q;
+        dc.in = w.tmp;
+        dc.own = w.p;
+        dc.has_own = true;
+        dc.d_own = sd_twist(epsp);
+        dc.d_hop = sd_scalar(k);
+        dc.epi = 1;
+        dc.part = w.partq;
+        break;
+    case 3:
+        dc.out = w.tmp;
+        dc.in = w.q;
+        dc.out_parity = 1;
+        dc.dag = 1;
+        dc.d_hop = sd_mul(sd_scalar(-k), sd_mul(sd_twist_inv(-epsp), sd_gamma5()));
+        dc.d_own = sd_scalar(0);
+        break;
+    default:
+        dc.in = w.tmp;
+        dc.own = w.q;
+        dc.has_own = true;
+        dc.d_own = sd_twist(-epsp);
+        dc.d_hop = sd_mul(sd_scalar(k), sd_gamma5());
+        dc.epi = 2;
+        dc.r = w.r;
+        dc.rho = w.rho;
+        dc.sc = w.dsc;
+        dc.part = w.partb;
+        break;
     }
-    return it;
+    return dc;
 }
 
 }  // namespace
 
-SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,
-                      const tm_solve_params &p, hipStream_t s)
+void Solver::init(tm_ctx *ctx, void *xe_, void *xo_, const void *be_, const void *bo_, int nrhs_,
+                  const tm_solve_params &par, hipStream_t s)
 {
-    const double t0 = now_s();
+    t0 = now_s();
+    c = ctx;
+    xe = xe_;
+    xo = xo_;
+    be = be_;
+    bo = bo_;
+    nrhs = nrhs_;
+    p = par;
     TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     TM_REQUIRE(p.tol > 0 && std::isfinite(p.tol), "tol must be > 0");
     TM_REQUIRE(p.maxiter > 0, "maxiter must be > 0");
     TM_REQUIRE(p.solver >= TM_CG_F64 && p.solver <= TM_CG_LOW, "unknown solver");
     TM_REQUIRE(p.mu_sign == 1 || p.mu_sign == -1, "mu_sign must be +1 or -1");
-    const int low_prec = p.solver == TM_CG_F64 ? TM_F64 : p.inner_prec;
-    TM_REQUIRE(low_prec == TM_F64 || low_prec == TM_F32 || low_prec == TM_F16 || low_prec == TM_BF16,
-               "bad inner precision");
-    TM_REQUIRE(p.solver == TM_CG_F64 || low_prec != TM_F64, "MIXED/LOW need a FP32/FP16/BF16 inner precision");
-    const int check_every = p.check_every > 0 ? p.check_every : 8;
-    const double delta = p.solver == TM_CG_MIXED ? (p.delta > 0 ? p.delta : 0.1) : 0.0;
-    const double epsp = eps_of(c, p.mu_sign);
-    const double kap = c->kappa;
-    const int nblk = reduce_blocks(c);
+    lp = p.solver == TM_CG_F64 ? TM_F64 : p.inner_prec;
+    TM_REQUIRE(lp == TM_F64 || lp == TM_F32 || lp == TM_F16 || lp == TM_BF16, "bad inner precision");
+    TM_REQUIRE(p.solver == TM_CG_F64 || lp != TM_F64, "MIXED/LOW need a FP32/FP16/BF16 inner precision");
+    check_every = p.check_every > 0 ? p.check_every : 8;
+    delta = p.solver == TM_CG_MIXED ? (p.delta > 0 ? p.delta : 0.1) : 0.0;
+    epsp = eps_of(c, p.mu_sign);
+    nsb = dslash_site_blocks(c);
+    total = since_check = 0;
+    done = false;
     const size_t f64 = field_bytes(c, TM_F64, nrhs);
+    bh = ws_get(c, "s_bh", f64);
+    t64 = ws_get(c, "s_t64", f64);
+    rho64 = ws_get(c, "s_rho64", f64);
+    r64 = ws_get(c, "s_r64", f64);
+    q64 = ws_get(c, "s_q64", f64);
 
-    void *bh = ws_get(c, "s_bh", f64);
-    void *t64 = ws_get(c, "s_t64", f64);
-    void *rho64 = ws_get(c, "s_rho64", f64);
-    void *r64 = ws_get(c, "s_r64", f64);
-    void *q64 = ws_get(c, "s_q64", f64);
-
-    // |b|^2 over the full lattice
-    std::vector<double> bn2 = norms_host(c, be, TM_F64, nrhs, s);
+    bn2 = norms_host(c, be, TM_F64, nrhs, s);
     {
         std::vector<double> bo2 = norms_host(c, bo, TM_F64, nrhs, s);
         for (int r = 0; r < nrhs; r++) bn2[r] += bo2[r];
@@ -256,20 +235,22 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
 
     // bhat_e = b_e - H_eo R_oo^-1 b_o
     launch_spin_diag(c, t64, bo, TM_F64, nrhs, sd_twist_inv(epsp), s);
-    op_dslash(c, bh, t64, be, nrhs, TM_F64, 0, 0, sd_scalar(kap), sd_scalar(1.0), s);
+    op_dslash(c, bh, t64, be, nrhs, TM_F64, 0, 0, sd_scalar(c->kappa), sd_scalar(1.0), s);
 
-    SolveOut out;
-    out.st.assign(nrhs, tm_solve_stats{});
-    std::vector<CGScalars> hsc(nrhs);
-    std::vector<int> n_rel(nrhs, 0);
-    std::vector<double> iter_res(nrhs, 0.0);
-    CGScalars *dsc = (CGScalars *)ws_get(c, "s_sc", sizeof(CGScalars) * nrhs);
-    const int nsb = dslash_site_blocks(c);
-    double *partq = (double *)ws_get(c, "s_partq", sizeof(double) * nsb * nrhs);
-    double *partb = (double *)ws_get(c, "s_partb", sizeof(double) * nsb * nrhs * 2);
-
-    if (p.solver == TM_CG_F64) {
-        CGWork w{nrhs, TM_F64, nblk};
+    hsc.assign(nrhs, CGScalars{});
+    n_rel.assign(nrhs, 0);
+    iter_res.assign(nrhs, 0.0);
+    sigma.assign(nrhs, 1.0);
+    w = CGWork{};
+    w.nrhs = nrhs;
+    w.prec = lp;
+    w.dsc = (CGScalars *)ws_get(c, "s_sc", sizeof(CGScalars) * nrhs);
+    w.partq = (double *)ws_get(c, "s_partq", sizeof(double) * nsb * nrhs);
+    w.partb = (double *)ws_get(c, "s_partb", sizeof(double) * nsb * nrhs * 2);
+    dscale = (double *)ws_get(c, "s_scale", sizeof(double) * nrhs);
+    launch_zero(c, xe, TM_F64, nrhs, s);
+    copy_field(rho64, bh, f64, s);
+    if (lp == TM_F64) {
         w.x = xe;
         w.xprec = TM_F64;
         w.rho = rho64;
@@ -277,130 +258,166 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
         w.q = q64;
         w.tmp = t64;
         w.p = ws_get(c, "s_p64", f64);
-        w.sv = ws_get(c, "s_s64", f64);
-        w.dsc = dsc;
-        w.partq = partq;
-        w.partb = partb;
-        launch_zero(c, xe, TM_F64, nrhs, s);
-        copy_field(rho64, bh, f64, s);
         op_schur_dag(c, r64, rho64, t64, nrhs, TM_F64, epsp, s);
         copy_field(w.p, r64, f64, s);
         std::vector<double> rr = norms_host(c, r64, TM_F64, nrhs, s);
         std::vector<double> rho2 = norms_host(c, rho64, TM_F64, nrhs, s);
         for (int r = 0; r < nrhs; r++) {
             CGScalars &q = hsc[r];
-            memset(&q, 0, sizeof(q));
             q.rr = rr[r];
             q.rho2 = rho2[r];
             q.rho2_ref = rho2[r];
             q.target2 = p.tol * p.tol * bn2[r];
             q.sigma = 1.0;
             q.active = rho2[r] > q.target2 ? 1 : 0;
+            iter_res[r] = std::sqrt(rho2[r] / bn2[r]);
         }
-        upload(dsc, hsc.data(), sizeof(CGScalars) * nrhs, s);
-        bool upd;
-        cg_iterate(c, w, epsp, 0.0, p.maxiter, check_every, hsc, s, upd);
-        download(c, hsc.data(), dsc, sizeof(CGScalars) * nrhs, s);
-        for (int r = 0; r < nrhs; r++) iter_res[r] = std::sqrt(hsc[r].rho2 / bn2[r]);
+        upload(w.dsc, hsc.data(), sizeof(CGScalars) * nrhs, s);
     } else {
-        // low-precision CG on vectors scaled to unit RMS per element; FP64
-        // solution, residual and (MIXED) reliable updates
-        const int lp = low_prec;
+        // low-precision vectors scaled to unit RMS per element
         const size_t fl = field_bytes(c, lp, nrhs);
-        CGWork w{nrhs, lp, nblk};
         w.x = ws_get(c, "s_y32", field_bytes(c, TM_F32, nrhs));
         w.xprec = TM_F32;
         w.rho = ws_get(c, "s_rho_lo", fl);
         w.r = ws_get(c, "s_r_lo", fl);
         w.q = ws_get(c, "s_q_lo", fl);
         w.p = ws_get(c, "s_p_lo", fl);
-        w.sv = ws_get(c, "s_s_lo", fl);
         w.tmp = ws_get(c, "s_t_lo", fl);
-        w.dsc = dsc;
-        w.partq = partq;
-        w.partb = partb;
-        double *dscale = (double *)ws_get(c, "s_scale", sizeof(double) * nrhs);
-        const double nel = 12.0 * c->geo.vh;
-        std::vector<double> sigma(nrhs, 1.0), hscale(nrhs);
-
-        launch_zero(c, xe, TM_F64, nrhs, s);
-        copy_field(rho64, bh, f64, s);
-        // (re)start from the FP64 residual rho64 = bhat - Ahat x: r = Ahat^dag rho
-        auto restart = [&](bool first) {
-            op_schur_dag(c, r64, rho64, t64, nrhs, TM_F64, epsp, s);
-            std::vector<double> nr = norms_host(c, r64, TM_F64, nrhs, s);
-            std::vector<double> nrho = norms_host(c, rho64, TM_F64, nrhs, s);
-            std::vector<double> sig_new(nrhs);
-            for (int r = 0; r < nrhs; r++) {
-                sig_new[r] = nr[r] > 0 ? std::sqrt(nel / nr[r]) : 1.0;
-                if (!std::isfinite(sig_new[r])) sig_new[r] = 1.0;
-            }
-            if (!first) {
-                for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r] / sigma[r];
-                upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
-                launch_copy_convert(c, w.p, lp, w.p, lp, nrhs, dscale, s);
-            }
-            for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r];
-            upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
-            launch_copy_convert(c, w.r, lp, r64, TM_F64, nrhs, dscale, s);
-            launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
-            if (first) copy_field(w.p, w.r, fl, s);
-            launch_zero(c, w.x, TM_F32, nrhs, s);
-            std::vector<double> rr = norms_host(c, w.r, lp, nrhs, s);
-            std::vector<double> rho2 = norms_host(c, w.rho, lp, nrhs, s);
-            if (!first) download(c, hsc.data(), dsc, sizeof(CGScalars) * nrhs, s);
-            for (int r = 0; r < nrhs; r++) {
-                CGScalars &q = hsc[r];
-                if (first) {
-                    memset(&q, 0, sizeof(q));
-                    q.active = 1;
-                }
-                q.rr = rr[r];
-                q.rho2 = rho2[r];
-                q.rho2_ref = rho2[r];
-                q.target2 = p.tol * p.tol * bn2[r] * sig_new[r] * sig_new[r];
-                q.sigma = sig_new[r];
-                q.want_update = 0;
-                // converged on the true FP64 residual
-                if (nrho[r] <= p.tol * p.tol * bn2[r]) q.active = 0;
-                iter_res[r] = std::sqrt(nrho[r] / bn2[r]);
-            }
-            sigma = sig_new;
-            upload(dsc, hsc.data(), sizeof(CGScalars) * nrhs, s);
-        };
-        // x_hi += y / sigma
-        auto accumulate = [&]() {
-            for (int r = 0; r < nrhs; r++) hscale[r] = 1.0 / sigma[r];
-            upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
-            launch_axpy_dev(c, xe, TM_F64, w.x, TM_F32, nrhs, dscale, s);
-        };
-        restart(true);
-        int total = 0;
-        while (total < p.maxiter) {
-            bool upd = false;
-            int done = cg_iterate(c, w, epsp, delta, p.maxiter - total, check_every, hsc, s, upd);
-            total += done;
-            accumulate();
-            if (p.solver == TM_CG_LOW) {
-                for (int r = 0; r < nrhs; r++) iter_res[r] = std::sqrt(hsc[r].rho2 / bn2[r]) / hsc[r].sigma;
-                break;
-            }
-            // reliable update: FP64 true residual of the accumulated solution
-            op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s);
-            copy_field(rho64, bh, f64, s);
-            launch_axpby_host(c, rho64, q64, TM_F64, nrhs, -1.0, 1.0, s);
-            for (int r = 0; r < nrhs; r++)
-                if (hsc[r].active) n_rel[r]++;
-            restart(false);
-            bool any = false;
-            for (auto &q : hsc) any |= q.active != 0;
-            if (!any) break;
-        }
+        restart(true, s);
     }
+    bool any = false;
+    for (auto &q : hsc) any |= q.active != 0;
+    done = !any;
+}
 
+// (re)start the low-precision iteration from the FP64 residual rho64:
+// r = Ahat^dag rho, new per-RHS scales, p rescaled (kept otherwise)
+void Solver::restart(bool first, hipStream_t s)
+{
+    const double nel = 12.0 * c->geo.vh;
+    const size_t fl = field_bytes(c, lp, nrhs);
+    std::vector<double> hscale(nrhs);
+    op_schur_dag(c, r64, rho64, t64, nrhs, TM_F64, epsp, s);
+    std::vector<double> nr = norms_host(c, r64, TM_F64, nrhs, s);
+    std::vector<double> nrho = norms_host(c, rho64, TM_F64, nrhs, s);
+    std::vector<double> sig_new(nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        sig_new[r] = nr[r] > 0 ? std::sqrt(nel / nr[r]) : 1.0;
+        if (!std::isfinite(sig_new[r])) sig_new[r] = 1.0;
+    }
+    if (!first) {
+        for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r] / sigma[r];
+        upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+        launch_copy_convert(c, w.p, lp, w.p, lp, nrhs, dscale, s);
+    }
+    for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r];
+    upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+    launch_copy_convert(c, w.r, lp, r64, TM_F64, nrhs, dscale, s);
+    launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
+    if (first) copy_field(w.p, w.r, fl, s);
+    launch_zero(c, w.x, TM_F32, nrhs, s);
+    std::vector<double> rr = norms_host(c, w.r, lp, nrhs, s);
+    std::vector<double> rho2 = norms_host(c, w.rho, lp, nrhs, s);
+    if (!first) download(c, hsc.data(), w.dsc, sizeof(CGScalars) * nrhs, s);
+    for (int r = 0; r < nrhs; r++) {
+        CGScalars &q = hsc[r];
+        if (first) {
+            memset(&q, 0, sizeof(q));
+            q.active = 1;
+        }
+        q.rr = rr[r];
+        q.rho2 = rho2[r];
+        q.rho2_ref = rho2[r];
+        q.target2 = p.tol * p.tol * bn2[r] * sig_new[r] * sig_new[r];
+        q.sigma = sig_new[r];
+        q.want_update = 0;
+        if (nrho[r] <= p.tol * p.tol * bn2[r]) q.active = 0;  // converged on the true FP64 residual
+        iter_res[r] = std::sqrt(nrho[r] / bn2[r]);
+    }
+    sigma = sig_new;
+    upload(w.dsc, hsc.data(), sizeof(CGScalars) * nrhs, s);
+}
+
+// x_hi += y / sigma
+void Solver::accumulate(hipStream_t s)
+{
+    std::vector<double> hscale(nrhs);
+    for (int r = 0; r < nrhs; r++) hscale[r] = 1.0 / sigma[r];
+    upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+    launch_axpy_dev(c, xe, TM_F64, w.x, TM_F32, nrhs, dscale, s);
+}
+
+void Solver::iteration_tail(hipStream_t s)
+{
+    cg_finish_beta(c, w.dsc, w.partb, nsb, nrhs, delta, s);
+    cg_update_px(c, w.p, w.r, w.x, w.prec, w.xprec, nrhs, w.dsc, s);
+}
+
+void Solver::iteration(hipStream_t s)
+{
+    launch_dslash(c, stage_call(c, w, epsp, 1), s);
+    launch_dslash(c, stage_call(c, w, epsp, 2), s);
+    cg_finish_alpha(c, w.dsc, w.partq, nsb, nrhs, s);
+    launch_dslash(c, stage_call(c, w, epsp, 3), s);
+    launch_dslash(c, stage_call(c, w, epsp, 4), s);
+    iteration_tail(s);
+}
+
+DslashCall Solver::stage(int k) const { return stage_call(c, w, epsp, k); }
+
+void Solver::count_iteration()
+{
+    total++;
+    since_check++;
+}
+
+bool Solver::due() const { return since_check >= check_every || total >= p.maxiter; }
+
+// host check after a group of iterations: NaN, convergence, reliable update
+void Solver::check(hipStream_t s)
+{
+    since_check = 0;
+    download(c, hsc.data(), w.dsc, sizeof(CGScalars) * nrhs, s);
+    bool any_active = false, any_update = false, any_bad = false;
+    for (auto &q : hsc) {
+        any_active |= q.active != 0;
+        any_update |= (q.active && q.want_update);
+        any_bad |= q.bad != 0;
+    }
+    if (any_bad) throw TmError{TM_ERR_NAN, "NaN/Inf in a solver reduction"};
+    const bool out_of_iters = total >= p.maxiter;
+    if (lp == TM_F64) {
+        for (int r = 0; r < nrhs; r++) iter_res[r] = std::sqrt(hsc[r].rho2 / bn2[r]);
+        done = !any_active || out_of_iters;
+        return;
+    }
+    if (p.solver == TM_CG_LOW) {
+        if (!any_active || out_of_iters) {
+            accumulate(s);
+            for (int r = 0; r < nrhs; r++) iter_res[r] = std::sqrt(hsc[r].rho2 / bn2[r]) / hsc[r].sigma;
+            done = true;
+        }
+        return;
+    }
+    if (!any_update && !out_of_iters) return;
+    // reliable update: FP64 true residual of the accumulated solution
+    accumulate(s);
+    op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s);
+    copy_field(rho64, bh, field_bytes(c, TM_F64, nrhs), s);
+    launch_axpby_host(c, rho64, q64, TM_F64, nrhs, -1.0, 1.0, s);
+    for (int r = 0; r < nrhs; r++)
+        if (hsc[r].active) n_rel[r]++;
+    restart(false, s);
+    bool any = false;
+    for (auto &q : hsc) any |= q.active != 0;
+    done = !any || out_of_iters;
+}
+
+SolveOut Solver::finalize(hipStream_t s)
+{
+    const double kap = c->kappa;
     // odd reconstruction psi_o = R^-1 (b_o - H_oe psi_e)
-    op_dslash(c, xo, xe, bo, nrhs, TM_F64, 1, 0, sd_mul(sd_scalar(kap), sd_twist_inv(epsp)), sd_twist_inv(epsp),
-              s);
+    op_dslash(c, xo, xe, bo, nrhs, TM_F64, 1, 0, sd_mul(sd_scalar(kap), sd_twist_inv(epsp)), sd_twist_inv(epsp), s);
     // true residual b - M x, both parities
     op_dslash(c, rho64, xo, xe, nrhs, TM_F64, 0, 0, sd_scalar(-kap), sd_twist(epsp), s);
     launch_axpby_host(c, rho64, be, TM_F64, nrhs, -1.0, 1.0, s);
@@ -408,7 +425,10 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
     launch_axpby_host(c, t64, bo, TM_F64, nrhs, -1.0, 1.0, s);
     std::vector<double> re = norms_host(c, rho64, TM_F64, nrhs, s);
     std::vector<double> ro = norms_host(c, t64, TM_F64, nrhs, s);
+    download(c, hsc.data(), w.dsc, sizeof(CGScalars) * nrhs, s);
     const double t1 = now_s();
+    SolveOut out;
+    out.st.assign(nrhs, tm_solve_stats{});
     for (int r = 0; r < nrhs; r++) {
         tm_solve_stats &st = out.st[r];
         st.iters = hsc[r].iters;
@@ -421,6 +441,19 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
         if (!st.converged && p.solver != TM_CG_LOW && out.status == TM_OK) out.status = TM_ERR_NOCONV;
     }
     return out;
+}
+
+SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,
+                      const tm_solve_params &p, hipStream_t s)
+{
+    Solver S;
+    S.init(c, xe, xo, be, bo, nrhs, p, s);
+    while (!S.done) {
+        S.iteration(s);
+        S.count_iteration();
+        if (S.due()) S.check(s);
+    }
+    return S.finalize(s);
 }
 
 // ---------------------------------------------------------------- loops
@@ -479,6 +512,32 @@ void hpe_exact_part(tm_ctx *c, double e, cx<double> *out)
         for (int t = 0; t < Lt; t++) out[(size_t)n * Lt + t] = n == 0 ? c0 : n == 15 ? c15 : cx<double>{0, 0};
 }
 
+void contract_noise(tm_ctx *c, int estimators, const void *ee, const void *eo, const void *se, const void *so,
+                    int nrhs, double epsp, cx<double> *dst)
+{
+    const int Lt = c->geo.L[3];
+    const size_t per = (size_t)16 * Lt;
+    const size_t f64 = field_bytes(c, TM_F64, nrhs);
+    std::vector<cx<double>> C;
+    int k = 0;
+    if (estimators & TM_EST_STD) {
+        outer_slices_host(c, se, so, ee, eo, nrhs, C, s_of(c));
+        loops_from_outer(c, C, false, cx<double>{1, 0}, dst + per * k++);
+    }
+    if (estimators & TM_EST_ONE_END) {
+        outer_slices_host(c, se, so, se, so, nrhs, C, s_of(c));
+        loops_from_outer(c, C, true, cx<double>{0, 2.0 * epsp}, dst + per * k++);
+    }
+    if (estimators & TM_EST_HPE) {
+        void *he = ws_get(c, "l_h_e", f64), *ho = ws_get(c, "l_h_o", f64);
+        copy_field(he, se, f64, s_of(c));
+        copy_field(ho, so, f64, s_of(c));
+        op_bh_power(c, he, ho, nrhs, epsp, 4, s_of(c));
+        outer_slices_host(c, he, ho, ee, eo, nrhs, C, s_of(c));
+        loops_from_outer(c, C, false, cx<double>{1, 0}, dst + per * k++);
+    }
+}
+
 int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noise, tm_loop_stats *stats,
               hipStream_t s)
 {
@@ -503,31 +562,16 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
     const size_t f64 = field_bytes(c, TM_F64, nrhs);
     void *ee = ws_get(c, "l_eta_e", f64), *eo = ws_get(c, "l_eta_o", f64);
     void *se = ws_get(c, "l_s_e", f64), *so = ws_get(c, "l_s_o", f64);
-    void *he = ws_get(c, "l_h_e", f64), *ho = ws_get(c, "l_h_o", f64);
     const size_t per = (size_t)16 * Lt;
     // per-noise loops [noise][prec 0 hp, 1 lp][est][16][Lt]
     std::vector<cx<double>> pn((size_t)n_noise * 2 * n_est * per, cx<double>{0, 0});
     tm_loop_stats st{};
     int status = TM_OK;
-    std::vector<cx<double>> C;
+    c->stream = s;
 
     auto contract = [&](int noise, int slot) {
-        for (int k = 0; k < n_est; k++) {
-            cx<double> *dst = &pn[(((size_t)noise * 2 + slot) * n_est + k) * per];
-            if (est_ids[k] == TM_EST_STD) {
-                outer_slices_host(c, se, so, ee, eo, nrhs, C, s);
-                loops_from_outer(c, C, false, cx<double>{1, 0}, dst);
-            } else if (est_ids[k] == TM_EST_ONE_END) {
-                outer_slices_host(c, se, so, se, so, nrhs, C, s);
-                loops_from_outer(c, C, true, cx<double>{0, 2.0 * epsp}, dst);
-            } else {
-                copy_field(he, se, f64, s);
-                copy_field(ho, so, f64, s);
-                op_bh_power(c, he, ho, nrhs, epsp, 4, s);
-                outer_slices_host(c, he, ho, ee, eo, nrhs, C, s);
-                loops_from_outer(c, C, false, cx<double>{1, 0}, dst);
-            }
-        }
+        contract_noise(c, p->estimators, ee, eo, se, so, nrhs, epsp,
+                       &pn[((size_t)noise * 2 + slot) * n_est * per]);
     };
 
     for (int k = 0; k < n_noise; k++) {

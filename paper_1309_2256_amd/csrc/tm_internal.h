@@ -247,6 +247,7 @@ struct tm_ctx {
     // autotuned right-hand sides per Dslash thread, keyed by (precision, nrhs)
     std::map<std::pair<int, int>, int> rhs_tile;
     std::string err;
+    hipStream_t stream = nullptr;  // stream of the current loop-driver call
     // pinned host staging for scalar read-back
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
@@ -301,6 +302,21 @@ struct DslashCall {
 
 void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s);
 int dslash_site_blocks(tm_ctx *c);
+
+// One launch over several contexts (lattices), one DslashCall each; all
+// share precision and operator form; R right-hand sides per thread divides
+// every nrhs.  prepare() uploads the parameter table (not capturable);
+// launch() is a single kernel launch (capturable in a HIP graph).
+struct MultiDslash {
+    void *table = nullptr;  // device, >= dslash_multi_table_bytes(n)
+    size_t table_bytes = 0;
+    int *start = nullptr;   // device, n + 1 block offsets
+    int prec = 0, dag = 0, own = 0, epi = 0, R = 1, n = 0, grid = 0;
+};
+size_t dslash_multi_table_bytes(int n);
+void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, int R,
+                          hipStream_t s);
+void multi_dslash_launch(const MultiDslash &m, hipStream_t s);
 
 // ---------------------------------------------------------------- blas
 

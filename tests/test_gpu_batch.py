@@ -1,0 +1,129 @@
+"""Uneven batches (three lattices in one graph-captured CG iteration stream).
+
+Each instance of a batch must reproduce its own single-lattice solve bit for
+bit (same arithmetic, same reliable-update cadence); residuals are also
+recomputed by the FP64 oracle, and the per-instance loops are checked
+against the oracle and against the single-lattice loop driver.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_1309_2256_amd as P  # noqa: E402
+
+DEV = "cuda:0"
+C4 = ("c4a", "c4b", "c4c")
+NRHS = {"c4a": 48, "c4b": 24, "c4c": 12}
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def inst():
+    out = []
+    for name in C4:
+        cfg = S.CONFIGS[name]
+        U = S.gauge_links(cfg["L"], cfg["eps_links"], cfg["seed"])
+        ctx = P.Context(cfg["L"], cfg["kappa"], cfg["two_kappa_mu"])
+        ctx.set_gauge(cuda(U))
+        out.append(dict(name=name, cfg=cfg, U=U, ctx=ctx))
+    yield out
+    for d in out:
+        d["ctx"].close()
+
+
+def sources(d, n, seed):
+    return S.random_spinor(d["cfg"]["L"], seed, n)
+
+
+@pytest.mark.parametrize("solver,prec", [(P.TM_CG_MIXED, P.TM_F16), (P.TM_CG_F64, P.TM_F32)])
+def test_batch_solve_matches_single_bit_for_bit(inst, solver, prec):
+    params = P.solve_params(tol=1e-9, solver=solver, inner_prec=prec)
+    bs = [cuda(sources(d, NRHS[d["name"]], 300 + k)) for k, d in enumerate(inst)]
+    xs = [torch.zeros_like(b) for b in bs]
+    batch = P.Batch([d["ctx"] for d in inst])
+    st, bstats = batch.solve(xs, bs, [NRHS[d["name"]] for d in inst], params)
+    batch.close()
+    for k, d in enumerate(inst):
+        n = NRHS[d["name"]]
+        x1 = torch.zeros_like(bs[k])
+        _, sstats = d["ctx"].solve(x1, bs[k], n, params)
+        assert torch.equal(xs[k], x1), d["name"]
+        assert [s.iters for s in bstats[k]] == [s.iters for s in sstats]
+        assert max(s.true_rel_res for s in bstats[k]) <= 1e-9
+        # the oracle recomputes the residual of a few right-hand sides
+        cfg, U = d["cfg"], d["U"]
+        xh, bh = host(xs[k]), host(bs[k])
+        for r in (0, n - 1):
+            res = np.linalg.norm(bh[r] - O.apply_M(cfg["L"], cfg["kappa"], cfg["two_kappa_mu"], -1, U,
+                                                   xh[r])) / np.linalg.norm(bh[r])
+            assert res <= 1e-9, (d["name"], r, res)
+
+
+def loop_params(seed, n_hp, est, hp):
+    p = P.tm_loop_params()
+    p.seed, p.n_hp, p.n_lp, p.estimators, p.dilution, p.mu_sign = seed, n_hp, 0, est, \
+        P.TM_DIL_SPIN_COLOUR, 1
+    p.hp = hp
+    return p
+
+
+def test_batch_loops(inst):
+    """c4: 4 / 2 / 1 noise vectors x 12 spin-colour dilutions (48 / 24 / 12
+    RHS) in one batch, mixed FP16 CG to 1e-9; per-instance loops against the
+    single-lattice driver (1e-7 normwise: the solves differ only in reliable-
+    update timing) and, for the 8^3x16 lattice, against the oracle."""
+    hp = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+    est = P.TM_EST_STD | P.TM_EST_ONE_END | P.TM_EST_HPE
+    plist = [loop_params(1040 + k, NRHS[d["name"]] // 12, est, hp) for k, d in enumerate(inst)]
+    batch = P.Batch([d["ctx"] for d in inst])
+    outs, stats, st = batch.loops(plist)
+    batch.close()
+    for k, d in enumerate(inst):
+        assert stats[k].max_res_hp <= 1e-9 and stats[k].n_solves_hp == NRHS[d["name"]]
+        single, _, sst, _ = d["ctx"].loops(plist[k])
+        for e in range(3):
+            err = np.abs(outs[k][e] - single[e]).max() / np.abs(single[e]).max()
+            assert err < 1e-7, (d["name"], e, err)
+    # oracle, first lattice, first noise only
+    d = inst[0]
+    cfg = d["cfg"]
+    p1 = loop_params(1040, 1, est, hp)
+    batch = P.Batch([d["ctx"]])
+    outs1, _, _ = batch.loops([p1])
+    batch.close()
+    ref, _ = O.loops(cfg["L"], cfg["kappa"], cfg["two_kappa_mu"], -1, d["U"], 1040, 1, 1e-12, 7,
+                     dilution=True)
+    for e, key in enumerate((O.EST_STD, O.EST_ONE_END, O.EST_HPE)):
+        err = np.abs(outs1[0][e] - ref[key]).max() / np.abs(ref[key]).max()
+        assert err < 1e-7, (key, err)
+
+
+def test_batch_argument_checks(inst):
+    import ctypes
+    arr = (ctypes.c_void_p * 2)(inst[0]["ctx"].h, inst[0]["ctx"].h)
+    h = ctypes.c_void_p()
+    assert P.tm_batch_create(ctypes.byref(h), arr, 2) == P.TM_ERR_ARG
+    batch = P.Batch([d["ctx"] for d in inst])
+    hp = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+    bad = [loop_params(1, 1, P.TM_EST_STD, hp) for _ in inst]
+    bad[1].n_lp = 2
+    with pytest.raises(P.TMError) as ei:
+        batch.loops(bad)
+    assert ei.value.status == P.TM_ERR_ARG
+    batch.close()
