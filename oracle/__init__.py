@@ -68,6 +68,11 @@ def lib():
                                    dp, dp]
         L.or_schur_at.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   dp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
+        L.or_transport.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, ctypes.c_int]
+        L.or_ptc_forward.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp]
+        L.or_ptc_loss_grad.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, dp,
+                                       dp]
+        L.or_ptc_loss_grad.restype = ctypes.c_double
         L.or_site_parity.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_int)]
         L.or_neighbours.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_long)]
         _lib = L
@@ -316,3 +321,45 @@ def loops(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, dilution=False
     if estimators & EST_HPE:
         mean[EST_HPE] = mean[EST_HPE] + hpe_exact(L, kappa, eps, t_bc, U)
     return mean, per_noise
+
+
+# ---------------------------------------------------------------- learned preconditioner
+
+def transport(L, t_bc, U, k, psi, adj=False):
+    """Path k: 0 identity, 1..4 hop in +mu, 5..8 hop in -mu (parallel transported)."""
+    U, psi = _links(L, U), _spinor(L, psi)
+    out = np.empty_like(psi)
+    lib().or_transport(_L(L), int(t_bc), _p(U), int(k), _p(psi), _p(out), int(adj))
+    return out
+
+
+def _weights(W, nc):
+    W = np.ascontiguousarray(W, dtype=np.complex128)
+    assert W.shape == (9, nc, 4, 4), W.shape
+    return W
+
+
+def ptc_forward(L, t_bc, U, W1, W2, psi):
+    """Two linear parallel-transport layers 1 -> nc -> 1 (weights [9][nc][4][4])."""
+    nc = W1.shape[1]
+    W1, W2 = _weights(W1, nc), _weights(W2, nc)
+    U, psi = _links(L, U), _spinor(L, psi)
+    out = np.empty_like(psi)
+    lib().or_ptc_forward(_L(L), int(t_bc), _p(U), nc, _p(W1), _p(W2), _p(psi), _p(out))
+    return out
+
+
+def ptc_loss_grad(L, t_bc, U, W1, W2, rs, es):
+    """Mean over pairs of |N(r) - e|^2 / |e|^2 and its gradient (complex
+    dl/dRe w + i dl/dIm w) for W1 and W2."""
+    nc = W1.shape[1]
+    W1, W2 = _weights(W1, nc), _weights(W2, nc)
+    U = _links(L, U)
+    G1 = np.zeros_like(W1)
+    G2 = np.zeros_like(W2)
+    loss = 0.0
+    for r, e in zip(rs, es):
+        loss += lib().or_ptc_loss_grad(_L(L), int(t_bc), _p(U), nc, _p(W1), _p(W2),
+                                       _p(_spinor(L, r)), _p(_spinor(L, e)), _p(G1), _p(G2))
+    n = len(rs)
+    return loss / n, G1 / n, G2 / n

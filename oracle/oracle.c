@@ -789,3 +789,168 @@ void or_schur_at(const int L[4], double kappa, double eps, int t_bc, const doubl
             }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* gauge-covariant parallel-transport network                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Path k: 0 identity; 1..4 one hop in +mu (mu = k-1): (T phi)(x) =
+ * U_mu(x) phi(x+mu); 5..8 one hop in -mu (mu = k-5): (T phi)(x) =
+ * U_mu(x-mu)^dag phi(x-mu); the fermion boundary phase rides on hops across
+ * the time boundary.  adj = 1 applies the adjoint (block-wise conjugate
+ * transpose of the same matrix).
+ */
+void or_transport(const int L[4], int t_bc, const double *Ud, int k, const double *ind, double *outd,
+                  int adj)
+{
+    const cplx *U = (const cplx *)Ud, *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    long V = vol(L);
+    if (k == 0) {
+        memcpy(out, in, sizeof(cplx) * 12 * V);
+        return;
+    }
+    const int mu = (k - 1) & 3;
+    const int fwd = k <= 4;
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; x++) {
+        double ph;
+        /* matrix element T[x][y] = W for y = x + d; its adjoint has element
+         * T^dag[y][x] = W^dag, i.e. (T^dag f)(x) = W(x - d -> x)^dag f(x - d) */
+        int dir = fwd ? +1 : -1;
+        if (adj) dir = -dir;
+        long y = step(L, t_bc, x, mu, dir, &ph);
+        const cplx *W;
+        int dagger;
+        if (!adj) {
+            W = fwd ? U + 9 * ((long)mu * V + x) : U + 9 * ((long)mu * V + y);
+            dagger = !fwd;
+        } else {
+            /* row y of T holds W_T(y) acting on f(x); adjoint takes its dagger */
+            W = fwd ? U + 9 * ((long)mu * V + y) : U + 9 * ((long)mu * V + x);
+            dagger = fwd;
+        }
+        for (int a = 0; a < 4; a++)
+            for (int i = 0; i < 3; i++) {
+                cplx t = 0;
+                for (int j = 0; j < 3; j++)
+                    t += (dagger ? conj(W[3 * j + i]) : W[3 * i + j]) * in[12 * y + 3 * a + j];
+                out[12 * x + 3 * a + i] = ph * t;
+            }
+    }
+}
+
+/* out(x) += S in(x) for a 4x4 spin matrix S (complex [4][4]) */
+static void spin_mac(long V, const cplx *S, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; x++)
+        for (int a = 0; a < 4; a++)
+            for (int c = 0; c < 3; c++) {
+                cplx t = 0;
+                for (int b = 0; b < 4; b++) t += S[4 * a + b] * in[12 * x + 3 * b + c];
+                out[12 * x + 3 * a + c] += t;
+            }
+}
+
+/*
+ * Two linear parallel-transport layers, 1 -> nc -> 1 channels:
+ *   phi_c = sum_k W1[k][c] T_k in,     out = sum_{k,c} W2[k][c] T_k phi_c,
+ * W1, W2: complex [9][nc][4][4] spin matrices.  Evaluated layer by layer.
+ */
+void or_ptc_forward(const int L[4], int t_bc, const double *U, int nc, const double *W1d,
+                    const double *W2d, const double *ind, double *outd)
+{
+    const cplx *W1 = (const cplx *)W1d, *W2 = (const cplx *)W2d;
+    long V = vol(L);
+    size_t n = sizeof(cplx) * 12 * V;
+    cplx *T = malloc(n), *phi = malloc(n * nc), *out = (cplx *)outd;
+    memset(phi, 0, n * nc);
+    for (int k = 0; k < 9; k++) {
+        or_transport(L, t_bc, U, k, ind, (double *)T, 0);
+        for (int c = 0; c < nc; c++) spin_mac(V, W1 + 16 * (k * nc + c), T, phi + 12 * V * c);
+    }
+    memset(out, 0, n);
+    for (int k = 0; k < 9; k++)
+        for (int c = 0; c < nc; c++) {
+            or_transport(L, t_bc, U, k, (double *)(phi + 12 * V * c), (double *)T, 0);
+            spin_mac(V, W2 + 16 * (k * nc + c), T, out);
+        }
+    free(T);
+    free(phi);
+}
+
+/*
+ * Loss of one pair, l = |N(in) - e|^2 / |e|^2, and its gradient with respect
+ * to the real and imaginary parts of every weight, accumulated into G1, G2 as
+ * complex numbers dl/dRe(w) + i dl/dIm(w), by reverse-mode differentiation of
+ * the forward pass above: with delta = 2 (out - e) / |e|^2,
+ *   G2[k][c] = sum_x delta(x) (T_k phi_c)(x)^dag      (spin outer product,
+ *                                                      colour traced)
+ *   g_c      = sum_k T_k^dag (W2[k][c]^dag delta)
+ *   G1[k][c] = sum_x g_c(x) (T_k in)(x)^dag.
+ * Returns l.
+ */
+double or_ptc_loss_grad(const int L[4], int t_bc, const double *U, int nc, const double *W1d,
+                        const double *W2d, const double *ind, const double *ed, double *G1d,
+                        double *G2d)
+{
+    const cplx *W1 = (const cplx *)W1d, *W2 = (const cplx *)W2d, *e = (const cplx *)ed;
+    cplx *G1 = (cplx *)G1d, *G2 = (cplx *)G2d;
+    long V = vol(L);
+    size_t n = sizeof(cplx) * 12 * V;
+    cplx *T = malloc(n), *phi = malloc(n * nc), *out = malloc(n), *delta = malloc(n);
+    cplx *g = malloc(n), *tmp = malloc(n), *Tin = malloc(n * 9);
+    or_ptc_forward(L, t_bc, U, nc, W1d, W2d, ind, (double *)out);
+    /* hidden layer again (kept for the gradients) */
+    memset(phi, 0, n * nc);
+    for (int k = 0; k < 9; k++) {
+        or_transport(L, t_bc, U, k, ind, (double *)(Tin + 12 * V * k), 0);
+        for (int c = 0; c < nc; c++) spin_mac(V, W1 + 16 * (k * nc + c), Tin + 12 * V * k, phi + 12 * V * c);
+    }
+    double en = 0, l = 0;
+    for (long i = 0; i < 12 * V; i++) en += creal(e[i] * conj(e[i]));
+    for (long i = 0; i < 12 * V; i++) {
+        cplx d = out[i] - e[i];
+        l += creal(d * conj(d));
+        delta[i] = 2.0 * d / en;
+    }
+    l /= en;
+    for (int c = 0; c < nc; c++) {
+        memset(g, 0, n);
+        for (int k = 0; k < 9; k++) {
+            or_transport(L, t_bc, U, k, (double *)(phi + 12 * V * c), (double *)T, 0);
+            cplx *G = G2 + 16 * (k * nc + c);
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    cplx acc = 0;
+                    for (long x = 0; x < V; x++)
+                        for (int col = 0; col < 3; col++)
+                            acc += delta[12 * x + 3 * a + col] * conj(T[12 * x + 3 * b + col]);
+                    G[4 * a + b] += acc;
+                }
+            /* W2^dag delta, then transported back */
+            cplx Wd[16];
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) Wd[4 * a + b] = conj(W2[16 * (k * nc + c) + 4 * b + a]);
+            memset(tmp, 0, n);
+            spin_mac(V, Wd, delta, tmp);
+            or_transport(L, t_bc, U, k, (double *)tmp, (double *)T, 1);
+            for (long i = 0; i < 12 * V; i++) g[i] += T[i];
+        }
+        for (int k = 0; k < 9; k++) {
+            cplx *G = G1 + 16 * (k * nc + c);
+            const cplx *ti = Tin + 12 * V * k;
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    cplx acc = 0;
+                    for (long x = 0; x < V; x++)
+                        for (int col = 0; col < 3; col++) acc += g[12 * x + 3 * a + col] * conj(ti[12 * x + 3 * b + col]);
+                    G[4 * a + b] += acc;
+                }
+        }
+    }
+    free(T); free(phi); free(out); free(delta); free(g); free(tmp); free(Tin);
+    return l;
+}

@@ -36,4 +36,11 @@ void or_hpe_exact(const int L[4], double kappa, double eps, int t_bc, const doub
                   double *out);
 void or_schur_at(const int L[4], double kappa, double eps, int t_bc, const double *U,
                  const double *x, const long *sites, long nsites, double *out);
+void or_transport(const int L[4], int t_bc, const double *U, int k, const double *in, double *out,
+                  int adj);
+void or_ptc_forward(const int L[4], int t_bc, const double *U, int nc, const double *W1,
+                    const double *W2, const double *in, double *out);
+double or_ptc_loss_grad(const int L[4], int t_bc, const double *U, int nc, const double *W1,
+                        const double *W2, const double *in, const double *e, double *G1,
+                        double *G2);
 #endif

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 
 #include "runtime.h"
@@ -24,6 +25,10 @@ struct tm_batch {
     std::vector<int> graph_set;  // instances captured in the current graph
     int graph_iters = 0, graph_R = 0;
     std::map<std::vector<int>, int> tuned_R;  // (prec, nrhs...) -> RHS per thread
+    // debugging switches (environment): TM_BATCH_EAGER=1 replays the
+    // iterations without graph capture, TM_BATCH_SINGLE=1 uses per-instance
+    // launches instead of the multi-instance kernels
+    bool eager = false, single_launches = false;
 };
 
 namespace {
@@ -74,6 +79,10 @@ void prepare_stages(tm_batch *b, std::vector<Solver> &S, const std::vector<int> 
 void launch_iteration(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set)
 {
     hipStream_t s = b->stream;
+    if (b->single_launches) {
+        for (int i : set) S[i].iteration(s);
+        return;
+    }
     multi_dslash_launch(b->md[0], s);
     multi_dslash_launch(b->md[1], s);
     for (int i : set) cg_finish_alpha(S[i].c, S[i].w.dsc, S[i].w.partq, S[i].nsb, S[i].nrhs, s);
@@ -124,8 +133,8 @@ int choose_R(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set)
 void build_graph(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set, int iters)
 {
     drop_graph(b);
-    const int R = choose_R(b, S, set);
-    prepare_stages(b, S, set, R);
+    const int R = b->single_launches ? 1 : choose_R(b, S, set);
+    if (!b->single_launches) prepare_stages(b, S, set, R);
     TM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     try {
         for (int k = 0; k < iters; k++) launch_iteration(b, S, set);
@@ -163,8 +172,13 @@ void run_batch(tm_batch *b, std::vector<Solver> &S)
             }
             continue;
         }
-        if (b->graph_set != set || b->graph_iters != K) build_graph(b, S, set, K);
-        TM_HIP(hipGraphLaunch(b->exec, b->stream));
+        if (b->eager) {
+            if (!b->single_launches) prepare_stages(b, S, set, choose_R(b, S, set));
+            for (int k = 0; k < K; k++) launch_iteration(b, S, set);
+        } else {
+            if (b->graph_set != set || b->graph_iters != K) build_graph(b, S, set, K);
+            TM_HIP(hipGraphLaunch(b->exec, b->stream));
+        }
         for (int i : set) {
             for (int k = 0; k < K; k++) S[i].count_iteration();
             S[i].check(b->stream);
@@ -189,6 +203,8 @@ extern "C" int tm_batch_create(tm_batch **out, tm_ctx *const *ctxs, int n)
     if (!b) return TM_ERR_OOM;
     b->ctx.assign(ctxs, ctxs + n);
     b->device = ctxs[0]->device;
+    if (const char *e = getenv("TM_BATCH_EAGER")) b->eager = atoi(e) != 0;
+    if (const char *e = getenv("TM_BATCH_SINGLE")) b->single_launches = atoi(e) != 0;
     int st = bguard(b, [&]() {
         TM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
         for (auto &m : b->md) {

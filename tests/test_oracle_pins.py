@@ -363,3 +363,73 @@ def test_tsm_reduces_to_plain_and_is_unbiased(dense2):
                                        O.cgnr(L, kappa, eps, -1, U, O.noise_z4(L, 5000 + k, 0),
                                               3e-1)[0]) for k in range(K)])
     assert np.max(np.abs(lp_only.mean(0) - ex) / (lp_only.std(0) / np.sqrt(K) + 1e-30)) > 5
+
+
+# ---------------------------------------------------------------- learned preconditioner
+
+def _rand_weights(rng, nc, scale=0.3):
+    return scale * (rng.standard_normal((9, nc, 4, 4)) + 1j * rng.standard_normal((9, nc, 4, 4)))
+
+
+def test_transport_adjoints_and_equivariance():
+    L = (4, 2, 2, 4)
+    U = S.gauge_links(L, 0.5, 51)
+    f, g = S.random_spinor(L, 52), S.random_spinor(L, 53)
+    for k in range(9):
+        Tg = O.transport(L, -1, U, k, g)
+        Tdf = O.transport(L, -1, U, k, f, adj=True)
+        assert abs(np.vdot(f, Tg) - np.vdot(Tdf, g)) < 1e-12
+    for mu in range(4):  # the adjoint of a +mu hop is the -mu hop
+        assert np.abs(O.transport(L, -1, U, 1 + mu, f, adj=True) - O.transport(L, -1, U, 5 + mu, f)).max() < 1e-15
+    # gauge equivariance of the network: N[U^g](g phi) = g N[U](phi)
+    rng = np.random.default_rng(54)
+    W1, W2 = _rand_weights(rng, 12), _rand_weights(rng, 12)
+    gm = S.random_su3(int(np.prod(L)), 55)
+    Ug = S.gauge_transform(L, U, gm)
+    rot = lambda v: np.einsum("xab,xsb->xsa", gm, v)  # noqa: E731
+    lhs = O.ptc_forward(L, -1, Ug, W1, W2, rot(f))
+    rhs = rot(O.ptc_forward(L, -1, U, W1, W2, f))
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+
+
+def test_ptc_special_weights():
+    """Identity weights give the identity map; first-layer weights
+    -kappa (1 -+ gamma_mu) on the +-mu paths give the hopping term H."""
+    L, kappa = (4, 2, 2, 4), 0.13
+    U = S.gauge_links(L, 0.5, 56)
+    f = S.random_spinor(L, 57)
+    nc = 12
+    W1 = np.zeros((9, nc, 4, 4), dtype=complex)
+    W2 = np.zeros((9, nc, 4, 4), dtype=complex)
+    W1[0, 0] = np.eye(4)
+    W2[0, 0] = np.eye(4)
+    assert np.abs(O.ptc_forward(L, -1, U, W1, W2, f) - f).max() < 1e-15
+    W1[0, 0] = 0
+    for mu in range(4):
+        g = O.gamma(1 << mu)
+        W1[1 + mu, 0] = -kappa * (np.eye(4) - g)
+        W1[5 + mu, 0] = -kappa * (np.eye(4) + g)
+    assert np.abs(O.ptc_forward(L, -1, U, W1, W2, f) - O.hop(L, kappa, -1, U, f)).max() < 1e-14
+
+
+def test_ptc_gradient_finite_differences():
+    L = (2, 2, 2, 4)
+    U = S.gauge_links(L, 0.5, 58)
+    rng = np.random.default_rng(59)
+    nc = 3
+    W1, W2 = _rand_weights(rng, nc), _rand_weights(rng, nc)
+    rs = [S.random_spinor(L, 60 + i) for i in range(2)]
+    es = [S.random_spinor(L, 70 + i) for i in range(2)]
+    loss, G1, G2 = O.ptc_loss_grad(L, -1, U, W1, W2, rs, es)
+    h = 1e-6
+    for W, G in ((W1, G1), (W2, G2)):
+        for idx in [(0, 0, 0, 0), (3, 1, 2, 1), (8, 2, 3, 3), (5, 0, 1, 2)]:
+            for part in (1, 1j):
+                Wp, Wm = W.copy(), W.copy()
+                Wp[idx] += h * part
+                Wm[idx] -= h * part
+                lp = O.ptc_loss_grad(L, -1, U, Wp if W is W1 else W1, Wp if W is W2 else W2, rs, es)[0]
+                lm = O.ptc_loss_grad(L, -1, U, Wm if W is W1 else W1, Wm if W is W2 else W2, rs, es)[0]
+                fd = (lp - lm) / (2 * h)
+                an = G[idx].real if part == 1 else G[idx].imag
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (idx, part, fd, an)
