@@ -207,13 +207,6 @@ extern "C" int tm_batch_create(tm_batch **out, tm_ctx *const *ctxs, int n)
     if (const char *e = getenv("TM_BATCH_SINGLE")) b->single_launches = atoi(e) != 0;
     int st = bguard(b, [&]() {
         TM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
-        for (auto &m : b->md) {
-            m.table_bytes = dslash_multi_table_bytes(n);
-            m.table = nullptr;
-            m.start = nullptr;
-            TM_HIP(hipMalloc(&m.table, m.table_bytes));
-            TM_HIP(hipMalloc((void **)&m.start, sizeof(int) * (n + 1)));
-        }
         return TM_OK;
     });
     if (st != TM_OK) {
@@ -230,10 +223,6 @@ extern "C" void tm_batch_destroy(tm_batch *b)
     (void)hipSetDevice(b->device);
     drop_graph(b);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    for (auto &m : b->md) {
-        if (m.table) (void)hipFree(m.table);
-        if (m.start) (void)hipFree(m.start);
-    }
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

@@ -15,6 +15,7 @@
 //            backward links are stored conjugated and the antiperiodic
 //            boundary phase is folded in, so the kernel has no branch on it.
 #include <cstdlib>
+#include <cstring>
 
 #include "tm_internal.h"
 
@@ -27,8 +28,10 @@ constexpr int kBlock = 256;
 template <typename T, int R>
 constexpr int waves_for() { return sizeof(T) == 8 ? 2 : (R <= 2 ? 4 : 3); }
 
+// 16-byte aligned so that an array of records keeps every complex field
+// naturally aligned
 template <typename T>
-struct DParams {
+struct alignas(16) DParams {
     void *out;
     const void *in;
     const void *own;
@@ -489,16 +492,26 @@ __global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash(DParams<
 
 // Several lattices in one launch: instance i owns hardware blocks
 // [start[i], start[i+1]) (padded to multiples of 8; padding blocks exit).
+// The records travel in the kernel-argument segment, like the single form's
+// parameters: uniform, read-only scalar loads that the compiler may repeat
+// after the epilogue's stores without going through the vector caches.
+template <typename T>
+struct MultiArgs {
+    DParams<T> p[kMultiInst];
+    int start[kMultiInst + 1];
+    int n;
+};
+static_assert(sizeof(MultiArgs<double>) <= 4096, "kernel arguments exceed 4 KiB");
+
 template <typename SS, typename LS, typename T, int R, int DAG, int OWN, int EPI>
-__global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash_multi(const DParams<T> *P, const int *start,
-                                                                             int n)
+__global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash_multi(const MultiArgs<T> m)
 {
     int i = 0;
-    while (i + 1 < n && (int)blockIdx.x >= start[i + 1]) i++;
-    const int local = (int)blockIdx.x - start[i];
-    const int nreal = P[i].nblk * P[i].ngroups;
+    while (i + 1 < m.n && (int)blockIdx.x >= m.start[i + 1]) i++;
+    const int local = (int)blockIdx.x - m.start[i];
+    const int nreal = m.p[i].nblk * m.p[i].ngroups;
     if (local >= nreal) return;
-    dslash_block<SS, LS, T, R, DAG, OWN, EPI>(P[i], local, nreal);
+    dslash_block<SS, LS, T, R, DAG, OWN, EPI>(m.p[i], local, nreal);
 }
 
 template <typename T>
@@ -637,40 +650,49 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 }
 
 template <typename SS, typename LS, typename T, int R>
-void multi_fill(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, hipStream_t s)
+void multi_fill(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs)
 {
-    std::vector<DParams<T>> tab;
-    std::vector<int> start(1, 0);
-    for (size_t k = 0; k < cs.size(); k++) {
-        TM_REQUIRE(dcs[k].nrhs % R == 0, "RHS tile must divide every instance's nrhs");
-        tab.push_back(fill_params<SS, LS, T, R>(cs[k], dcs[k]));
-        const int nb = tab.back().nblk * tab.back().ngroups;
-        start.push_back(start.back() + (nb + 7) / 8 * 8);
+    m.args.clear();
+    m.grid.clear();
+    for (size_t c0 = 0; c0 < cs.size(); c0 += kMultiInst) {
+        MultiArgs<T> a{};
+        const size_t c1 = std::min(cs.size(), c0 + kMultiInst);
+        a.n = (int)(c1 - c0);
+        a.start[0] = 0;
+        for (size_t k = c0; k < c1; k++) {
+            TM_REQUIRE(dcs[k].nrhs % R == 0, "RHS tile must divide every instance's nrhs");
+            const int j = (int)(k - c0);
+            a.p[j] = fill_params<SS, LS, T, R>(cs[k], dcs[k]);
+            const int nb = a.p[j].nblk * a.p[j].ngroups;
+            a.start[j + 1] = a.start[j] + (nb + 7) / 8 * 8;
+        }
+        const unsigned char *raw = reinterpret_cast<const unsigned char *>(&a);
+        m.args.emplace_back(raw, raw + sizeof(a));
+        m.grid.push_back(a.start[a.n]);
     }
-    TM_REQUIRE(m.table_bytes >= tab.size() * sizeof(DParams<T>), "multi-instance table too small");
-    TM_HIP(hipMemcpyAsync(m.table, tab.data(), tab.size() * sizeof(DParams<T>), hipMemcpyHostToDevice, s));
-    TM_HIP(hipMemcpyAsync(m.start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    TM_HIP(hipStreamSynchronize(s));
-    m.grid = start.back();
 }
 
 template <typename SS, typename LS, typename T, int R>
 void multi_go(const MultiDslash &m, hipStream_t s)
 {
-    const DParams<T> *P = (const DParams<T> *)m.table;
-    dim3 g(m.grid), b(kBlock);
-    // the four stage forms of a CG iteration on the Schur normal equations
-    if (m.dag == 0 && m.own == 0 && m.epi == EPI_STORE)
-        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 0, EPI_STORE>), g, b, 0, s, P, m.start, m.n);
-    else if (m.dag == 1 && m.own == 0 && m.epi == EPI_STORE)
-        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 1, 0, EPI_STORE>), g, b, 0, s, P, m.start, m.n);
-    else if (m.dag == 0 && m.own == 1 && m.epi == EPI_NORM)
-        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 1, EPI_NORM>), g, b, 0, s, P, m.start, m.n);
-    else if (m.dag == 0 && m.own == 1 && m.epi == EPI_CG)
-        hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 1, EPI_CG>), g, b, 0, s, P, m.start, m.n);
-    else
-        throw TmError{TM_ERR_UNSUPPORTED, "multi-instance Dslash form not instantiated"};
-    TM_HIP(hipGetLastError());
+    for (size_t c = 0; c < m.args.size(); c++) {
+        TM_REQUIRE(m.args[c].size() == sizeof(MultiArgs<T>), "multi-instance arguments of another precision");
+        MultiArgs<T> a;
+        std::memcpy(&a, m.args[c].data(), sizeof(a));
+        dim3 g(m.grid[c]), b(kBlock);
+        // the four stage forms of a CG iteration on the Schur normal equations
+        if (m.dag == 0 && m.own == 0 && m.epi == EPI_STORE)
+            hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 0, EPI_STORE>), g, b, 0, s, a);
+        else if (m.dag == 1 && m.own == 0 && m.epi == EPI_STORE)
+            hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 1, 0, EPI_STORE>), g, b, 0, s, a);
+        else if (m.dag == 0 && m.own == 1 && m.epi == EPI_NORM)
+            hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 1, EPI_NORM>), g, b, 0, s, a);
+        else if (m.dag == 0 && m.own == 1 && m.epi == EPI_CG)
+            hipLaunchKernelGGL((k_dslash_multi<SS, LS, T, R, 0, 1, EPI_CG>), g, b, 0, s, a);
+        else
+            throw TmError{TM_ERR_UNSUPPORTED, "multi-instance Dslash form not instantiated"};
+        TM_HIP(hipGetLastError());
+    }
 }
 
 template <typename F>
@@ -705,8 +727,6 @@ void multi_dispatch(int prec, int R, F &&f)
 
 }  // namespace
 
-size_t dslash_multi_table_bytes(int n) { return (size_t)n * sizeof(DParams<double>); }
-
 void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, int R,
                           hipStream_t s)
 {
@@ -724,7 +744,7 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
         TM_REQUIRE(cs[k]->have_gauge, "no gauge field set");
         if (m.prec != TM_F64) ensure_links32(cs[k], s);
     }
-    multi_dispatch(m.prec, R, [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs, s); });
+    multi_dispatch(m.prec, R, [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs); });
 }
 
 void multi_dslash_launch(const MultiDslash &m, hipStream_t s)

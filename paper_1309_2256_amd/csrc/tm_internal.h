@@ -251,6 +251,11 @@ struct tm_ctx {
     // pinned host staging for scalar read-back
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
+    // learned preconditioner (ptc.hip): channel count (0 = no weights),
+    // Adam step counter, training-pair store (capacity, count, precision)
+    int ptc_nc = 0;
+    long ptc_step = 0;
+    int ptc_cap = 0, ptc_n = 0, ptc_store = TM_F32;
 };
 
 void *ws_get(tm_ctx *c, const std::string &name, size_t bytes);
@@ -305,15 +310,16 @@ int dslash_site_blocks(tm_ctx *c);
 
 // One launch over several contexts (lattices), one DslashCall each; all
 // share precision and operator form; R right-hand sides per thread divides
-// every nrhs.  prepare() uploads the parameter table (not capturable);
-// launch() is a single kernel launch (capturable in a HIP graph).
+// every nrhs.  prepare() builds the launch arguments on the host;
+// launch() is one kernel launch per chunk of instances (capturable).
 struct MultiDslash {
-    void *table = nullptr;  // device, >= dslash_multi_table_bytes(n)
-    size_t table_bytes = 0;
-    int *start = nullptr;   // device, n + 1 block offsets
-    int prec = 0, dag = 0, own = 0, epi = 0, R = 1, n = 0, grid = 0;
+    // per chunk of at most kMultiInst instances: the kernel-argument block
+    // (instance records + block offsets) and the grid it covers
+    std::vector<std::vector<unsigned char>> args;
+    std::vector<int> grid;
+    int prec = 0, dag = 0, own = 0, epi = 0, R = 1, n = 0;
 };
-size_t dslash_multi_table_bytes(int n);
+constexpr int kMultiInst = 16;  // instances per launch (kernel-argument space)
 void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, int R,
                           hipStream_t s);
 void multi_dslash_launch(const MultiDslash &m, hipStream_t s);
