@@ -136,9 +136,14 @@ typedef enum {
     TM_CG_F64 = 0,   /* plain FP64 CGNR on the even-odd system */
     TM_CG_MIXED = 1, /* CGNR with FP32 arithmetic and inner_prec storage, FP64
                         reliable updates (true residual recomputed in FP64) */
-    TM_CG_LOW = 2    /* truncated low-precision CGNR (TSM low-precision solve):
+    TM_CG_LOW = 2,   /* truncated low-precision CGNR (TSM low-precision solve):
                         inner_prec storage, FP32 arithmetic, no reliable update;
                         stops on the iterated residual */
+    TM_FGMRES = 3,   /* restarted GMRES(m) on the full system M x = b in FP64
+                        (no preconditioner); the reference for TM_FGMRES_PTC */
+    TM_FGMRES_PTC = 4 /* flexible GMRES(m) (Saad 1993) in FP64, right-
+                        preconditioned by the parallel-transport network of
+                        tm_ptc_* evaluated in FP32 (weights must be set) */
 } tm_solver;
 
 typedef struct {
@@ -150,12 +155,13 @@ typedef struct {
                          residual falls below delta x its value at the last
                          update (MIXED; 0 selects 0.1)                           */
     int mu_sign;      /* +1 u flavour, -1 d flavour                              */
-    int check_every;  /* iterations between host convergence checks (0 = 8)      */
+    int check_every;  /* CG: iterations between host convergence checks (0 = 8);
+                         FGMRES: restart length m (0 = 16, at most 32)           */
 } tm_solve_params;
 
 typedef struct {
-    int iters;            /* CG iterations                                      */
-    int n_reliable;       /* reliable updates performed                         */
+    int iters;            /* CG iterations (FGMRES: Arnoldi steps)              */
+    int n_reliable;       /* reliable updates performed (FGMRES: restarts)      */
     int converged;        /* 1 when |b - M x| <= tol |b| at exit                 */
     int reserved;
     double true_rel_res;  /* |b - M x| / |b| recomputed in FP64 at exit         */
@@ -267,6 +273,69 @@ int tm_batch_solve(tm_batch *batch, double *const *x, const double *const *b, co
  * host array of n entries or NULL. */
 int tm_batch_loops(tm_batch *batch, const tm_loop_params *p, double *const *loops,
                    tm_loop_stats *stats, tm_stream stream);
+
+/* ---------------------------------------------------------------- learned preconditioner
+ * A gauge-covariant parallel-transport convolution network (PTC, in the form
+ * of Lehner and Wettig, arXiv:2302.05419) that approximates M^-1 and serves as
+ * the right preconditioner of TM_FGMRES_PTC.  It is an addition to the 2013
+ * method, acting on full-lattice fields.
+ *   Paths: k = 0 identity; k = 1..4 (T_k f)(x) = U_mu(x) f(x+mu), mu = k-1;
+ *   k = 5..8 (T_k f)(x) = U_mu(x-mu)^dag f(x-mu), mu = k-5; the time boundary
+ *   phase of tm_lattice.t_bc multiplies hops across t = Lt-1 <-> 0.
+ *   Two linear layers, one input channel, nc hidden channels, one output:
+ *     phi_c = sum_k W1[k][c] T_k psi,   N(psi) = sum_{k,c} W2[k][c] T_k phi_c,
+ *   W1, W2: host [9][nc][4][4] complex double, spin matrices (row-major)
+ *   acting on the spin index only (gauge covariance allows no colour mixing).
+ *   Loss of a pair (r, e): |N(r) - e|^2 / |e|^2; gradients are complex
+ *   numbers dl/dRe(w) + i dl/dIm(w).
+ * The device evaluates the collapsed form N = sum_k T_k sum_k' A[k][k'] T_k'
+ * with A[k][k'] = sum_c W2[k][c] W1[k'][c] (exact: both layers are linear and
+ * T_k commutes with spin matrices), transports in FP32, gradient sums in FP64. */
+
+/* Set / read the weights (1 <= nc <= 64). */
+int tm_ptc_set_weights(tm_ctx *ctx, int nc, const double *W1, const double *W2);
+int tm_ptc_get_weights(tm_ctx *ctx, int nc, double *W1, double *W2);
+/* Weights of the hopping expansion of M^-1 to second order,
+ * N = B - B H B + B H B H B with B = R(mu_sign eps)^-1 (sec. II.E), using
+ * channels 0..8 (nc >= 9); the other entries of W1 get uniform values in
+ * [-noise, noise] from SplitMix64(seed). */
+int tm_ptc_init_hopping(tm_ctx *ctx, int nc, int mu_sign, uint64_t seed, double noise);
+/* out = N(in): device canonical full FP64 [nrhs][V][4][3], computed in FP32. */
+int tm_ptc_apply(tm_ctx *ctx, double *out, const double *in, int nrhs, tm_stream stream);
+/* Mean loss over npairs pairs (r[i], e[i]) (device canonical full FP64) and
+ * its gradient; G1, G2: host [9][nc][4][4] complex double (may be NULL). */
+int tm_ptc_loss_grad(tm_ctx *ctx, const double *r, const double *e, int npairs, double *loss, double *G1,
+                     double *G2, tm_stream stream);
+/* Training-pair store owned by the context: reserve room for `capacity`
+ * pairs held in store_prec (TM_F32 or TM_BF16, round to nearest even); this
+ * drops stored pairs.  tm_ptc_pairs_add appends n pairs (device canonical
+ * full FP64 r, e; TM_ERR_ARG beyond capacity or for e = 0). */
+int tm_ptc_pairs_reserve(tm_ctx *ctx, int capacity, int store_prec);
+int tm_ptc_pairs_add(tm_ctx *ctx, const double *r, const double *e, int n, tm_stream stream);
+
+typedef struct {
+    int epochs;        /* passes over the stored pairs (>= 1)                      */
+    int batch;         /* pairs per optimiser step (1 <= batch <= stored pairs)    */
+    double lr;         /* Adam step size (Kingma and Ba 2015)                      */
+    double beta1, beta2, adam_eps; /* Adam moments and denominator guard            */
+    uint64_t seed;     /* order of the batches within each epoch                   */
+} tm_ptc_train_params;
+
+typedef struct {
+    int steps;         /* optimiser steps taken                                    */
+    int reserved;
+    double loss_first; /* mean batch loss over the first epoch                     */
+    double loss_last;  /* mean batch loss over the last epoch                      */
+    double seconds;
+} tm_ptc_train_stats;
+
+/* Train the weights by Adam on the stored pairs: each epoch visits the
+ * floor(n / batch) consecutive batches in an order drawn from `seed`; a step
+ * minimises the batch mean of the loss.  loss_per_step: host array of
+ * epochs * floor(n / batch) doubles (loss of each batch before its step) or
+ * NULL.  The weights start from the current ones (set or initialised). */
+int tm_ptc_train(tm_ctx *ctx, const tm_ptc_train_params *p, tm_ptc_train_stats *stats, double *loss_per_step,
+                 tm_stream stream);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,7 @@ TM_OK, TM_ERR_ARG, TM_ERR_HIP, TM_ERR_OOM, TM_ERR_NOCONV, TM_ERR_NAN, TM_ERR_UNS
 TM_F64, TM_F32, TM_F16, TM_BF16 = 0, 1, 2, 3
 (TM_HOP_EO, TM_HOP_OE, TM_RINV_HOP_OE, TM_SCHUR, TM_SCHUR_DAG, TM_NORMAL, TM_FULL, TM_FULL_DAG,
  TM_RINV_HOP_EO) = range(9)
-TM_CG_F64, TM_CG_MIXED, TM_CG_LOW = 0, 1, 2
+TM_CG_F64, TM_CG_MIXED, TM_CG_LOW, TM_FGMRES, TM_FGMRES_PTC = 0, 1, 2, 3, 4
 TM_EST_STD, TM_EST_ONE_END, TM_EST_HPE = 1, 2, 4
 TM_DIL_NONE, TM_DIL_SPIN_COLOUR = 0, 1
 
@@ -66,6 +66,17 @@ class tm_loop_stats(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class tm_ptc_train_params(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("adam_eps", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class tm_ptc_train_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("reserved", ctypes.c_int), ("loss_first", ctypes.c_double),
+                ("loss_last", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _SIGS = {
@@ -92,6 +103,16 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.POINTER(tm_solve_stats)), _vp]),
     "tm_batch_loops": (ctypes.c_int, [_vp, ctypes.POINTER(tm_loop_params), ctypes.POINTER(_dp),
                                       ctypes.POINTER(tm_loop_stats), _vp]),
+    "tm_ptc_set_weights": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
+    "tm_ptc_get_weights": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
+    "tm_ptc_init_hopping": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                           ctypes.c_double]),
+    "tm_ptc_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "tm_ptc_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _dp, _dp, _dp, _vp]),
+    "tm_ptc_pairs_reserve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "tm_ptc_pairs_add": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "tm_ptc_train": (ctypes.c_int, [_vp, ctypes.POINTER(tm_ptc_train_params),
+                                    ctypes.POINTER(tm_ptc_train_stats), _dp, _vp]),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -202,6 +223,51 @@ class Context:
     def noise(self, out, seed, r, dilution=TM_DIL_NONE, stream=None):
         self._check(tm_noise(self.h, _ptr(out), ctypes.c_uint64(seed), r, dilution,
                              _stream(stream)))
+
+    # ------------------------------------------------------------ learned preconditioner
+    def ptc_set_weights(self, W1, W2):
+        W1 = np.ascontiguousarray(W1, dtype=np.complex128)
+        W2 = np.ascontiguousarray(W2, dtype=np.complex128)
+        assert W1.shape == W2.shape and W1.shape[0] == 9 and W1.shape[2:] == (4, 4), W1.shape
+        self._check(tm_ptc_set_weights(self.h, W1.shape[1], W1.ctypes.data_as(_dp),
+                                       W2.ctypes.data_as(_dp)))
+
+    def ptc_get_weights(self, nc):
+        W1 = np.zeros((9, nc, 4, 4), dtype=np.complex128)
+        W2 = np.zeros_like(W1)
+        self._check(tm_ptc_get_weights(self.h, nc, W1.ctypes.data_as(_dp), W2.ctypes.data_as(_dp)))
+        return W1, W2
+
+    def ptc_init_hopping(self, nc=12, mu_sign=1, seed=0, noise=0.0):
+        self._check(tm_ptc_init_hopping(self.h, nc, mu_sign, ctypes.c_uint64(seed), noise))
+
+    def ptc_apply(self, out, inp, nrhs, stream=None):
+        self._check(tm_ptc_apply(self.h, _ptr(out), _ptr(inp), nrhs, _stream(stream)))
+
+    def ptc_loss_grad(self, r, e, npairs, nc, stream=None):
+        loss = ctypes.c_double()
+        G1 = np.zeros((9, nc, 4, 4), dtype=np.complex128)
+        G2 = np.zeros_like(G1)
+        self._check(tm_ptc_loss_grad(self.h, _ptr(r), _ptr(e), npairs, ctypes.byref(loss),
+                                     G1.ctypes.data_as(_dp), G2.ctypes.data_as(_dp), _stream(stream)))
+        return loss.value, G1, G2
+
+    def ptc_pairs_reserve(self, capacity, store_prec=TM_F32):
+        self._check(tm_ptc_pairs_reserve(self.h, capacity, store_prec))
+
+    def ptc_pairs_add(self, r, e, n, stream=None):
+        self._check(tm_ptc_pairs_add(self.h, _ptr(r), _ptr(e), n, _stream(stream)))
+
+    def ptc_train(self, epochs, batch, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-12, seed=0,
+                  n_pairs=None, stream=None):
+        p = tm_ptc_train_params(epochs, batch, lr, beta1, beta2, adam_eps, ctypes.c_uint64(seed))
+        st = tm_ptc_train_stats()
+        hist = None
+        if n_pairs is not None:
+            hist = np.zeros(epochs * (n_pairs // batch))
+        self._check(tm_ptc_train(self.h, ctypes.byref(p), ctypes.byref(st),
+                                 hist.ctypes.data_as(_dp) if hist is not None else None, _stream(stream)))
+        return st, hist
 
     def contract(self, eta, s, nrhs, estimators, mu_sign=1, stream=None):
         n_est = bin(estimators).count("1")

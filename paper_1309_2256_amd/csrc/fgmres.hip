@@ -1,0 +1,403 @@
+// Restarted flexible GMRES (Saad 1993) on the full system M(mu) x = b in FP64,
+// right-preconditioned by the parallel-transport network (ptc.hip) or by the
+// identity (plain GMRES(m)).  Arnoldi with classical Gram-Schmidt, complex
+// Givens rotations and the small least-squares problem on the device (one
+// thread per right-hand side); the host reads one flag per right-hand side
+// per Arnoldi step to stop.  After each cycle the true residual b - M x is
+// recomputed in FP64 and the cycle restarts from it.
+//
+// Vectors are full fields as two half-lattice FP64 blocks, the even block
+// [nrhs][12][vh] followed by the odd one; the preconditioned directions z_j
+// are kept in FP32 (the precision the network returns them in), so
+// x = x0 + sum_j y_j z_j uses exactly the vectors that M was applied to.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 8;   // basis vectors per multi-dot / multi-axpy launch
+constexpr int kDotBlk = 256;
+constexpr int kMaxM = 32;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <typename SV>
+__device__ __forceinline__ cx<double> ldv(const SV *p, size_t k)
+{
+    return ldT<double>(p, k);
+}
+
+// part[((r*kChunk + i)*2 + h)*nblk + blk] (re, im) = block sums of conj(v_i) w
+// over half h of right-hand side r; grid (nblk, nrhs, 2)
+template <typename SV>
+__global__ __launch_bounds__(kBlock) void k_mdot(const SV *V, size_t vstride, int nb, const double2 *w, size_t n,
+                                                 size_t hs, double2 *part)
+{
+    const int r = blockIdx.y, h = blockIdx.z, nblk = gridDim.x;
+    const size_t base = h * hs + (size_t)r * n;
+    double acc[2 * kChunk];
+#pragma unroll
+    for (int q = 0; q < 2 * kChunk; q++) acc[q] = 0;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)nblk * kBlock) {
+        const double2 wv = w[base + e];
+#pragma unroll
+        for (int i = 0; i < kChunk; i++)
+            if (i < nb) {
+                const cx<double> v = ldv(V, i * vstride + base + e);
+                acc[2 * i] = fma(v.r, wv.x, fma(v.i, wv.y, acc[2 * i]));
+                acc[2 * i + 1] = fma(v.r, wv.y, fma(-v.i, wv.x, acc[2 * i + 1]));
+            }
+    }
+    __shared__ double red[kBlock / 64][2 * kChunk];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 2 * kChunk; q++) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[wv][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kChunk && (int)threadIdx.x < nb) {
+        const int i = threadIdx.x;
+        double re = 0, im = 0;
+        for (int k = 0; k < kBlock / 64; k++) {
+            re += red[k][2 * i];
+            im += red[k][2 * i + 1];
+        }
+        part[(((size_t)r * kChunk + i) * 2 + h) * nblk + blockIdx.x] = make_double2(re, im);
+    }
+}
+
+// out[r*ld + i0 + i] = sum over halves and blocks (fixed order)
+__global__ void k_mdot_finish(const double2 *part, int nb, int nblk, int nrhs, double2 *out, int ld, int i0)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrhs * nb) return;
+    const int r = idx / nb, i = idx % nb;
+    double re = 0, im = 0;
+    for (int h = 0; h < 2; h++)
+        for (int b = 0; b < nblk; b++) {
+            const double2 v = part[(((size_t)r * kChunk + i) * 2 + h) * nblk + b];
+            re += v.x;
+            im += v.y;
+        }
+    out[(size_t)r * ld + i0 + i] = make_double2(re, im);
+}
+
+// w += sign * sum_i coef[r*ld + i0 + i] v_i; grid (blocks, nrhs, 2)
+template <typename SV>
+__global__ __launch_bounds__(kBlock) void k_maxpy(double2 *w, const SV *V, size_t vstride, int nb,
+                                                  const double2 *__restrict__ coef, int ld, int i0, double sign,
+                                                  size_t n, size_t hs)
+{
+    const int r = blockIdx.y, h = blockIdx.z;
+    const size_t base = h * hs + (size_t)r * n;
+    cx<double> cf[kChunk];
+#pragma unroll
+    for (int i = 0; i < kChunk; i++) {
+        const double2 v = i < nb ? coef[(size_t)r * ld + i0 + i] : make_double2(0, 0);
+        cf[i] = {sign * v.x, sign * v.y};
+    }
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        double2 a = w[base + e];
+        cx<double> acc = {a.x, a.y};
+#pragma unroll
+        for (int i = 0; i < kChunk; i++)
+            if (i < nb) cmac(acc, cf[i], ldv(V, i * vstride + base + e));
+        w[base + e] = make_double2(acc.r, acc.i);
+    }
+}
+
+struct GState {
+    double2 *H;      // [nrhs][m+1][m], column j of the rotated Hessenberg matrix
+    double *cs;      // [nrhs][m]
+    double2 *sn;     // [nrhs][m]
+    double2 *g;      // [nrhs][m+1]
+    double2 *dots;   // [nrhs][m+1]: h_0..h_j of the current column, |w|^2 at j+1
+    int *active;     // [nrhs]
+    int *ncol;       // [nrhs] columns of the current cycle in the solution
+    double *res2;    // [nrhs] |g_{ncol}|^2, the residual estimate squared
+    const double *target2;  // [nrhs]
+    double *vscale;  // [2 nrhs] scale of the next basis vector (both halves)
+};
+
+// Arnoldi column j for every right-hand side: rotate, new Givens rotation,
+// residual estimate, convergence flag.  One thread per right-hand side.
+__global__ void k_arnoldi(GState st, int j, int m, int nrhs)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const double2 *d = st.dots + (size_t)r * (m + 1);
+    const double hn = sqrt(fmax(d[j + 1].x, 0.0));
+    const bool act = st.active[r] != 0;
+    const double sc = act && hn > 0 ? 1.0 / hn : 0.0;
+    st.vscale[r] = sc;
+    st.vscale[r + nrhs] = sc;
+    if (!act) return;
+    cx<double> h[kMaxM + 1];
+    for (int i = 0; i <= j; i++) h[i] = {d[i].x, d[i].y};
+    h[j + 1] = {hn, 0};
+    double *cs = st.cs + (size_t)r * m;
+    double2 *sn = st.sn + (size_t)r * m;
+    for (int i = 0; i < j; i++) {
+        const cx<double> s = {sn[i].x, sn[i].y};
+        const cx<double> t = cs[i] * h[i] + s * h[i + 1];
+        h[i + 1] = cs[i] * h[i + 1] - conjg(s) * h[i];
+        h[i] = t;
+    }
+    // G [a; b] = [rho; 0] with G = [[c, s], [-conj(s), c]], c real
+    const cx<double> a = h[j], b = h[j + 1];
+    const double na = sqrt(a.r * a.r + a.i * a.i), nb = sqrt(b.r * b.r + b.i * b.i);
+    const double nn = sqrt(na * na + nb * nb);
+    double c;
+    cx<double> s;
+    if (nn == 0) {
+        c = 1;
+        s = {0, 0};
+    } else if (na == 0) {
+        c = 0;
+        s = {1, 0};
+    } else {
+        c = na / nn;
+        const cx<double> ph = {a.r / na, a.i / na};
+        s = (1.0 / nn) * (ph * conjg(b));
+    }
+    h[j] = c * a + s * b;
+    h[j + 1] = {0, 0};
+    cs[j] = c;
+    sn[j] = make_double2(s.r, s.i);
+    double2 *H = st.H + (size_t)r * (m + 1) * m;
+    for (int i = 0; i <= j + 1; i++) H[(size_t)i * m + j] = make_double2(h[i].r, h[i].i);
+    double2 *g = st.g + (size_t)r * (m + 1);
+    const cx<double> gj = {g[j].x, g[j].y};
+    const cx<double> g1 = {0, 0};
+    const cx<double> nj = c * gj + s * g1, nj1 = c * g1 - conjg(s) * gj;
+    g[j] = make_double2(nj.r, nj.i);
+    g[j + 1] = make_double2(nj1.r, nj1.i);
+    st.ncol[r] = j + 1;
+    st.res2[r] = nj1.r * nj1.r + nj1.i * nj1.i;
+    if (st.res2[r] <= st.target2[r]) st.active[r] = 0;
+}
+
+// y = R^-1 g over the ncol columns of the cycle (zeros beyond); one thread
+// per right-hand side
+__global__ void k_backsolve(GState st, double2 *y, int m, int nrhs)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const int n = st.ncol[r];
+    const double2 *H = st.H + (size_t)r * (m + 1) * m;
+    const double2 *g = st.g + (size_t)r * (m + 1);
+    double2 *yr = y + (size_t)r * m;
+    for (int i = n; i < m; i++) yr[i] = make_double2(0, 0);
+    for (int i = n - 1; i >= 0; i--) {
+        cx<double> acc = {g[i].x, g[i].y};
+        for (int k = i + 1; k < n; k++) {
+            const cx<double> hk = {H[(size_t)i * m + k].x, H[(size_t)i * m + k].y};
+            const cx<double> yk = {yr[k].x, yr[k].y};
+            acc = acc - hk * yk;
+        }
+        const cx<double> d = {H[(size_t)i * m + i].x, H[(size_t)i * m + i].y};
+        const double dd = d.r * d.r + d.i * d.i;
+        const cx<double> q = dd > 0 ? cx<double>{(acc.r * d.r + acc.i * d.i) / dd, (acc.i * d.r - acc.r * d.i) / dd}
+                                    : cx<double>{0, 0};
+        yr[i] = make_double2(q.r, q.i);
+    }
+}
+
+struct Fg {
+    tm_ctx *c;
+    int nrhs, m;
+    size_t n, hs;  // elements per right-hand side per half, per half
+    hipStream_t s;
+    double2 *part;
+};
+
+// out[r*ld + i0 .. i0 + nb) = <v_i, w> for nb basis vectors in chunks
+template <typename SV>
+void mdot(Fg &f, const SV *V, size_t vstride, int nb, const double2 *w, double2 *out, int ld, int i0)
+{
+    for (int c0 = 0; c0 < nb; c0 += kChunk) {
+        const int k = std::min(kChunk, nb - c0);
+        hipLaunchKernelGGL(k_mdot<SV>, dim3(kDotBlk, f.nrhs, 2), dim3(kBlock), 0, f.s, V + c0 * vstride, vstride, k,
+                           w, f.n, f.hs, f.part);
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_mdot_finish, dim3((f.nrhs * k + 63) / 64), dim3(64), 0, f.s, (const double2 *)f.part, k,
+                           kDotBlk, f.nrhs, out, ld, i0 + c0);
+        TM_HIP(hipGetLastError());
+    }
+}
+
+template <typename SV>
+void maxpy(Fg &f, double2 *w, const SV *V, size_t vstride, int nb, const double2 *coef, int ld, double sign)
+{
+    const int blocks = (int)std::min<size_t>((f.n + kBlock - 1) / kBlock, 2048);
+    for (int c0 = 0; c0 < nb; c0 += kChunk) {
+        const int k = std::min(kChunk, nb - c0);
+        hipLaunchKernelGGL(k_maxpy<SV>, dim3(blocks, f.nrhs, 2), dim3(kBlock), 0, f.s, w, V + c0 * vstride, vstride,
+                           k, coef, ld, c0, sign, f.n, f.hs);
+        TM_HIP(hipGetLastError());
+    }
+}
+
+// out = M in on full FP64 fields (halves consecutive)
+void apply_M(Fg &f, double2 *out, const double2 *in, double epsp)
+{
+    tm_ctx *c = f.c;
+    const SpinDiag dh = sd_scalar(-c->kappa), dw = sd_twist(epsp);
+    op_dslash(c, out, in + f.hs, in, f.nrhs, TM_F64, 0, 0, dh, dw, f.s);
+    op_dslash(c, out + f.hs, in, in + f.hs, f.nrhs, TM_F64, 1, 0, dh, dw, f.s);
+}
+
+}  // namespace
+
+SolveOut fgmres_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,
+                       const tm_solve_params &p, hipStream_t s)
+{
+    const double t0 = now_s();
+    const bool ptc = p.solver == TM_FGMRES_PTC;
+    TM_REQUIRE(p.tol > 0 && std::isfinite(p.tol), "tol must be > 0");
+    TM_REQUIRE(p.maxiter > 0, "maxiter must be > 0");
+    TM_REQUIRE(p.mu_sign == 1 || p.mu_sign == -1, "mu_sign must be +1 or -1");
+    TM_REQUIRE(!ptc || c->ptc_nc > 0, "FGMRES with the network needs weights (tm_ptc_set_weights / train)");
+    const int m = p.check_every > 0 ? p.check_every : 16;
+    TM_REQUIRE(m >= 1 && m <= kMaxM, "restart length must be in [1, 32]");
+    const double epsp = eps_of(c, p.mu_sign);
+    Fg f{c, nrhs, m, (size_t)12 * c->geo.vh, (size_t)12 * c->geo.vh * nrhs, s, nullptr};
+    const size_t vs = 2 * f.hs;  // complex elements per full vector (all rhs)
+    f.part = (double2 *)ws_get(c, "fg_part", sizeof(double2) * nrhs * kChunk * 2 * kDotBlk);
+    double2 *V = (double2 *)ws_get(c, "fg_V", sizeof(double2) * vs * (m + 1));
+    float2 *Z = ptc ? (float2 *)ws_get(c, "fg_Z", sizeof(float2) * vs * m) : nullptr;
+    float2 *zin = ptc ? (float2 *)ws_get(c, "fg_zin", sizeof(float2) * vs) : nullptr;
+    double2 *x = (double2 *)ws_get(c, "fg_x", sizeof(double2) * vs);
+    double2 *b = (double2 *)ws_get(c, "fg_b", sizeof(double2) * vs);
+    double2 *w = (double2 *)ws_get(c, "fg_w", sizeof(double2) * vs);
+    double2 *zt = ptc ? (double2 *)ws_get(c, "fg_zt", sizeof(double2) * vs) : nullptr;
+    GState st;
+    st.H = (double2 *)ws_get(c, "fg_H", sizeof(double2) * nrhs * (m + 1) * m);
+    st.cs = (double *)ws_get(c, "fg_cs", sizeof(double) * nrhs * m);
+    st.sn = (double2 *)ws_get(c, "fg_sn", sizeof(double2) * nrhs * m);
+    st.g = (double2 *)ws_get(c, "fg_g", sizeof(double2) * nrhs * (m + 1));
+    st.dots = (double2 *)ws_get(c, "fg_dots", sizeof(double2) * nrhs * (m + 1));
+    st.active = (int *)ws_get(c, "fg_active", sizeof(int) * nrhs);
+    st.ncol = (int *)ws_get(c, "fg_ncol", sizeof(int) * nrhs);
+    st.res2 = (double *)ws_get(c, "fg_res2", sizeof(double) * nrhs);
+    double *target2 = (double *)ws_get(c, "fg_target2", sizeof(double) * nrhs);
+    st.target2 = target2;
+    st.vscale = (double *)ws_get(c, "fg_vscale", sizeof(double) * 2 * nrhs);
+    double2 *y = (double2 *)ws_get(c, "fg_y", sizeof(double2) * nrhs * m);
+    const size_t hb = field_bytes(c, TM_F64, nrhs);
+    copy_field(b, be, hb, s);
+    copy_field(b + f.hs, bo, hb, s);
+    launch_zero(c, x, TM_F64, 2 * nrhs, s);
+
+    std::vector<double> bn2(nrhs), t2(nrhs), beta2(nrhs), res2(nrhs), hscale(2 * nrhs);
+    std::vector<int> iters(nrhs, 0), act(nrhs);
+    std::vector<double2> h_d(nrhs * (m + 1));
+    {
+        mdot(f, b, vs, 1, b, st.dots, m + 1, 0);
+        download(c, h_d.data(), st.dots, sizeof(double2) * nrhs * (m + 1), s);
+        for (int r = 0; r < nrhs; r++) {
+            bn2[r] = h_d[(size_t)r * (m + 1)].x;
+            TM_REQUIRE(std::isfinite(bn2[r]), "NaN/Inf in the source");
+            t2[r] = p.tol * p.tol * bn2[r];
+        }
+        upload(target2, t2.data(), sizeof(double) * nrhs, s);
+    }
+    int restarts = 0, total = 0;
+    bool nan = false;
+    while (true) {
+        // V_0 = b - M x, beta = |V_0|
+        apply_M(f, w, x, epsp);
+        copy_field(V, b, 2 * hb, s);
+        launch_axpby_host(c, V, w, TM_F64, 2 * nrhs, -1.0, 1.0, s);
+        mdot(f, V, vs, 1, V, st.dots, m + 1, 0);
+        download(c, h_d.data(), st.dots, sizeof(double2) * nrhs * (m + 1), s);
+        bool any = false;
+        for (int r = 0; r < nrhs; r++) {
+            beta2[r] = h_d[(size_t)r * (m + 1)].x;
+            if (!std::isfinite(beta2[r])) nan = true;
+            act[r] = beta2[r] > t2[r] ? 1 : 0;
+            any |= act[r] != 0;
+            res2[r] = beta2[r];
+        }
+        if (nan || !any || total >= p.maxiter) break;
+        std::vector<double2> g0((size_t)nrhs * (m + 1), make_double2(0, 0));
+        for (int r = 0; r < nrhs; r++) {
+            const double be_ = std::sqrt(beta2[r]);
+            hscale[r] = hscale[r + nrhs] = act[r] ? 1.0 / be_ : 0.0;
+            g0[(size_t)r * (m + 1)] = make_double2(act[r] ? be_ : 0.0, 0.0);
+        }
+        upload(st.g, g0.data(), sizeof(double2) * g0.size(), s);
+        upload(st.active, act.data(), sizeof(int) * nrhs, s);
+        std::vector<int> zero(nrhs, 0);
+        upload(st.ncol, zero.data(), sizeof(int) * nrhs, s);
+        upload(st.vscale, hscale.data(), sizeof(double) * 2 * nrhs, s);
+        launch_copy_convert(c, V, TM_F64, V, TM_F64, 2 * nrhs, st.vscale, s);
+        int j = 0;
+        for (; j < m && total < p.maxiter; j++) {
+            double2 *vj = V + (size_t)j * vs;
+            // w = M z_j, z_j = N(v_j) (FP32) or v_j
+            if (ptc) {
+                float2 *zj = Z + (size_t)j * vs;
+                launch_copy_convert(c, zin, TM_F32, vj, TM_F64, 2 * nrhs, nullptr, s);
+                ptc_apply_halves(c, zin, zin + f.hs, zj, zj + f.hs, nrhs, s);
+                launch_copy_convert(c, zt, TM_F64, zj, TM_F32, 2 * nrhs, nullptr, s);
+                apply_M(f, w, zt, epsp);
+            } else {
+                apply_M(f, w, vj, epsp);
+            }
+            // classical Gram-Schmidt against v_0..v_j, then |w|^2
+            mdot(f, V, vs, j + 1, w, st.dots, m + 1, 0);
+            maxpy(f, w, V, vs, j + 1, st.dots, m + 1, -1.0);
+            mdot(f, w, vs, 1, w, st.dots, m + 1, j + 1);
+            hipLaunchKernelGGL(k_arnoldi, dim3((nrhs + 63) / 64), dim3(64), 0, s, st, j, m, nrhs);
+            TM_HIP(hipGetLastError());
+            launch_copy_convert(c, V + (size_t)(j + 1) * vs, TM_F64, w, TM_F64, 2 * nrhs, st.vscale, s);
+            total++;
+            for (int r = 0; r < nrhs; r++) iters[r] += act[r];
+            download(c, act.data(), st.active, sizeof(int) * nrhs, s);
+            bool still = false;
+            for (int r = 0; r < nrhs; r++) still |= act[r] != 0;
+            if (!still) {
+                j++;
+                break;
+            }
+        }
+        // x += sum_j y_j z_j
+        hipLaunchKernelGGL(k_backsolve, dim3((nrhs + 63) / 64), dim3(64), 0, s, st, y, m, nrhs);
+        TM_HIP(hipGetLastError());
+        if (ptc)
+            maxpy(f, x, Z, vs, j, y, m, 1.0);
+        else
+            maxpy(f, x, V, vs, j, y, m, 1.0);
+        restarts++;
+    }
+    // solution out; true residual already in beta2 (b - M x of the last x)
+    copy_field(xe, x, hb, s);
+    copy_field(xo, x + f.hs, hb, s);
+    TM_HIP(hipStreamSynchronize(s));
+    SolveOut out;
+    out.st.resize(nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        tm_solve_stats &q = out.st[r];
+        q = tm_solve_stats{};
+        q.iters = iters[r];
+        q.n_reliable = restarts;
+        q.true_rel_res = std::sqrt(beta2[r] / bn2[r]);
+        q.iter_rel_res = q.true_rel_res;
+        q.converged = q.true_rel_res <= p.tol ? 1 : 0;
+        q.seconds = now_s() - t0;
+        if (!q.converged && out.status == TM_OK) out.status = TM_ERR_NOCONV;
+    }
+    if (nan) out.status = TM_ERR_NAN;
+    return out;
+}

@@ -7,6 +7,22 @@
 // eps' = mu_sign * eps
 double eps_of(tm_ctx *c, int mu_sign);
 
+// host helpers: wall clock; synchronous upload; download through the pinned
+// stage (synchronises s); per-RHS |v|^2 on the host; bytes of a half field;
+// asynchronous device copy
+double now_s();
+void upload(void *dev, const void *host, size_t bytes, hipStream_t s);
+void download(tm_ctx *c, void *host, const void *dev, size_t bytes, hipStream_t s);
+std::vector<double> norms_host(tm_ctx *c, const void *v, int prec, int nrhs, hipStream_t s);
+size_t field_bytes(tm_ctx *c, int prec, int nrhs);
+void copy_field(void *dst, const void *src, size_t bytes, hipStream_t s);
+// chiral-basis Gamma_n = gamma_1^n0 gamma_2^n1 gamma_3^n2 gamma_4^n3
+void gamma_n(int n, cx<double> G[4][4]);
+
+// learned preconditioner out = N(in) on FP32 half fields (ptc.hip)
+void ptc_apply_halves(tm_ctx *c, const void *in_e, const void *in_o, void *out_e, void *out_o, int nrhs,
+                      hipStream_t s);
+
 // out = D_hop Hop[in] (+ D_own own) on output parity out_par (see DslashCall)
 void op_dslash(tm_ctx *c, void *out, const void *in, const void *own, int nrhs, int prec, int out_par,
                int dag, SpinDiag dhop, SpinDiag down, hipStream_t s);
@@ -65,6 +81,10 @@ struct Solver {
     void restart(bool first, hipStream_t s);
     void accumulate(hipStream_t s);
 };
+
+// Restarted (flexible) GMRES on the full system (fgmres.hip)
+SolveOut fgmres_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,
+                       const tm_solve_params &p, hipStream_t s);
 
 // Solve M(mu_sign) x = b with b, x given as FP64 half fields (even, odd).
 SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,

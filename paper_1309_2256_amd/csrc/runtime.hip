@@ -8,8 +8,6 @@
 
 #include "runtime.h"
 
-namespace {
-
 double now_s()
 {
     using namespace std::chrono;
@@ -46,6 +44,8 @@ void copy_field(void *dst, const void *src, size_t bytes, hipStream_t s)
     TM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
 }
 
+namespace {
+
 // chiral-basis Dirac matrices gamma_1..gamma_4 (x, y, z, t)
 const cx<double> kGamma[4][4][4] = {
     {{{0, 0}, {0, 0}, {0, 0}, {0, -1}}, {{0, 0}, {0, 0}, {0, -1}, {0, 0}},
@@ -57,6 +57,8 @@ const cx<double> kGamma[4][4][4] = {
     {{{0, 0}, {0, 0}, {1, 0}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}, {1, 0}},
      {{1, 0}, {0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {1, 0}, {0, 0}, {0, 0}}},
 };
+
+}  // namespace
 
 // Gamma_n = gamma_1^n0 gamma_2^n1 gamma_3^n2 gamma_4^n3
 void gamma_n(int n, cx<double> G[4][4])
@@ -75,8 +77,6 @@ void gamma_n(int n, cx<double> G[4][4])
         memcpy(G, T, sizeof(T));
     }
 }
-
-}  // namespace
 
 hipStream_t s_of(tm_ctx *c) { return c->stream; }
 
@@ -446,6 +446,7 @@ SolveOut Solver::finalize(hipStream_t s)
 SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void *bo, int nrhs,
                       const tm_solve_params &p, hipStream_t s)
 {
+    if (p.solver == TM_FGMRES || p.solver == TM_FGMRES_PTC) return fgmres_halves(c, xe, xo, be, bo, nrhs, p, s);
     Solver S;
     S.init(c, xe, xo, be, bo, nrhs, p, s);
     while (!S.done) {
