@@ -16,7 +16,9 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtm.so")
 ARCH = os.environ.get("TM_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
+# -ffp-contract=off: multiply-adds are FMAs only where the source writes
+# fma(), so results do not depend on per-instantiation contraction choices
+FLAGS = ["-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

@@ -140,15 +140,22 @@ __global__ __launch_bounds__(kBlock) void k_finish_alpha(CGScalars *sc, const do
     }
 }
 
-// part layout: [slot 0: |r|^2 for all rhs][slot 1: |rho|^2 for all rhs]
+// part layout: [slot 0: |r|^2 for all rhs][slot 1: |rho|^2 for all rhs].
+// With reliable updates (delta > 0) slot 1 is not used: the Schur residual
+// rho -= alpha q has |rho'|^2 = |rho|^2 - 2 alpha <r, p> + alpha^2 |q|^2
+// = |rho|^2 - alpha |r|^2 (CG: <r, p> = |r|^2, alpha = |r|^2 / |q|^2), a
+// recurrence whose rounding stays far below the delta^2 |rho_ref|^2 it is
+// compared with between two updates (each update resets it to the FP64
+// true residual).
 __global__ __launch_bounds__(kBlock) void k_finish_beta(CGScalars *sc, const double *part, int nblk,
                                                         int nrhs, double delta)
 {
     const int r = blockIdx.x;
     double rr = sum_partials(part, nblk, r);
-    double rho2 = sum_partials(part, nblk, nrhs + r);
+    double rho2 = delta > 0 ? 0.0 : sum_partials(part, nblk, nrhs + r);
     if (threadIdx.x == 0) {
         CGScalars &s = sc[r];
+        if (delta > 0) rho2 = s.active ? fmax(s.rho2 - s.alpha * s.rr, 0.0) : s.rho2;
         if (!finite(rr) || !finite(rho2)) s.bad = 1;
         if (s.active) {
             s.beta = (s.rr > 0) ? rr / s.rr : 0.0;

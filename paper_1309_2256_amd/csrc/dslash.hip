@@ -23,10 +23,10 @@ namespace {
 
 constexpr int kBlock = 256;
 // resident waves per SIMD requested from the compiler (bounds the registers
-// per lane to 512 / waves): one FP64 right-hand side needs ~180 registers,
-// one or two FP32-arithmetic right-hand sides fit in 128
+// per lane to 512 / waves): one FP64 right-hand side fits in ~150 registers,
+// two in 256; one or two FP32-arithmetic right-hand sides fit in 128
 template <typename T, int R>
-constexpr int waves_for() { return sizeof(T) == 8 ? 2 : (R <= 2 ? 4 : 3); }
+constexpr int waves_for() { return sizeof(T) == 8 ? (R == 1 ? 3 : 2) : (R <= 2 ? 4 : 3); }
 
 // 16-byte aligned so that an array of records keeps every complex field
 // naturally aligned
@@ -144,18 +144,21 @@ __device__ __forceinline__ void hop_dir(cx<T> acc[12], const cx<T> W[9], const r
         acc[3 + c].r += w1[c].r;
         acc[3 + c].i += w1[c].i;
         cx<T> &l0 = acc[6 + c], &l1 = acc[9 + c];
+        // explicit FMAs: the rounding must not depend on what the compiler
+        // contracts in a given instantiation (results are bit-identical for
+        // every right-hand-side tile)
         if (MU == 0) {          // lower = -S (i w1, i w0)
-            l0.r += s * w1[c].i; l0.i -= s * w1[c].r;
-            l1.r += s * w0[c].i; l1.i -= s * w0[c].r;
+            l0.r = fma(s, w1[c].i, l0.r); l0.i = fma(-s, w1[c].r, l0.i);
+            l1.r = fma(s, w0[c].i, l1.r); l1.i = fma(-s, w0[c].r, l1.i);
         } else if (MU == 1) {   // lower = -S (w1, -w0)
-            l0.r -= s * w1[c].r; l0.i -= s * w1[c].i;
-            l1.r += s * w0[c].r; l1.i += s * w0[c].i;
+            l0.r = fma(-s, w1[c].r, l0.r); l0.i = fma(-s, w1[c].i, l0.i);
+            l1.r = fma(s, w0[c].r, l1.r); l1.i = fma(s, w0[c].i, l1.i);
         } else if (MU == 2) {   // lower = -S (i w0, -i w1)
-            l0.r += s * w0[c].i; l0.i -= s * w0[c].r;
-            l1.r -= s * w1[c].i; l1.i += s * w1[c].r;
+            l0.r = fma(s, w0[c].i, l0.r); l0.i = fma(-s, w0[c].r, l0.i);
+            l1.r = fma(-s, w1[c].i, l1.r); l1.i = fma(s, w1[c].r, l1.i);
         } else {                // lower = -S (w0, w1)
-            l0.r -= s * w0[c].r; l0.i -= s * w0[c].i;
-            l1.r -= s * w1[c].r; l1.i -= s * w1[c].i;
+            l0.r = fma(-s, w0[c].r, l0.r); l0.i = fma(-s, w0[c].i, l0.i);
+            l1.r = fma(-s, w1[c].r, l1.r); l1.i = fma(-s, w1[c].i, l1.i);
         }
     }
 }
@@ -172,10 +175,11 @@ typedef unsigned v2u __attribute__((__vector_size__(2 * sizeof(unsigned))));
 typedef unsigned v4u __attribute__((__vector_size__(4 * sizeof(unsigned))));
 // descriptor word 3 for raw (untyped) access on gfx9-class parts
 constexpr int kRsrcFlags = 0x00020000;
-// cache-policy operand: non-temporal (streaming) hint for data that is not
-// re-read by this launch (outputs) or only by the adjacent right-hand-side
-// groups of the same site block (links), so it does not displace the
-// neighbour spinors in L2
+// cache-policy operand of the output stores: non-temporal (streaming) hint,
+// outputs are not re-read by this launch.  Links are loaded with the default
+// policy: the right-hand-side groups of a site block (adjacent workgroups on
+// one XCD) read them again, and a streaming hint on them raised the fetched
+// bytes by a quarter.
 constexpr int kNT = 2;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, size_t bytes)
@@ -216,7 +220,7 @@ struct BufIO<double2> {
     template <typename T>
     __device__ __forceinline__ static cx<T> ldlink(rsrc_t r, int voff, int soff)
     {
-        D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kNT));
+        D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
         return {(T)v.x, (T)v.y};
     }
     __device__ __forceinline__ static rawc<double> ldraw(rsrc_t r, int voff, int soff)
@@ -242,7 +246,7 @@ struct BufIO<float2> {
     template <typename T>
     __device__ __forceinline__ static cx<T> ldlink(rsrc_t r, int voff, int soff)
     {
-        F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNT));
+        F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
         return {(T)v.x, (T)v.y};
     }
     __device__ __forceinline__ static rawc<float> ldraw(rsrc_t r, int voff, int soff)
@@ -367,7 +371,8 @@ __device__ __forceinline__ double norm2c(cx<T> v)
 //   EPI_NORM   as EPI_STORE, plus per-block partial |out|^2 per right-hand side
 //   EPI_CG     s = D_hop Hop[in] + D_own q (own = q); then r -= alpha s,
 //              rho -= alpha q in place (s is never stored), partial |r|^2 and
-//              |rho|^2 -- the last half of Ahat^dag q fused with the CG updates
+//              |rho|^2 -- the last half of Ahat^dag q fused with the CG updates;
+//              rho = null: r only (the solver follows |rho|^2 by recurrence)
 enum { EPI_STORE = 0, EPI_NORM = 1, EPI_CG = 2 };
 
 // Block order: see map_block.
@@ -437,27 +442,44 @@ __device__ __forceinline__ void dslash_block(const DParams<T> &a, int bhw, int n
         if constexpr (EPI == EPI_CG) alpha = (T)a.sc[r0 + rr].alpha;
 #pragma unroll
         for (int q = 0; q < NQ; q++) nrm[rr][q] = 0;
+        // all loads of this right-hand side first, then arithmetic and
+        // stores: the stores may alias the loaded fields as far as the
+        // compiler knows, so interleaving them would serialise the loads
+        cx<T> o[12], rl[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            o[k] = {0, 0};
+            if (OWN) o[k] = BufIO<SS>::template ld<T>(ownr, vo, k * vb);
+            if constexpr (EPI == EPI_CG) rl[k] = BufIO<SS>::template ld<T>(rr_r, vo, k * vb);
+        }
+        const bool track_rho = EPI == EPI_CG && a.rho != nullptr;  // uniform
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             cx<T> v = (k < 6 ? a.hop_u : a.hop_l) * acc[rr][k];
-            cx<T> o = {0, 0};
-            if (OWN) {
-                o = BufIO<SS>::template ld<T>(ownr, vo, k * vb);
-                v = v + (k < 6 ? a.own_u : a.own_l) * o;
-            }
+            if (OWN) v = v + (k < 6 ? a.own_u : a.own_l) * o[k];
             if constexpr (EPI == EPI_CG) {
-                cx<T> rv = BufIO<SS>::template ld<T>(rr_r, vo, k * vb) - alpha * v;
-                cx<T> hv = BufIO<SS>::template ld<T>(rho_r, vo, k * vb) - alpha * o;
+                const cx<T> rv = rl[k] - alpha * v;
                 if (valid) {
                     BufIO<SS>::template st<T>(rr_r, vo, k * vb, rv);
-                    BufIO<SS>::template st<T>(rho_r, vo, k * vb, hv);
                     nrm[rr][0] += norm2c(stored<SS>(rv));
-                    nrm[rr][1] += norm2c(stored<SS>(hv));
                 }
             } else {
                 if (valid) {
                     BufIO<SS>::template st<T>(outr, vo, k * vb, v);
                     if constexpr (EPI == EPI_NORM) nrm[rr][0] += norm2c(stored<SS>(v));
+                }
+            }
+        }
+        if (track_rho) {
+            cx<T> hl[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) hl[k] = BufIO<SS>::template ld<T>(rho_r, vo, k * vb);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const cx<T> hv = hl[k] - alpha * o[k];
+                if (valid) {
+                    BufIO<SS>::template st<T>(rho_r, vo, k * vb, hv);
+                    nrm[rr][1] += norm2c(stored<SS>(hv));
                 }
             }
         }
@@ -582,14 +604,24 @@ void launch_t(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     TM_HIP(hipGetLastError());
 }
 
+// Right-hand sides per thread that fit the register budget: FP32 arithmetic
+// 1..3 (4 or more exceed 3 resident waves and spill), FP64 1..2
+template <typename T>
+constexpr int max_tile() { return sizeof(T) == 8 ? 2 : 3; }
+
 template <typename SS, typename LS, typename T>
 void launch_r(tm_ctx *c, const DslashCall &dc, int R, hipStream_t s)
 {
-    switch (R) {
-    case 3: launch_t<SS, LS, T, 3>(c, dc, s); break;
-    case 2: launch_t<SS, LS, T, 2>(c, dc, s); break;
-    default: launch_t<SS, LS, T, 1>(c, dc, s);
+    if (R == 3) {
+        if constexpr (max_tile<T>() >= 3) {
+            launch_t<SS, LS, T, 3>(c, dc, s);
+            return;
+        }
     }
+    if (R >= 2)
+        launch_t<SS, LS, T, 2>(c, dc, s);
+    else
+        launch_t<SS, LS, T, 1>(c, dc, s);
 }
 
 // Right-hand sides per thread (each loaded link serves R spinors).  The first
@@ -598,55 +630,52 @@ void launch_r(tm_ctx *c, const DslashCall &dc, int R, hipStream_t s)
 template <typename SS, typename LS, typename T>
 void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 {
-    if constexpr (std::is_same<T, double>::value) {
-        launch_t<SS, LS, T, 1>(c, dc, s);
-    } else {
-        const int n = dc.nrhs;
-        const auto key = std::make_pair(dc.spinor_prec, n);
-        auto it = c->rhs_tile.find(key);
-        if (it != c->rhs_tile.end()) {
-            launch_r<SS, LS, T>(c, dc, it->second, s);
-            return;
-        }
-        int fixed = 0;
-        if (const char *e = getenv("TM_DSLASH_RHS_TILE")) fixed = atoi(e);
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        TM_HIP(hipStreamIsCapturing(s, &cs));
-        const int def = n % 2 == 0 ? 2 : 1;
-        if (fixed > 0 && n % fixed == 0) {
-            c->rhs_tile[key] = fixed;
-        } else if (dc.epi != 0 || cs != hipStreamCaptureStatusNone || n == 1) {
-            launch_r<SS, LS, T>(c, dc, def, s);  // tune on a later plain launch
-            return;
-        } else {
-            hipEvent_t e0, e1;
-            TM_HIP(hipEventCreate(&e0));
-            TM_HIP(hipEventCreate(&e1));
-            float best = 1e30f;
-            int bestR = def;
-            // 4 or more right-hand sides per thread exceed the register
-            // budget of 3 resident waves and spill
-            for (int R : {1, 2, 3}) {
-                if (n % R) continue;
-                launch_r<SS, LS, T>(c, dc, R, s);  // warm
-                TM_HIP(hipEventRecord(e0, s));
-                launch_r<SS, LS, T>(c, dc, R, s);
-                launch_r<SS, LS, T>(c, dc, R, s);
-                TM_HIP(hipEventRecord(e1, s));
-                TM_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                TM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
-                    best = ms;
-                    bestR = R;
-                }
-            }
-            TM_HIP(hipEventDestroy(e0));
-            TM_HIP(hipEventDestroy(e1));
-            c->rhs_tile[key] = bestR;
-        }
-        launch_r<SS, LS, T>(c, dc, c->rhs_tile[key], s);
+    const int n = dc.nrhs;
+    const auto key = std::make_pair(dc.spinor_prec, n);
+    auto it = c->rhs_tile.find(key);
+    if (it != c->rhs_tile.end()) {
+        launch_r<SS, LS, T>(c, dc, it->second, s);
+        return;
     }
+    int fixed = 0;
+    if (const char *e = getenv("TM_DSLASH_RHS_TILE")) fixed = atoi(e);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TM_HIP(hipStreamIsCapturing(s, &cs));
+    const int def = sizeof(T) == 8 ? 1 : (n % 2 == 0 ? 2 : 1);
+    // repeated launches must give the same result: no fused update, output
+    // distinct from both inputs
+    const bool repeatable = dc.epi == 0 && dc.out != dc.in && dc.out != dc.own;
+    if (fixed > 0 && fixed <= max_tile<T>() && n % fixed == 0) {
+        c->rhs_tile[key] = fixed;
+    } else if (!repeatable || cs != hipStreamCaptureStatusNone || n == 1) {
+        launch_r<SS, LS, T>(c, dc, def, s);  // tune on a later plain launch
+        return;
+    } else {
+        hipEvent_t e0, e1;
+        TM_HIP(hipEventCreate(&e0));
+        TM_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        int bestR = def;
+        for (int R = 1; R <= max_tile<T>(); R++) {
+            if (n % R) continue;
+            launch_r<SS, LS, T>(c, dc, R, s);  // warm
+            TM_HIP(hipEventRecord(e0, s));
+            launch_r<SS, LS, T>(c, dc, R, s);
+            launch_r<SS, LS, T>(c, dc, R, s);
+            TM_HIP(hipEventRecord(e1, s));
+            TM_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            TM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bestR = R;
+            }
+        }
+        TM_HIP(hipEventDestroy(e0));
+        TM_HIP(hipEventDestroy(e1));
+        c->rhs_tile[key] = bestR;
+    }
+    launch_r<SS, LS, T>(c, dc, c->rhs_tile[key], s);
 }
 
 template <typename SS, typename LS, typename T, int R>

@@ -47,6 +47,7 @@ struct CGWork {
     int xprec = 0;
     CGScalars *dsc = nullptr;
     double *partq = nullptr, *partb = nullptr;
+    bool rho_vec = true;  // the fused update also updates the vector rho
 };
 
 // State of one solve of M x = b on FP64 half fields: init, then iterations

@@ -183,7 +183,7 @@ DslashCall stage_call(tm_ctx *c, const CGWork &w, double epsp, int stage)
         dc.d_hop = sd_mul(sd_scalar(k), sd_gamma5());
         dc.epi = 2;
         dc.r = w.r;
-        dc.rho = w.rho;
+        dc.rho = w.rho_vec ? w.rho : nullptr;
         dc.sc = w.dsc;
         dc.part = w.partb;
         break;
@@ -244,6 +244,10 @@ void Solver::init(tm_ctx *ctx, void *xe_, void *xo_, const void *be_, const void
     w = CGWork{};
     w.nrhs = nrhs;
     w.prec = lp;
+    // with reliable updates |rho|^2 follows a scalar recurrence between
+    // updates; plain and truncated solves keep the vector (the recurrence
+    // would lose the residual below ~1e-7 of its start to cancellation)
+    w.rho_vec = p.solver != TM_CG_MIXED;
     w.dsc = (CGScalars *)ws_get(c, "s_sc", sizeof(CGScalars) * nrhs);
     w.partq = (double *)ws_get(c, "s_partq", sizeof(double) * nsb * nrhs);
     w.partb = (double *)ws_get(c, "s_partb", sizeof(double) * nsb * nrhs * 2);
@@ -296,25 +300,43 @@ void Solver::restart(bool first, hipStream_t s)
 {
     const double nel = 12.0 * c->geo.vh;
     const size_t fl = field_bytes(c, lp, nrhs);
-    std::vector<double> hscale(nrhs);
-    op_schur_dag(c, r64, rho64, t64, nrhs, TM_F64, epsp, s);
-    std::vector<double> nr = norms_host(c, r64, TM_F64, nrhs, s);
+    std::vector<double> hscale(nrhs), sig_new(nrhs);
     std::vector<double> nrho = norms_host(c, rho64, TM_F64, nrhs, s);
-    std::vector<double> sig_new(nrhs);
-    for (int r = 0; r < nrhs; r++) {
-        sig_new[r] = nr[r] > 0 ? std::sqrt(nel / nr[r]) : 1.0;
-        if (!std::isfinite(sig_new[r])) sig_new[r] = 1.0;
-    }
-    if (!first) {
+    auto unit_scale = [&](double n2) {
+        const double v = n2 > 0 ? std::sqrt(nel / n2) : 1.0;
+        return std::isfinite(v) ? v : 1.0;
+    };
+    if (first) {
+        // r = Ahat^dag rho in FP64, both scaled to unit RMS of r
+        op_schur_dag(c, r64, rho64, t64, nrhs, TM_F64, epsp, s);
+        std::vector<double> nr = norms_host(c, r64, TM_F64, nrhs, s);
+        for (int r = 0; r < nrhs; r++) sig_new[r] = unit_scale(nr[r]);
+        for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r];
+        upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+        launch_copy_convert(c, w.r, lp, r64, TM_F64, nrhs, dscale, s);
+        launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
+        copy_field(w.p, w.r, fl, s);
+    } else {
+        // the true residual rho (FP64) enters the low-precision iteration at
+        // unit RMS; r = Ahat^dag rho is formed at the iteration's precision
+        // (the FP64 part of the update is the residual itself), then both
+        // are rescaled to unit RMS of r and p follows the new scale
+        std::vector<double> srho(nrhs);
+        for (int r = 0; r < nrhs; r++) srho[r] = unit_scale(nrho[r]);
+        upload(dscale, srho.data(), sizeof(double) * nrhs, s);
+        launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
+        op_schur_dag(c, w.r, w.rho, w.tmp, nrhs, lp, epsp, s);
+        std::vector<double> nrl = norms_host(c, w.r, lp, nrhs, s);
+        for (int r = 0; r < nrhs; r++) sig_new[r] = unit_scale(nrl[r] / (srho[r] * srho[r]));
+        for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r] / srho[r];
+        upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+        launch_copy_convert(c, w.r, lp, w.r, lp, nrhs, dscale, s);
+        upload(dscale, sig_new.data(), sizeof(double) * nrhs, s);
+        launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
         for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r] / sigma[r];
         upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
         launch_copy_convert(c, w.p, lp, w.p, lp, nrhs, dscale, s);
     }
-    for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r];
-    upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
-    launch_copy_convert(c, w.r, lp, r64, TM_F64, nrhs, dscale, s);
-    launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
-    if (first) copy_field(w.p, w.r, fl, s);
     launch_zero(c, w.x, TM_F32, nrhs, s);
     std::vector<double> rr = norms_host(c, w.r, lp, nrhs, s);
     std::vector<double> rho2 = norms_host(c, w.rho, lp, nrhs, s);

@@ -8,6 +8,7 @@
 #include <map>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "tm.h"
@@ -167,8 +168,17 @@ __device__ __forceinline__ cx<T> ldT(const S *p, size_t k)
 template <typename T, typename S>
 __device__ __forceinline__ void stT(S *p, size_t k, cx<T> v)
 {
-    using R = typename StoreTraits<S>::real;
-    StoreTraits<S>::st(p, k, cx<R>{(R)v.r, (R)v.i});
+    if constexpr (std::is_same<S, h2>::value && std::is_same<T, double>::value) {
+        // one rounding FP64 -> binary16 (not through FP32, whose rounding
+        // could move a value onto a binary16 tie)
+        h2 o;
+        o.x = (_Float16)v.r;
+        o.y = (_Float16)v.i;
+        p[k] = o;
+    } else {
+        using R = typename StoreTraits<S>::real;
+        StoreTraits<S>::st(p, k, cx<R>{(R)v.r, (R)v.i});
+    }
 }
 
 static inline size_t prec_bytes(int prec)
