@@ -35,6 +35,11 @@ def main():
     ap.add_argument("--dslash-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-ptc", action="store_true",
+                    help="skip the learned-preconditioner comparison on 32^3x64")
+    ap.add_argument("--ptc-pairs", type=int, default=4096)
+    ap.add_argument("--ptc-rhs", type=int, default=4,
+                    help="right-hand sides of the FGMRES runs (memory: ~12 GB each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the workload (one 32^3x64 lattice, noise vectors "
@@ -202,14 +207,136 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_dslash<h2,float2,float,2,0,0> (R_oo^-1 H_oe, 12 RHS)",
+            "kernel": "k_dslash (R_oo^-1 H_oe, 12 RHS FP16, autotuned RHS tile)",
             "avg_launch_us": dslash_s * 1e6, "algorithmic_bytes_per_launch": alg_bytes,
             "copy_gb_s": copy_gbs, "frac_of_copy": achieved / copy_gbs,
         },
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    traffic = dslash_traffic(alg_bytes)
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic["bytes"]
+        out["roofline"]["traffic_source"] = traffic["source"]
+        out["roofline"]["kernel"] = traffic["kernel"]
     ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_ptc:
+        out["ptc_c5"] = ptc_leg(args, P, S, torch, dev)
+    print(json.dumps(out), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_rinv_hop_12rhs_fp16_c3_traffic.json")
+
+
+def dslash_traffic(alg_bytes):
+    """HBM bytes per launch of the timed Dslash from the committed counter
+    summary (FETCH_SIZE x its copy calibration + WRITE_SIZE x its), or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    src = open(os.path.join(ROOT, "paper_1309_2256_amd", "csrc", "dslash.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["dslash_hip_sha256"]:
+        return None
+    b = (rec["fetch_kib_per_dispatch"] * rec["fetch_factor"] +
+         rec["write_kib_per_dispatch"] * rec["write_factor"]) * 1024
+    return {"bytes": b, "kernel": rec["kernel"],
+            "source": os.path.relpath(TRAFFIC_FILE, ROOT) + " (%.2f x algorithmic)" % (b / alg_bytes)}
+
+
+def ptc_leg(args, P, S, torch, dev):
+    """Learned preconditioner on the 32^3x64 lattice with 16^3x32-lattice
+    physics (links exp(i 0.2 H), kappa 0.124, 2 kappa mu 0.0028): train the
+    parallel-transport network on (eta, M^-1 eta) pairs from 16^3x32 solves
+    (Z4 spin-colour-diluted sources, mixed CG to 1e-6, BF16 pair store),
+    then solve 32^3x64 right-hand sides to 1e-9 with FGMRES(16) + network,
+    FGMRES(16) without it, and the mixed-precision CG."""
+    def log(msg):
+        print("[bench/ptc] " + msg, file=sys.stderr, flush=True)
+
+    def make(name):
+        cfg = S.CONFIGS[name]
+        U = torch.from_numpy(S.gauge_links(cfg["L"], cfg["eps_links"], cfg["seed"])).to(dev)
+        c = P.Context(cfg["L"], cfg["kappa"], cfg["two_kappa_mu"])
+        c.set_gauge(U)
+        torch.cuda.synchronize()
+        return c, cfg
+
+    res = {}
+    c2, cfg2 = make("c2")
+    V2 = int(np.prod(cfg2["L"]))
+    npairs = args.ptc_pairs // 12 * 12
+    c2.ptc_pairs_reserve(npairs, P.TM_BF16)
+    eta = torch.zeros((12, V2, 4, 3), dtype=torch.complex128, device=dev)
+    x = torch.zeros_like(eta)
+    lp = P.solve_params(tol=1e-6, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+    t0 = time.perf_counter()
+    for k in range(npairs // 12):
+        c2.noise(eta, 9000, k, P.TM_DIL_SPIN_COLOUR)
+        c2.solve(x, eta, 12, lp)
+        c2.ptc_pairs_add(eta, x, 12)
+    torch.cuda.synchronize()
+    res["pairs"] = npairs
+    res["pairs_seconds"] = time.perf_counter() - t0
+    log("%d pairs in %.1fs" % (npairs, res["pairs_seconds"]))
+    del eta, x
+    c2.ptc_init_hopping(nc=12, mu_sign=1, seed=1, noise=1e-3)
+    W1h, W2h = c2.ptc_get_weights(12)
+    st, _ = c2.ptc_train(epochs=2, batch=16, lr=1e-3, seed=3)
+    res["train"] = {"steps": st.steps, "batch": 16, "epochs": 2, "loss_first_epoch": st.loss_first,
+                    "loss_last_epoch": st.loss_last, "seconds": st.seconds}
+    log("trained: loss %.4f -> %.4f in %.1fs" % (st.loss_first, st.loss_last, st.seconds))
+    W1t, W2t = c2.ptc_get_weights(12)
+    c2.close()
+    del c2
+    torch.cuda.empty_cache()
+
+    c5, cfg5 = make("c5")
+    V5 = int(np.prod(cfg5["L"]))
+    b = torch.zeros((12, V5, 4, 3), dtype=torch.complex128, device=dev)
+    x = torch.zeros_like(b)
+
+    def run(name, params, nrhs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        status, stats = c5.solve(x[:nrhs], b[:nrhs], nrhs, params, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        ok = sum(1 for s_ in stats if s_.true_rel_res <= 1e-9)
+        r = {"rhs": nrhs, "verified": ok, "solves_per_s": ok / dt,
+             "iters_mean": float(np.mean([s_.iters for s_ in stats])),
+             "max_true_rel_res": max(s_.true_rel_res for s_ in stats), "seconds": dt}
+        log("%s: %d/%d verified, %.1f iterations, %.2fs" % (name, ok, nrhs, r["iters_mean"], dt))
+        return r
+
+    # mixed CG on all 24 right-hand sides (2 noises x 12), 12 per call
+    tot, n_ok, its = 0.0, 0, []
+    for k in range(2):
+        c5.noise(b, 505, k, P.TM_DIL_SPIN_COLOUR)
+        r = run("mixed CG noise %d" % k, P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED,
+                                                         inner_prec=P.TM_F16), 12)
+        tot += r["seconds"]
+        n_ok += r["verified"]
+        its.append(r["iters_mean"])
+    res["mixed_cg"] = {"rhs": 24, "verified": n_ok, "solves_per_s": n_ok / tot,
+                       "iters_mean": float(np.mean(its)), "seconds": tot}
+    c5.noise(b, 505, 0, P.TM_DIL_SPIN_COLOUR)
+    n = min(args.ptc_rhs, 12)
+    fg = dict(tol=1e-9, check_every=16, maxiter=3000)
+    c5.ptc_set_weights(W1t, W2t)
+    res["fgmres_ptc_trained"] = run("FGMRES(16)+network (trained)",
+                                    P.solve_params(solver=P.TM_FGMRES_PTC, **fg), n)
+    c5.ptc_set_weights(W1h, W2h)
+    res["fgmres_ptc_hopping_init"] = run("FGMRES(16)+network (hopping-expansion weights)",
+                                         P.solve_params(solver=P.TM_FGMRES_PTC, **fg), n)
+    res["fgmres_no_net"] = run("FGMRES(16) without network", P.solve_params(solver=P.TM_FGMRES, **fg), n)
+    res["workload"] = ("32^3x64, links exp(i 0.2 H) seed 105, kappa 0.124, 2 kappa mu 0.0028; "
+                       "Z4 noise seed 505 spin-colour diluted; FGMRES legs on the first %d "
+                       "dilutions of noise 0" % n)
+    c5.close()
+    return res
 
 
 if __name__ == "__main__":
