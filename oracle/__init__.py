@@ -70,6 +70,8 @@ def lib():
                                   dp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
         L.or_transport.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, ctypes.c_int]
         L.or_ptc_forward.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp]
+        L.or_ptc_at.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp,
+                                ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
         L.or_ptc_loss_grad.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, dp,
                                        dp]
         L.or_ptc_loss_grad.restype = ctypes.c_double
@@ -346,6 +348,18 @@ def ptc_forward(L, t_bc, U, W1, W2, psi):
     U, psi = _links(L, U), _spinor(L, psi)
     out = np.empty_like(psi)
     lib().or_ptc_forward(_L(L), int(t_bc), _p(U), nc, _p(W1), _p(W2), _p(psi), _p(out))
+    return out
+
+
+def ptc_at(L, t_bc, U, W1, W2, psi, sites):
+    """N(psi) at the given sites only (site by site from the definition) -> (n, 4, 3)."""
+    nc = W1.shape[1]
+    W1, W2 = _weights(W1, nc), _weights(W2, nc)
+    U, psi = _links(L, U), _spinor(L, psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int_)
+    out = np.empty((len(sites), 4, 3), dtype=np.complex128)
+    lib().or_ptc_at(_L(L), int(t_bc), _p(U), nc, _p(W1), _p(W2), _p(psi),
+                    sites.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(sites), _p(out))
     return out
 
 

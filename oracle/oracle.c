@@ -881,6 +881,78 @@ void or_ptc_forward(const int L[4], int t_bc, const double *U, int nc, const dou
     free(phi);
 }
 
+/* Path k at site x: neighbour y, link W (row-major) to apply (daggered for
+ * backward hops) and boundary phase; k = 0 is the identity (y = x). */
+static long path_link(const int L[4], int t_bc, const cplx *U, int k, long x, cplx W[9], double *ph)
+{
+    long V = vol(L);
+    if (k == 0) {
+        for (int e = 0; e < 9; e++) W[e] = (e % 4 == 0) ? 1.0 : 0.0;
+        *ph = 1.0;
+        return x;
+    }
+    const int mu = (k - 1) & 3, fwd = k <= 4;
+    long y = step(L, t_bc, x, mu, fwd ? +1 : -1, ph);
+    const cplx *Um = fwd ? U + 9 * ((long)mu * V + x) : U + 9 * ((long)mu * V + y);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) W[3 * i + j] = fwd ? Um[3 * i + j] : conj(Um[3 * j + i]);
+    return y;
+}
+
+/* out += S (W f) * ph for one site: colour link W, then spin matrix S */
+static void site_acc(const cplx *S, const cplx W[9], double ph, const cplx f[12], cplx out[12])
+{
+    cplx t[12];
+    for (int a = 0; a < 4; a++)
+        for (int i = 0; i < 3; i++) {
+            cplx v = 0;
+            for (int j = 0; j < 3; j++) v += W[3 * i + j] * f[3 * a + j];
+            t[3 * a + i] = ph * v;
+        }
+    for (int a = 0; a < 4; a++)
+        for (int c = 0; c < 3; c++) {
+            cplx v = 0;
+            for (int b = 0; b < 4; b++) v += S[4 * a + b] * t[3 * b + c];
+            out[3 * a + c] += v;
+        }
+}
+
+/*
+ * The same two layers as or_ptc_forward, evaluated only at the given sites
+ * straight from the definition (for lattices where whole-lattice hidden
+ * fields are too large): N(psi)(x) = sum_{k,c} W2[k][c] (T_k phi_c)(x) with
+ * phi_c(y) = sum_k' W1[k'][c] (T_k' psi)(y) formed at the nine sites y the
+ * paths of x reach.  out: [nsites][12].
+ */
+void or_ptc_at(const int L[4], int t_bc, const double *Ud, int nc, const double *W1d, const double *W2d,
+               const double *ind, const long *sites, long nsites, double *outd)
+{
+    const cplx *U = (const cplx *)Ud, *W1 = (const cplx *)W1d, *W2 = (const cplx *)W2d;
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+#pragma omp parallel for schedule(dynamic)
+    for (long n = 0; n < nsites; n++) {
+        const long x = sites[n];
+        cplx acc[12] = {0};
+        for (int k = 0; k < 9; k++) {
+            cplx W[9];
+            double ph;
+            const long y = path_link(L, t_bc, U, k, x, W, &ph);
+            for (int c = 0; c < nc; c++) {
+                cplx phi[12] = {0};
+                for (int kp = 0; kp < 9; kp++) {
+                    cplx W1l[9];
+                    double ph1;
+                    const long z = path_link(L, t_bc, U, kp, y, W1l, &ph1);
+                    site_acc(W1 + 16 * (kp * nc + c), W1l, ph1, in + 12 * z, phi);
+                }
+                site_acc(W2 + 16 * (k * nc + c), W, ph, phi, acc);
+            }
+        }
+        for (int e = 0; e < 12; e++) out[12 * n + e] = acc[e];
+    }
+}
+
 /*
  * Loss of one pair, l = |N(in) - e|^2 / |e|^2, and its gradient with respect
  * to the real and imaginary parts of every weight, accumulated into G1, G2 as

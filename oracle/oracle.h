@@ -40,6 +40,8 @@ void or_transport(const int L[4], int t_bc, const double *U, int k, const double
                   int adj);
 void or_ptc_forward(const int L[4], int t_bc, const double *U, int nc, const double *W1,
                     const double *W2, const double *in, double *out);
+void or_ptc_at(const int L[4], int t_bc, const double *U, int nc, const double *W1, const double *W2,
+               const double *in, const long *sites, long nsites, double *out);
 double or_ptc_loss_grad(const int L[4], int t_bc, const double *U, int nc, const double *W1,
                         const double *W2, const double *in, const double *e, double *G1,
                         double *G2);

@@ -184,3 +184,46 @@ def test_fgmres_argument_checks():
                           allow_noconv=True)
     assert st == P.TM_ERR_NOCONV and stats[0].converged == 0 and stats[0].iters == 3
     ctx.close()
+
+
+@pytest.fixture(scope="module")
+def c5():
+    cfg = S.CONFIGS["c5"]
+    L = cfg["L"]
+    U = S.gauge_links(L, cfg["eps_links"], cfg["seed"])
+    ctx = P.Context(L, cfg["kappa"], cfg["two_kappa_mu"])
+    ctx.set_gauge(cuda(U))
+    yield dict(L=L, cfg=cfg, U=U, ctx=ctx)
+    ctx.close()
+
+
+def test_c5_ptc_forward_sampled_sites(c5):
+    """32^3x64 (the FGMRES workload): the network at 64 sampled sites against
+    the oracle's site-by-site evaluation of the two layers."""
+    L, U, ctx = c5["L"], c5["U"], c5["ctx"]
+    rng = np.random.default_rng(361)
+    W1, W2 = rand_weights(rng, 12), rand_weights(rng, 12)
+    ctx.ptc_set_weights(W1, W2)
+    f = S.random_spinor(L, 362, 1)
+    out = torch.zeros_like(cuda(f))
+    ctx.ptc_apply(out, cuda(f), 1)
+    got = host(out)[0]
+    V = int(np.prod(L))
+    sites = np.sort(rng.choice(V, 64, replace=False))
+    sites[:2] = [0, V - 1]
+    ref = O.ptc_at(L, -1, U, W1, W2, f[0], sites)
+    assert rel(got[sites], ref) < 2e-5
+
+
+def test_c5_fgmres_network_true_residual(c5):
+    """32^3x64: FGMRES(16) with the network (hopping-expansion weights) to
+    1e-9; the oracle recomputes |b - M x| / |b| in FP64 on the host."""
+    L, U, ctx, cfg = c5["L"], c5["U"], c5["ctx"], c5["cfg"]
+    ctx.ptc_init_hopping(nc=12, mu_sign=1)
+    b = S.random_spinor(L, 363, 1)
+    x = torch.zeros_like(cuda(b))
+    _, st = ctx.solve(x, cuda(b), 1, P.solve_params(tol=1e-9, solver=P.TM_FGMRES_PTC, check_every=16,
+                                                     maxiter=3000))
+    xh = host(x)[0]
+    res = np.linalg.norm(b[0] - O.apply_M(L, cfg["kappa"], cfg["two_kappa_mu"], -1, U, xh)) / np.linalg.norm(b[0])
+    assert res <= 1e-9 and st[0].converged == 1, (res, st[0].iters)
