@@ -5,7 +5,7 @@ throughput of the multi-RHS half-lattice Dslash.
 One step = one pass of the hot path over one batch: a Z4 noise vector with
 12 spin-colour dilutions generated on the GPU, even-odd source preparation,
 12 right-hand sides solved together by CG on the normal equations with FP16
-spinor storage / FP32 links and arithmetic and FP64 reliable updates to a
+spinor and link storage, FP32 arithmetic and FP64 reliable updates to a
 1e-9 full-system residual, odd reconstruction, FP64 true-residual check, and
 the one-end loop contraction 2 i eps sum_x s^dag gamma5 Gamma_n s for the 16
 Gamma at every time slice.  Inputs (gauge field) are resident in HBM before
@@ -120,25 +120,26 @@ def main():
           % (plain_iters, pst[0].true_rel_res, plain_time), file=sys.stderr, flush=True)
     del x, b
 
-    # dominant kernel: 12-RHS half-lattice Dslash R^-1 H (FP16 spinors, FP32 links)
+    # dominant kernel: 12-RHS half-lattice Dslash R^-1 H (FP16 spinors and
+    # links, FP32 arithmetic), the form the chosen solver launches
     vh = V // 2
     nb = ctx.half_numel(P.TM_F16, nrhs)
     bufs = [torch.randn(nb // 2, dtype=torch.float16, device=dev) * 0.1 for _ in range(2)]
     outb = torch.empty(nb, dtype=torch.uint8, device=dev)
     for _ in range(3):
-        ctx.dslash(outb, bufs[0], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16)
+        ctx.dslash(outb, bufs[0], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16, P.TM_F16)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for r in range(args.dslash_reps):
-        ctx.dslash(outb, bufs[r % 2], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16)
+        ctx.dslash(outb, bufs[r % 2], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16, P.TM_F16)
     ev1.record()
     torch.cuda.synchronize()
     dslash_s = ev0.elapsed_time(ev1) / 1e3 / args.dslash_reps
     # compulsory bytes per output site and RHS: 8 neighbour spinors are one
     # read of the input field (12 complex FP16 = 48 B), one output write
-    # (48 B), 8 FP32 links per site (576 B) shared by 12 RHS (48 B)
-    bytes_per_site_rhs = 48 + 48 + 8 * 9 * 8 / nrhs
+    # (48 B), 8 binary16 links per site (288 B) shared by 12 RHS (24 B)
+    bytes_per_site_rhs = 48 + 48 + 8 * 9 * 4 / nrhs
     alg_bytes = vh * nrhs * bytes_per_site_rhs
     achieved = alg_bytes / dslash_s / 1e9
     del bufs, outb
@@ -195,7 +196,7 @@ def main():
         "config": {
             "workload": "32^3x64 twisted-mass Wilson, kappa 0.1245, 2 kappa mu 0.0014, links "
                         "exp(i 0.15 H) seed 103; per step 1 Z4 noise x 12 spin-colour "
-                        "dilutions solved together (FP16 spinors, FP32 links and arithmetic, "
+                        "dilutions solved together (FP16 spinors and links, FP32 arithmetic, "
                         "FP64 reliable updates) to 1e-9, one-end loop contraction",
             "lattice": list(L), "rhs_per_step": nrhs, "parallelism": "single GPU",
         },
@@ -207,7 +208,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_dslash (R_oo^-1 H_oe, 12 RHS FP16, autotuned RHS tile)",
+            "kernel": "k_dslash (R_oo^-1 H_oe, 12 RHS, FP16 spinors and links, autotuned RHS tile)",
             "avg_launch_us": dslash_s * 1e6, "algorithmic_bytes_per_launch": alg_bytes,
             "copy_gb_s": copy_gbs, "frac_of_copy": achieved / copy_gbs,
         },

@@ -94,8 +94,8 @@ const char *tm_last_error(const tm_ctx *ctx);
 /* Upload the gauge field.  U: device pointer, canonical [4][V][3][3] complex
  * double.  Builds the internal even-odd link layout (forward links and
  * pre-conjugated backward links per site, boundary phase folded in) in FP64,
- * and the FP32 copy on first use by a FP32-link kernel (round to nearest
- * even).  U is not retained. */
+ * and the FP32 and IEEE binary16 copies on first use by a kernel that reads
+ * them (each rounded once from FP64, to nearest even).  U is not retained. */
 int tm_set_gauge(tm_ctx *ctx, const double *U, tm_stream stream);
 
 /* Operator kinds of tm_dslash. */
@@ -116,8 +116,9 @@ typedef enum {
  *               kinds, canonical FP64 for TM_FULL/TM_FULL_DAG (spinor_prec
  *               and link_prec must then be TM_F64).  in != out.
  *   mu_sign     +1: M_u (twist +eps), -1: M_d (twist -eps), sec. II.C.
- *   spinor_prec TM_F64 (links TM_F64) or TM_F32/TM_F16/TM_BF16 (links TM_F32);
- *               half/bf16 storage is computed in FP32.
+ *   spinor_prec TM_F64 (link_prec TM_F64), TM_F32 (link_prec TM_F32), or
+ *               TM_F16/TM_BF16 (link_prec TM_F16, the solvers' choice, or
+ *               TM_F32); FP32/FP16/BF16 storage is computed in FP32.
  * Enqueued on `stream`; does not synchronise. */
 int tm_dslash(tm_ctx *ctx, void *out, const void *in, int nrhs, int kind, int mu_sign,
               int spinor_prec, int link_prec, tm_stream stream);
@@ -135,7 +136,9 @@ int tm_unpack(tm_ctx *ctx, double *full, const void *even, const void *odd, int 
 typedef enum {
     TM_CG_F64 = 0,   /* plain FP64 CGNR on the even-odd system */
     TM_CG_MIXED = 1, /* CGNR with FP32 arithmetic and inner_prec storage, FP64
-                        reliable updates (true residual recomputed in FP64) */
+                        reliable updates (true residual recomputed in FP64);
+                        FP16/BF16 storage reads binary16 links, FP32 storage
+                        FP32 links */
     TM_CG_LOW = 2,   /* truncated low-precision CGNR (TSM low-precision solve):
                         inner_prec storage, FP32 arithmetic, no reliable update;
                         stops on the iterated residual */

@@ -183,8 +183,8 @@ class Context:
 
     def dslash(self, out, inp, nrhs, kind, mu_sign=1, spinor_prec=TM_F64, link_prec=None,
                stream=None):
-        if link_prec is None:
-            link_prec = TM_F64 if spinor_prec == TM_F64 else TM_F32
+        if link_prec is None:  # the solvers' choice for each spinor precision
+            link_prec = {TM_F64: TM_F64, TM_F32: TM_F32}.get(spinor_prec, TM_F16)
         self._check(tm_dslash(self.h, _ptr(out), _ptr(inp), nrhs, kind, mu_sign, spinor_prec,
                               link_prec, _stream(stream)))
 

@@ -50,6 +50,15 @@ void ensure_links32(tm_ctx *c, hipStream_t s)
     c->have_links32 = true;
 }
 
+void ensure_links16(tm_ctx *c, hipStream_t s)
+{
+    if (c->have_links16) return;
+    for (int p = 0; p < 2; p++)
+        if (!c->links16[p]) c->links16[p] = ws_get(c, p ? "links16_1" : "links16_0", (size_t)72 * c->geo.vh * 4);
+    launch_links_to_f16(c, s);
+    c->have_links16 = true;
+}
+
 namespace {
 
 template <typename F>
@@ -143,6 +152,7 @@ extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
         launch_gauge_ingest(c, U, hs(stream));
         c->have_gauge = true;
         c->have_links32 = false;
+        c->have_links16 = false;
         return TM_OK;
     });
 }
@@ -160,8 +170,16 @@ extern "C" int tm_dslash(tm_ctx *c, void *out, const void *in, int nrhs, int kin
         TM_REQUIRE(c->have_gauge, "no gauge field set");
         if (spinor_prec == TM_F64)
             TM_REQUIRE(link_prec == TM_F64, "FP64 spinors need FP64 links");
+        else if (spinor_prec == TM_F32)
+            TM_REQUIRE(link_prec == TM_F32, "FP32 spinors use FP32 links");
         else
-            TM_REQUIRE(link_prec == TM_F32, "FP32/FP16/BF16 spinors use FP32 links");
+            TM_REQUIRE(link_prec == TM_F32 || link_prec == TM_F16, "FP16/BF16 spinors use FP16 or FP32 links");
+        // the link copy for this call only (solvers use the binary16 copy)
+        struct LinkChoice {
+            tm_ctx *c;
+            ~LinkChoice() { c->half_links_f32 = false; }
+        } restore{c};
+        c->half_links_f32 = link_prec == TM_F32;
         hipStream_t s = hs(stream);
         const double epsp = eps_of(c, mu_sign), k = c->kappa;
         switch (kind) {

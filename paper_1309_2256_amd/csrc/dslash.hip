@@ -103,8 +103,21 @@ __device__ __forceinline__ cx<T> p_addi(rawc<L> u, rawc<L> l, T s)
 // gamma_4 = [[0, 1], [1, 0]]:           h = u - S l,          lower = -S w
 // with i s_1 = [[0, i], [i, 0]], i s_2 = [[0, 1], [-1, 0]], i s_3 = [[i, 0], [0, -i]].
 // psi[3*spin + colour]; u = spins 0, 1 and l = spins 2, 3.
-template <int MU, int S, typename T, typename L>
-__device__ __forceinline__ void hop_dir(cx<T> acc[12], const cx<T> W[9], const rawc<L> psi[12], T one)
+// acc += a * b for a link entry kept as stored binary16 (the conversion folds
+// into mixed-precision FMAs) or already converted
+template <typename T>
+__device__ __forceinline__ void lmac(cx<T> &acc, cx<T> a, cx<T> b) { cmac(acc, a, b); }
+template <typename T>
+__device__ __forceinline__ void lmac(cx<T> &acc, rawc<_Float16> a, cx<T> b)
+{
+    acc.r = fma((T)a.r, b.r, acc.r);
+    acc.r = fma(-(T)a.i, b.i, acc.r);
+    acc.i = fma((T)a.r, b.i, acc.i);
+    acc.i = fma((T)a.i, b.r, acc.i);
+}
+
+template <int MU, int S, typename T, typename L, typename WT>
+__device__ __forceinline__ void hop_dir(cx<T> acc[12], const WT W[9], const rawc<L> psi[12], T one)
 {
     const T s = (T)S * one;
     cx<T> h0[3], h1[3];
@@ -131,8 +144,8 @@ __device__ __forceinline__ void hop_dir(cx<T> acc[12], const cx<T> W[9], const r
         cx<T> a = {0, 0}, b = {0, 0};
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            cmac(a, W[3 * r + c], h0[c]);
-            cmac(b, W[3 * r + c], h1[c]);
+            lmac(a, W[3 * r + c], h0[c]);
+            lmac(b, W[3 * r + c], h1[c]);
         }
         w0[r] = a;
         w1[r] = b;
@@ -305,11 +318,27 @@ struct BufIO<b2> {
     }
 };
 
+// link entry as held in registers: binary16 links stay binary16 (converted
+// inside the FMAs), FP32/FP64 links in the arithmetic type
 template <typename LS, typename T>
-__device__ __forceinline__ void load_link(cx<T> W[9], rsrc_t lr, int vbytes, int voff)
+struct LinkEl {
+    using type = cx<T>;
+};
+template <typename T>
+struct LinkEl<h2, T> {
+    using type = rawc<_Float16>;
+};
+
+template <typename LS, typename T>
+__device__ __forceinline__ void load_link(typename LinkEl<LS, T>::type W[9], rsrc_t lr, int vbytes, int voff)
 {
 #pragma unroll
-    for (int k = 0; k < 9; k++) W[k] = BufIO<LS>::template ldlink<T>(lr, voff, k * vbytes);
+    for (int k = 0; k < 9; k++) {
+        if constexpr (std::is_same<LS, h2>::value)
+            W[k] = BufIO<h2>::ldraw(lr, voff, k * vbytes);
+        else
+            W[k] = BufIO<LS>::template ldlink<T>(lr, voff, k * vbytes);
+    }
 }
 
 template <typename SS>
@@ -325,8 +354,8 @@ __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, co
 {
     const LS *lbase = (const LS *)a.links + (size_t)dir * 9 * a.g.vh;
     const rsrc_t lr = make_rsrc(lbase, (size_t)9 * a.g.vh * sizeof(LS));
-    cx<T> W[9];
-    load_link<LS>(W, lr, a.g.vh * (int)sizeof(LS), i * (int)sizeof(LS));
+    typename LinkEl<LS, T>::type W[9];
+    load_link<LS, T>(W, lr, a.g.vh * (int)sizeof(LS), i * (int)sizeof(LS));
 #pragma unroll
     for (int rr = 0; rr < R; rr++) {
         rawc<typename RawT<SS>::L> psi[12];
@@ -564,7 +593,9 @@ DParams<T> fill_params(tm_ctx *c, const DslashCall &dc)
     a.out = dc.out;
     a.in = dc.in;
     a.own = dc.own;
-    a.links = (std::is_same<LS, double2>::value ? c->links64 : c->links32)[dc.out_parity];
+    a.links = (std::is_same<LS, double2>::value ? c->links64
+               : std::is_same<LS, h2>::value     ? c->links16
+                                                 : c->links32)[dc.out_parity];
     a.g = c->geo;
     a.p = dc.out_parity;
     a.nrhs = dc.nrhs;
@@ -631,7 +662,8 @@ template <typename SS, typename LS, typename T>
 void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 {
     const int n = dc.nrhs;
-    const auto key = std::make_pair(dc.spinor_prec, n);
+    // tiles are tuned per (spinor precision, link storage, nrhs)
+    const auto key = std::make_pair(dc.spinor_prec + (std::is_same<LS, h2>::value ? 8 : 0), n);
     auto it = c->rhs_tile.find(key);
     if (it != c->rhs_tile.end()) {
         launch_r<SS, LS, T>(c, dc, it->second, s);
@@ -743,8 +775,8 @@ void multi_dispatch(int prec, int R, F &&f)
     };
     struct PD { using SS = double2; using LS = double2; using T = double; };
     struct PF { using SS = float2; using LS = float2; using T = float; };
-    struct PH { using SS = h2; using LS = float2; using T = float; };
-    struct PB { using SS = b2; using LS = float2; using T = float; };
+    struct PH { using SS = h2; using LS = h2; using T = float; };
+    struct PB { using SS = b2; using LS = h2; using T = float; };
     switch (prec) {
     case TM_F64: byR((PD *)nullptr); break;
     case TM_F32: byR((PF *)nullptr); break;
@@ -771,7 +803,8 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
                        dcs[k].epi == m.epi,
                    "multi-instance calls must share precision and operator form");
         TM_REQUIRE(cs[k]->have_gauge, "no gauge field set");
-        if (m.prec != TM_F64) ensure_links32(cs[k], s);
+        if (m.prec == TM_F32) ensure_links32(cs[k], s);
+        if (m.prec == TM_F16 || m.prec == TM_BF16) ensure_links16(cs[k], s);
     }
     multi_dispatch(m.prec, R, [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs); });
 }
@@ -789,8 +822,26 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     switch (dc.spinor_prec) {
     case TM_F64: launch_rhs<double2, double2, double>(c, dc, s); break;
     case TM_F32: ensure_links32(c, s); launch_rhs<float2, float2, float>(c, dc, s); break;
-    case TM_F16: ensure_links32(c, s); launch_rhs<h2, float2, float>(c, dc, s); break;
-    case TM_BF16: ensure_links32(c, s); launch_rhs<b2, float2, float>(c, dc, s); break;
+    // FP16/BF16 spinors: binary16 links (the solvers' choice) unless the
+    // caller asked for the FP32 copy
+    case TM_F16:
+        if (c->half_links_f32) {
+            ensure_links32(c, s);
+            launch_rhs<h2, float2, float>(c, dc, s);
+        } else {
+            ensure_links16(c, s);
+            launch_rhs<h2, h2, float>(c, dc, s);
+        }
+        break;
+    case TM_BF16:
+        if (c->half_links_f32) {
+            ensure_links32(c, s);
+            launch_rhs<b2, float2, float>(c, dc, s);
+        } else {
+            ensure_links16(c, s);
+            launch_rhs<b2, h2, float>(c, dc, s);
+        }
+        break;
     default: throw TmError{TM_ERR_ARG, "bad spinor precision"};
     }
 }

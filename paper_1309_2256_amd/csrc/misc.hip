@@ -99,6 +99,18 @@ __global__ __launch_bounds__(kBlock) void k_d2f(float2 *out, const double2 *in, 
     }
 }
 
+// one rounding FP64 -> binary16 (not through FP32)
+__global__ __launch_bounds__(kBlock) void k_d2h(h2 *out, const double2 *in, size_t n)
+{
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        double2 v = in[e];
+        h2 o;
+        o.x = (_Float16)v.x;
+        o.y = (_Float16)v.y;
+        out[e] = o;
+    }
+}
+
 // ---------------------------------------------------------------- noise
 
 // SplitMix64 (Steele, Lea & Flood 2014): output c of the stream seeded with
@@ -260,6 +272,15 @@ void launch_links_to_f32(tm_ctx *c, hipStream_t s)
     size_t n = (size_t)72 * c->geo.vh;
     for (int p = 0; p < 2; p++)
         hipLaunchKernelGGL(k_d2f, dim3(2048), dim3(kBlock), 0, s, (float2 *)c->links32[p],
+                           (const double2 *)c->links64[p], n);
+    TM_HIP(hipGetLastError());
+}
+
+void launch_links_to_f16(tm_ctx *c, hipStream_t s)
+{
+    size_t n = (size_t)72 * c->geo.vh;
+    for (int p = 0; p < 2; p++)
+        hipLaunchKernelGGL(k_d2h, dim3(2048), dim3(kBlock), 0, s, (h2 *)c->links16[p],
                            (const double2 *)c->links64[p], n);
     TM_HIP(hipGetLastError());
 }

@@ -251,8 +251,13 @@ struct tm_ctx {
     // (backward hop), boundary phase folded in
     void *links64[2] = {nullptr, nullptr};
     void *links32[2] = {nullptr, nullptr};
+    void *links16[2] = {nullptr, nullptr};  // IEEE binary16 copy (FP16/BF16 spinors)
     bool have_gauge = false;
     bool have_links32 = false;
+    bool have_links16 = false;
+    // FP16/BF16-spinor Dslash launches read the FP32 links instead of the
+    // binary16 copy (set by tm_dslash for link_prec = TM_F32)
+    bool half_links_f32 = false;
     std::map<std::string, DevBuf> ws;
     // autotuned right-hand sides per Dslash thread, keyed by (precision, nrhs)
     std::map<std::pair<int, int>, int> rhs_tile;
@@ -271,6 +276,7 @@ struct tm_ctx {
 void *ws_get(tm_ctx *c, const std::string &name, size_t bytes);
 void *host_stage(tm_ctx *c, size_t bytes);
 void ensure_links32(tm_ctx *c, hipStream_t s);
+void ensure_links16(tm_ctx *c, hipStream_t s);
 
 // ---------------------------------------------------------------- dslash
 
@@ -395,6 +401,7 @@ void launch_unpack(tm_ctx *c, double *full, const void *even, const void *odd, i
                    hipStream_t s);
 void launch_gauge_ingest(tm_ctx *c, const double *U, hipStream_t s);
 void launch_links_to_f32(tm_ctx *c, hipStream_t s);
+void launch_links_to_f16(tm_ctx *c, hipStream_t s);
 // Z4 noise for noise index r into FP64 half fields; dilution 1: 12 rhs
 void launch_noise(tm_ctx *c, void *even, void *odd, uint64_t seed, long r, int dilution, hipStream_t s);
 // per time slice 4x4 colour-traced outer products C[b][a](t) = sum_x sum_c v_{bc} w*_{ac}

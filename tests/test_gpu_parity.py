@@ -197,12 +197,15 @@ def test_half_kinds_fp64(L):
     assert rel(got, O.schur(L, kappa, -eps, -1, U, ve)) < 1e-13
 
 
-@pytest.mark.parametrize("prec,bound", [(P.TM_F32, 2e-6), (P.TM_F16, 4e-3), (P.TM_BF16, 3e-2)])
+@pytest.mark.parametrize("prec,links,bound", [(P.TM_F32, P.TM_F32, 2e-6), (P.TM_F16, P.TM_F32, 4e-3),
+                                               (P.TM_F16, P.TM_F16, 4e-3), (P.TM_BF16, P.TM_F32, 3e-2),
+                                               (P.TM_BF16, P.TM_F16, 3e-2)])
 @pytest.mark.parametrize("L", [(4, 4, 4, 8), (6, 4, 4, 6)])
-def test_schur_low_precision(prec, bound, L):
-    """FP32 links with FP32/FP16/BF16 spinor storage, FP32 arithmetic: error
-    against the FP64 oracle is at the storage rounding level; 2 right-hand
-    sides per thread (even nrhs) give bit-identical results to 1 per call."""
+def test_schur_low_precision(prec, links, bound, L):
+    """FP32 or binary16 links with FP32/FP16/BF16 spinor storage, FP32
+    arithmetic: error against the FP64 oracle is at the storage rounding
+    level (binary16 links add 2^-11 relative per entry); several right-hand
+    sides per thread give bit-identical results to 1 per call."""
     kappa, eps = 0.124, 0.0123
     ctx, U = make_ctx(L, kappa, eps, 14)
     nrhs = 4
@@ -211,7 +214,7 @@ def test_schur_low_precision(prec, bound, L):
     ctx.pack(e, o, cuda(v), nrhs, prec)
     for kind, adj in ((P.TM_SCHUR, False), (P.TM_SCHUR_DAG, True)):
         outh = half_buf(ctx, prec, nrhs)
-        ctx.dslash(outh, e, nrhs, kind, 1, prec)
+        ctx.dslash(outh, e, nrhs, kind, 1, prec, links)
         # same storage precision back to canonical FP64
         full = torch.zeros((nrhs,) + v.shape[1:], dtype=torch.complex128, device=DEV)
         ctx.unpack(full, outh, half_buf(ctx, prec, nrhs), nrhs, prec)
@@ -223,12 +226,12 @@ def test_schur_low_precision(prec, bound, L):
         nb = ctx.half_numel(prec, 1)
         for r in range(nrhs):
             one = half_buf(ctx, prec, 1)
-            ctx.dslash(one, e[r * nb:(r + 1) * nb], 1, kind, 1, prec)
+            ctx.dslash(one, e[r * nb:(r + 1) * nb], 1, kind, 1, prec, links)
             assert torch.equal(one, outh[r * nb:(r + 1) * nb]), (kind, r)
     # odd nrhs takes the one-per-thread path
     odd = half_buf(ctx, prec, 3)
-    ctx.dslash(odd, e[:3 * ctx.half_numel(prec, 1)], 3, P.TM_SCHUR, 1, prec)
-    ctx.dslash(outh, e, nrhs, P.TM_SCHUR, 1, prec)
+    ctx.dslash(odd, e[:3 * ctx.half_numel(prec, 1)], 3, P.TM_SCHUR, 1, prec, links)
+    ctx.dslash(outh, e, nrhs, P.TM_SCHUR, 1, prec, links)
     assert torch.equal(odd, outh[:3 * ctx.half_numel(prec, 1)])
 
 
