@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--ptc-pairs", type=int, default=4096)
     ap.add_argument("--ptc-rhs", type=int, default=4,
                     help="right-hand sides of the FGMRES runs (memory: ~12 GB each)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the TSM/HPE (16^3x32) and uneven-batch legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the workload (one 32^3x64 lattice, noise vectors "
@@ -222,9 +224,99 @@ def main():
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
+    if not args.no_extra:
+        out["tsm_hpe_c2"] = tsm_leg(P, S, torch, dev)
+        out["uneven_batch_c4"] = batch_leg(P, S, torch, dev)
     if not args.no_ptc:
         out["ptc_c5"] = ptc_leg(args, P, S, torch, dev)
     print(json.dumps(out), flush=True)
+
+
+def make_context(P, S, torch, dev, name):
+    cfg = S.CONFIGS[name]
+    U = torch.from_numpy(S.gauge_links(cfg["L"], cfg["eps_links"], cfg["seed"])).to(dev)
+    c = P.Context(cfg["L"], cfg["kappa"], cfg["two_kappa_mu"])
+    c.set_gauge(U)
+    torch.cuda.synchronize()
+    return c, cfg
+
+
+def tsm_leg(P, S, torch, dev):
+    """Truncated Solver Method with the Hopping Parameter Expansion on the
+    16^3x32 lattice: 64 Z4 volume noises (seed 202) without dilution, all 64
+    solved to 1e-2 (low precision, no reliable update), the first 4 also to
+    1e-9 (mixed CG); standard and HPE loops at every time slice.  Reports
+    the cost of a high- and of a low-precision solve (the paper's
+    high/low cost ratio) for FP16 and FP32 low-precision storage."""
+    ctx, cfg = make_context(P, S, torch, dev, "c2")
+    res = {"workload": "16^3x32, links exp(i 0.2 H) seed 102, kappa 0.124, 2 kappa mu 0.0028; "
+                       "64 Z4 noises (seed 202), 4 high-precision (mixed CG to 1e-9) + 64 "
+                       "low-precision (to 1e-2) solves; STD + HPE loops"}
+    for name, lprec in (("lp_fp16", P.TM_F16), ("lp_fp32", P.TM_F32)):
+        p = P.tm_loop_params()
+        p.seed, p.n_hp, p.n_lp = S.NOISE_SEEDS["c2"], 4, 60
+        p.dilution, p.estimators, p.mu_sign = P.TM_DIL_NONE, P.TM_EST_STD | P.TM_EST_HPE, 1
+        p.hp = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+        p.lp = P.solve_params(tol=1e-2, solver=P.TM_CG_LOW, inner_prec=lprec)
+        ctx.loops(p)  # warm (tuning, buffers)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, st, status = ctx.loops(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        it_hp, it_lp = st.iters_hp / st.n_solves_hp, st.iters_lp / st.n_solves_lp
+        res[name] = {"seconds": dt, "n_solves_hp": st.n_solves_hp, "n_solves_lp": st.n_solves_lp,
+                     "iters_per_hp_solve": it_hp, "iters_per_lp_solve": it_lp,
+                     "hp_lp_iteration_ratio": it_hp / it_lp, "max_res_hp": st.max_res_hp,
+                     "max_res_lp": st.max_res_lp, "status": status}
+        print("[bench/tsm] %s: %d HP (%.0f it) + %d LP (%.1f it) solves in %.2fs"
+              % (name, st.n_solves_hp, it_hp, st.n_solves_lp, it_lp, dt), file=sys.stderr, flush=True)
+    ctx.close()
+    return res
+
+
+def batch_leg(P, S, torch, dev):
+    """Uneven batch: 8^3x16 / 12^3x24 / 16^3x32 lattices with 4 / 2 / 1 Z4
+    noises x 12 spin-colour dilutions (48 / 24 / 12 right-hand sides), mixed
+    CG to 1e-9 and standard + one-end loops, solved as one batch (one
+    graph-captured iteration stream) and, for comparison, lattice by lattice."""
+    names = ("c4a", "c4b", "c4c")
+    ctxs = [make_context(P, S, torch, dev, n)[0] for n in names]
+    hp = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+
+    def lp_of(k, n_hp):
+        p = P.tm_loop_params()
+        p.seed, p.n_hp, p.n_lp = 1040 + k, n_hp, 0
+        p.dilution, p.estimators, p.mu_sign = P.TM_DIL_SPIN_COLOUR, P.TM_EST_STD | P.TM_EST_ONE_END, 1
+        p.hp = hp
+        return p
+    plist = [lp_of(k, n) for k, n in enumerate((4, 2, 1))]
+    batch = P.Batch(ctxs)
+    batch.loops(plist)  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, bst, _ = batch.loops(plist)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    batch.close()
+    for c, p in zip(ctxs, plist):
+        c.loops(p)  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sst = [c.loops(p)[2] for c, p in zip(ctxs, plist)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    n = sum(q.n_solves_hp for q in bst)
+    ok = all(q.max_res_hp <= 1e-9 for q in bst) and all(q.max_res_hp <= 1e-9 for q in sst)
+    for c in ctxs:
+        c.close()
+    print("[bench/batch] %d solves: batch %.3fs, lattice by lattice %.3fs" % (n, tb, ts),
+          file=sys.stderr, flush=True)
+    return {"workload": "8^3x16 / 12^3x24 / 16^3x32 (links 0.3/0.2/0.15, seeds 1041-1043, kappa "
+                        "0.124, 2 kappa mu 0.005), 48/24/12 RHS, mixed CG to 1e-9, STD + one-end loops",
+            "solves": n, "all_verified": ok, "batch_seconds": tb, "batch_solves_per_s": n / tb,
+            "sequential_seconds": ts, "sequential_solves_per_s": n / ts, "speedup": ts / tb,
+            "iters": [q.iters_hp for q in bst]}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_rinv_hop_12rhs_fp16_c3_traffic.json")
@@ -258,12 +350,7 @@ def ptc_leg(args, P, S, torch, dev):
         print("[bench/ptc] " + msg, file=sys.stderr, flush=True)
 
     def make(name):
-        cfg = S.CONFIGS[name]
-        U = torch.from_numpy(S.gauge_links(cfg["L"], cfg["eps_links"], cfg["seed"])).to(dev)
-        c = P.Context(cfg["L"], cfg["kappa"], cfg["two_kappa_mu"])
-        c.set_gauge(U)
-        torch.cuda.synchronize()
-        return c, cfg
+        return make_context(P, S, torch, dev, name)
 
     res = {}
     c2, cfg2 = make("c2")
