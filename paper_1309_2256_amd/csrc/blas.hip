@@ -175,71 +175,6 @@ __global__ __launch_bounds__(kBlock) void k_finish_beta(CGScalars *sc, const dou
     }
 }
 
-// x += alpha p (x in XS), rho -= alpha q, partial |rho|^2
-template <typename S, typename XS>
-__global__ __launch_bounds__(kBlock) void k_update_xrho(XS *x, S *rho, const S *p, const S *q, size_t n,
-                                                        const CGScalars *sc, double xs, double *part,
-                                                        int nblk)
-{
-    using T = typename StoreTraits<S>::real;
-    using TX = typename StoreTraits<XS>::real;
-    const int r = blockIdx.y;
-    const double alpha = sc[r].alpha;
-    const T a = (T)alpha;
-    const TX ax = (TX)(alpha * xs);
-    const size_t base = (size_t)r * n;
-    double acc = 0;
-    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
-        const size_t k = base + e;
-        cx<T> pv = ldT<T>(p, k), qv = ldT<T>(q, k), rv = ldT<T>(rho, k);
-        cx<TX> xv = ldT<TX>(x, k);
-        xv = xv + ax * cx<TX>{(TX)pv.r, (TX)pv.i};
-        rv = rv - a * qv;
-        stT<TX>(x, k, xv);
-        stT<T>(rho, k, rv);
-        // the stored (rounded) value is what later iterations see
-        cx<T> rs = ldT<T>(rho, k);
-        acc += (double)(rs.r * rs.r + rs.i * rs.i);
-    }
-    double s = block_sum(acc);
-    if (threadIdx.x == 0) part[(size_t)r * nblk + blockIdx.x] = s;
-}
-
-// r -= alpha s, partial |r|^2 into slot 0 ([rhs][nblk])
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_update_r(S *rv, const S *sv, size_t n, const CGScalars *sc,
-                                                     double *part, int nblk)
-{
-    using T = typename StoreTraits<S>::real;
-    const int r = blockIdx.y;
-    const T a = (T)sc[r].alpha;
-    const size_t base = (size_t)r * n;
-    double acc = 0;
-    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
-        const size_t k = base + e;
-        cx<T> v = ldT<T>(rv, k) - a * ldT<T>(sv, k);
-        stT<T>(rv, k, v);
-        cx<T> vs = ldT<T>(rv, k);
-        acc += (double)(vs.r * vs.r + vs.i * vs.i);
-    }
-    double s = block_sum(acc);
-    if (threadIdx.x == 0) part[(size_t)r * nblk + blockIdx.x] = s;
-}
-
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_update_p(S *p, const S *rv, size_t n, const CGScalars *sc)
-{
-    using T = typename StoreTraits<S>::real;
-    const int r = blockIdx.y;
-    if (!sc[r].active) return;
-    const T b = (T)sc[r].beta;
-    const size_t base = (size_t)r * n;
-    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
-        const size_t k = base + e;
-        stT<T>(p, k, ldT<T>(rv, k) + b * ldT<T>(p, k));
-    }
-}
-
 // x += alpha p; p = r + beta p  (the solution update of this iteration folded
 // into the search-direction update; both use the p that produced q)
 template <typename S, typename XS>
@@ -286,15 +221,6 @@ void dispatch_prec(int prec, F &&f)
 
 }  // namespace
 
-int reduce_blocks(tm_ctx *c)
-{
-    size_t n = half_elems(c);
-    size_t g = (n + kBlock * 8 - 1) / (kBlock * 8);
-    if (g < 1) g = 1;
-    if (g > kMaxPart) g = kMaxPart;
-    return (int)g;
-}
-
 void launch_spin_diag(tm_ctx *c, void *out, const void *in, int prec, int nrhs, SpinDiag d, hipStream_t s)
 {
     size_t n = half_elems(c);
@@ -335,7 +261,17 @@ void launch_axpby_host(tm_ctx *c, void *y, const void *x, int prec, int nrhs, do
     TM_HIP(hipGetLastError());
 }
 
-void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *part, int nblk, hipStream_t s)
+// partial-sum blocks of the vector norms (a few per CU, at most kMaxPart)
+static int reduce_blocks(tm_ctx *c)
+{
+    size_t n = half_elems(c);
+    size_t g = (n + kBlock * 8 - 1) / (kBlock * 8);
+    if (g < 1) g = 1;
+    if (g > kMaxPart) g = kMaxPart;
+    return (int)g;
+}
+
+static void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *part, int nblk, hipStream_t s)
 {
     size_t n = half_elems(c);
     dispatch_prec(prec, [&](auto *tag) {
@@ -365,49 +301,6 @@ void cg_finish_beta(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int 
                     hipStream_t s)
 {
     hipLaunchKernelGGL(k_finish_beta, dim3(nrhs), dim3(kBlock), 0, s, sc, part, nblk, nrhs, delta);
-    TM_HIP(hipGetLastError());
-}
-
-void cg_update_xrho(tm_ctx *c, void *x, int xprec, void *rho, const void *p, const void *q, int prec,
-                    int nrhs, const CGScalars *sc, double *part, int nblk, double xs, hipStream_t s)
-{
-    size_t n = half_elems(c);
-    dim3 grid(nblk, nrhs);
-    if (prec == TM_F64) {
-        TM_REQUIRE(xprec == TM_F64, "FP64 CG needs an FP64 solution vector");
-        hipLaunchKernelGGL((k_update_xrho<double2, double2>), grid, dim3(kBlock), 0, s, (double2 *)x,
-                           (double2 *)rho, (const double2 *)p, (const double2 *)q, n, sc, xs, part, nblk);
-    } else {
-        TM_REQUIRE(xprec == TM_F32, "low-precision CG accumulates in FP32");
-        dispatch_prec(prec, [&](auto *tag) {
-            using S = std::remove_pointer_t<decltype(tag)>;
-            hipLaunchKernelGGL((k_update_xrho<S, float2>), grid, dim3(kBlock), 0, s, (float2 *)x, (S *)rho,
-                               (const S *)p, (const S *)q, n, sc, xs, part, nblk);
-        });
-    }
-    TM_HIP(hipGetLastError());
-}
-
-void cg_update_r(tm_ctx *c, void *r, const void *sv, int prec, int nrhs, const CGScalars *sc, double *part,
-                 int nblk, hipStream_t s)
-{
-    size_t n = half_elems(c);
-    dispatch_prec(prec, [&](auto *tag) {
-        using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_update_r<S>, dim3(nblk, nrhs), dim3(kBlock), 0, s, (S *)r, (const S *)sv, n, sc,
-                           part, nblk);
-    });
-    TM_HIP(hipGetLastError());
-}
-
-void cg_update_p(tm_ctx *c, void *p, const void *r, int prec, int nrhs, const CGScalars *sc, hipStream_t s)
-{
-    size_t n = half_elems(c);
-    dispatch_prec(prec, [&](auto *tag) {
-        using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_update_p<S>, dim3(grid_for(n), nrhs), dim3(kBlock), 0, s, (S *)p, (const S *)r,
-                           n, sc);
-    });
     TM_HIP(hipGetLastError());
 }
 

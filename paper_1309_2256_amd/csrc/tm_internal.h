@@ -358,7 +358,7 @@ void launch_axpy_dev(tm_ctx *c, void *y, int yprec, const void *x, int xprec, in
 // per-rhs |v|^2 into dev_out[nrhs] (device doubles), deterministic
 void launch_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *dev_out, hipStream_t s);
 
-// CG building blocks (see solver.hip)
+// CG building blocks (blas.hip; the iteration itself is in runtime.hip)
 struct CGScalars {
     double rr;       // |r|^2 (normal residual)
     double qq;       // |Ahat p|^2
@@ -376,22 +376,9 @@ struct CGScalars {
 void cg_finish_alpha(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int nrhs, hipStream_t s);
 void cg_finish_beta(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int nrhs, double delta,
                     hipStream_t s);
-// x += alpha p (x in xprec), rho -= alpha q, partial |rho|^2
-void cg_update_xrho(tm_ctx *c, void *x, int xprec, void *rho, const void *p, const void *q, int prec,
-                    int nrhs, const CGScalars *sc, double *part, int nblk, double xscale_by_sigma,
-                    hipStream_t s);
-// r -= alpha s, partial |r|^2
-void cg_update_r(tm_ctx *c, void *r, const void *sv, int prec, int nrhs, const CGScalars *sc,
-                 double *part, int nblk, hipStream_t s);
-// p = r + beta p
-void cg_update_p(tm_ctx *c, void *p, const void *r, int prec, int nrhs, const CGScalars *sc,
-                 hipStream_t s);
 // x += alpha p; p = r + beta p
 void cg_update_px(tm_ctx *c, void *p, const void *r, void *x, int prec, int xprec, int nrhs, const CGScalars *sc,
                   hipStream_t s);
-// partial |v|^2 only
-void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *part, int nblk, hipStream_t s);
-int reduce_blocks(tm_ctx *c);
 
 // ---------------------------------------------------------------- misc kernels
 
