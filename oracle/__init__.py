@@ -284,6 +284,91 @@ def loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators):
     return out
 
 
+# ---------------------------------------------------------------- momenta
+
+def momenta(p2max):
+    """Integer vectors n with |n|^2 <= p2max, ordered by |n|^2, then n_x,
+    n_y, n_z ascending ((0, 0, 0) first) -> (n_mom, 3)."""
+    n = int(np.floor(np.sqrt(p2max)))
+    out = []
+    for n2 in range(p2max + 1):
+        for nx in range(-n, n + 1):
+            for ny in range(-n, n + 1):
+                for nz in range(-n, n + 1):
+                    if nx * nx + ny * ny + nz * nz == n2:
+                        out.append((nx, ny, nz))
+    return np.array(out, dtype=int).reshape(-1, 3)
+
+
+def _site_coords(L):
+    s = np.arange(volume(L))
+    return (s % L[0], (s // L[0]) % L[1], (s // (L[0] * L[1])) % L[2], s // (L[0] * L[1] * L[2]))
+
+
+def _bilinear(L, left, right, G):
+    """Per-site left(x)^dag G right(x) summed over spin and colour -> (V,)."""
+    left, right = _spinor(L, left), _spinor(L, right)
+    return np.einsum("xac,ab,xbc->x", left.conj(), G, right)
+
+
+def project_momenta(L, dens, moms):
+    """sum_{x in t} e^{+i p.x} dens[..., x], p = 2 pi n / L -> (..., n_mom, Lt)."""
+    x, y, z, _ = _site_coords(L)
+    out = np.zeros(dens.shape[:-1] + (len(moms), L[3]), dtype=np.complex128)
+    for m, (nx, ny, nz) in enumerate(moms):
+        ph = np.exp(2j * np.pi * (nx * x / L[0] + ny * y / L[1] + nz * z / L[2]))
+        # t is the slowest index of the site order: one row per time slice
+        out[..., m, :] = (dens * ph).reshape(dens.shape[:-1] + (L[3], -1)).sum(axis=-1)
+    return out
+
+
+def contract_momentum(L, eps, eta, s, estimators, moms):
+    """Momentum-resolved loops of given fields (no solve):
+    STD: sum_{x in t} e^{ip.x} eta^dag Gamma_n s;  ONE_END: 2 i eps sum e^{ip.x}
+    s^dag gamma5 Gamma_n s.  Returns {estimator: (n_mom, 16, Lt)}."""
+    g5 = gamma(15)
+    out = {}
+    if estimators & EST_STD:
+        d = np.stack([_bilinear(L, eta, s, gamma(n)) for n in range(16)])
+        out[EST_STD] = np.transpose(project_momenta(L, d, moms), (1, 0, 2))
+    if estimators & EST_ONE_END:
+        d = np.stack([_bilinear(L, s, s, g5 @ gamma(n)) for n in range(16)]) * (2j * eps)
+        out[EST_ONE_END] = np.transpose(project_momenta(L, d, moms), (1, 0, 2))
+    return out
+
+
+def loops_momentum_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators, moms):
+    """As loops_for_solution, momentum resolved: {estimator: (n_mom, 16, Lt)}."""
+    out = {}
+    for e, s in zip(etas, sols):
+        part = contract_momentum(L, eps, e, s, estimators & (EST_STD | EST_ONE_END), moms)
+        if estimators & EST_HPE:
+            part[EST_HPE] = contract_momentum(L, eps, e, bh_power(L, kappa, eps, t_bc, U, s, 4),
+                                              EST_STD, moms)[EST_STD]
+        for k, v in part.items():
+            out[k] = out.get(k, 0) + v
+    return out
+
+
+def loops_momentum(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, moms, dilution=False):
+    """As loops, momentum resolved ({estimator: (n_mom, 16, Lt)}).  The exact
+    HPE part is the same at every site of a slice, so its Fourier sum over the
+    slice vanishes for p != 0 and it enters p = 0 only."""
+    per_noise = []
+    for r in range(n_noise):
+        eta = noise_z4(L, seed, r)
+        etas = dilute_spin_colour(eta) if dilution else [eta]
+        sols, _, _ = solve_sources(L, kappa, eps, t_bc, U, etas, tol)
+        per_noise.append(loops_momentum_for_solution(L, kappa, eps, t_bc, U, etas, sols,
+                                                     estimators, moms))
+    mean = {e: sum(p[e] for p in per_noise) / n_noise for e in per_noise[0]}
+    if estimators & EST_HPE:
+        assert tuple(moms[0]) == (0, 0, 0)
+        mean[EST_HPE] = mean[EST_HPE].copy()
+        mean[EST_HPE][0] += hpe_exact(L, kappa, eps, t_bc, U)
+    return mean, per_noise
+
+
 def tsm_combine(hp_loops, lp_of_hp_loops, lp_only_loops):
     """Truncated Solver Method (eq. estiTSM), applied to any loop functional:
        (1/N_HP) sum_{r<=N_HP} [L(s_HP,r) - L(s_LP,r)] + (1/N_LP) sum_{r>N_HP} L(s_LP,r).

@@ -448,3 +448,41 @@ def test_ptc_at_equals_whole_lattice_forward():
         full = O.ptc_forward(L, t_bc, U, W1, W2, f)
         at = O.ptc_at(L, t_bc, U, W1, W2, f, sites)
         assert np.abs(at - full[sites]).max() <= 1e-14 * np.abs(full).max()
+
+
+def test_momentum_projection_pins():
+    """Momentum-resolved contraction: p = 0 equals the per-slice C oracle;
+    shifting both fields by a spatial vector a multiplies L(t, p) by
+    e^{+i p.a}; the momentum list has the lattice-point counts of the
+    sphere |n|^2 <= 9 (1, 6, 12, 8, 6, 24, 24, 0, 12, 30 per shell)."""
+    L, eps = (6, 4, 4, 4), 0.07
+    moms = O.momenta(2)
+    assert tuple(moms[0]) == (0, 0, 0) and len(moms) == 19
+    shells = np.bincount((O.momenta(9) ** 2).sum(axis=1), minlength=10)
+    assert shells.tolist() == [1, 6, 12, 8, 6, 24, 24, 0, 12, 30]
+    eta, s = S.random_spinor(L, 90), S.random_spinor(L, 91)
+    out = O.contract_momentum(L, eps, eta, s, O.EST_STD | O.EST_ONE_END, moms)
+    assert np.abs(out[O.EST_STD][0] - O.contract_std(L, eta, s)).max() < 1e-12
+    assert np.abs(out[O.EST_ONE_END][0] - O.contract_oneend(L, eps, s)).max() < 1e-12
+    # translate by a = (1, 2, 3): field(x) -> field(x - a)
+    a = (1, 2, 3)
+    x, y, z, t = O._site_coords(L)
+    src = (((x - a[0]) % L[0]) + L[0] * (((y - a[1]) % L[1]) + L[1] * (((z - a[2]) % L[2]) + L[2] * t)))
+    out2 = O.contract_momentum(L, eps, eta[src], s[src], O.EST_STD, moms)[O.EST_STD]
+    ph = np.exp(2j * np.pi * (moms[:, 0] * a[0] / L[0] + moms[:, 1] * a[1] / L[1] + moms[:, 2] * a[2] / L[2]))
+    assert np.abs(out2 - ph[:, None, None] * out[O.EST_STD]).max() < 1e-11
+
+
+def test_loops_momentum_zero_momentum_is_loops():
+    """The p = 0 block of the momentum-resolved estimate equals the per-slice
+    estimate for every estimator, the exact HPE part included; for p != 0 the
+    HPE block is the pure stochastic part."""
+    L, kappa, eps = (4, 4, 4, 4), 0.124, 0.01
+    U = S.gauge_links(L, 0.3, 7)
+    est = O.EST_STD | O.EST_ONE_END | O.EST_HPE
+    moms = O.momenta(1)
+    mm, pn = O.loops_momentum(L, kappa, eps, -1, U, 11, 1, 1e-13, est, moms)
+    ref, _ = O.loops(L, kappa, eps, -1, U, 11, 1, 1e-13, est)
+    for e in (O.EST_STD, O.EST_ONE_END, O.EST_HPE):
+        assert np.abs(mm[e][0] - ref[e]).max() < 1e-10 * np.abs(ref[e]).max()
+    assert np.abs(mm[O.EST_HPE][1:] - pn[0][O.EST_HPE][1:]).max() == 0
