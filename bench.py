@@ -221,6 +221,8 @@ def main():
         out["roofline"]["traffic"] = traffic["bytes"]
         out["roofline"]["traffic_source"] = traffic["source"]
         out["roofline"]["kernel"] = traffic["kernel"]
+    if not args.no_extra:
+        out["momentum_c3"] = momentum_leg(P, torch, dev, ctx, L, nrhs)
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -230,6 +232,35 @@ def main():
     if not args.no_ptc:
         out["ptc_c5"] = ptc_leg(args, P, S, torch, dev)
     print(json.dumps(out), flush=True)
+
+
+def momentum_leg(P, torch, dev, ctx, L, nrhs, p2max=9, reps=3):
+    """Momentum projection on 32^3x64: standard and one-end loops of 12
+    resident right-hand sides (complex128 fields) for every momentum with
+    |n|^2 <= 9, against the per-slice (p = 0 only) contraction."""
+    V = int(np.prod(L))
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    eta = torch.randn((nrhs, V, 4, 3), dtype=torch.complex128, device=dev, generator=g)
+    sol = torch.randn((nrhs, V, 4, 3), dtype=torch.complex128, device=dev, generator=g)
+    est = P.TM_EST_STD | P.TM_EST_ONE_END
+    n_mom = len(P.momenta(p2max))
+    res = {"workload": "32^3x64, %d RHS, STD + one-end loops, %d momenta (|n|^2 <= %d)"
+                       % (nrhs, n_mom, p2max)}
+    for name, fn in (("per_slice", lambda: ctx.contract(eta, sol, nrhs, est)),
+                     ("momentum", lambda: ctx.contract_momentum(eta, sol, nrhs, est, p2max))):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = (time.perf_counter() - t) / reps * 1e3
+    print("[bench/momentum] per-slice %.1f ms, %d momenta %.1f ms"
+          % (res["per_slice_ms"], n_mom, res["momentum_ms"]), file=sys.stderr, flush=True)
+    del eta, sol
+    torch.cuda.empty_cache()
+    return res
 
 
 def make_context(P, S, torch, dev, name):

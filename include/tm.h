@@ -244,6 +244,29 @@ int tm_loops(tm_ctx *ctx, const tm_loop_params *p, double *loops, double *per_no
 int tm_contract(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int estimators,
                 int mu_sign, double *out, tm_stream stream);
 
+/* ---------------------------------------------------------------- momenta
+ * Momentum projection of the loops (sec. III, contraction kernels and the
+ * Fourier step): L_n(t, p) = sum_{x in t} e^{+i p.x} [loop density at x],
+ * p = 2 pi (n_x / L_x, n_y / L_y, n_z / L_z), x = (x, y, z) in 0 .. L - 1,
+ * for every integer vector n with |n|^2 <= p2max (the paper's cut-off in p^2,
+ * in units of (2 pi / L)^2).  Momentum order: |n|^2 ascending, then n_x, n_y,
+ * n_z ascending; (0, 0, 0) is first.  Every |n_i| must stay below L_i / 2. */
+
+/* Momenta for p2max: *count receives their number; list (may be NULL)
+ * receives [count][3] integers n and must hold *count entries on input. */
+int tm_momenta(int p2max, int *count, int *list);
+
+/* As tm_contract, momentum resolved: out host [n_est][n_mom][16][Lt] complex
+ * double. */
+int tm_contract_momentum(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int estimators, int mu_sign,
+                         int p2max, double *out, tm_stream stream);
+
+/* As tm_loops, momentum resolved: loops host [n_est][n_mom][16][Lt];
+ * per_noise host [n_noise][2][n_est][n_mom][16][Lt] or NULL.  The exact HPE
+ * part (the same at every site) enters p = 0 only. */
+int tm_loops_momentum(tm_ctx *ctx, const tm_loop_params *p, int p2max, double *loops, double *per_noise,
+                      tm_loop_stats *stats, tm_stream stream);
+
 /* ---------------------------------------------------------------- batches
  * Uneven batches: several lattices (one context each, gauge set, same
  * device, distinct contexts) advanced together.  Each CG iteration of all

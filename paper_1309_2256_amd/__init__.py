@@ -6,3 +6,4 @@ with the same entry-point names.
 """
 from .binding import *  # noqa: F401,F403
 from .binding import Batch, Context, TMError, solve_params  # noqa: F401
+from .storage import Base2Store  # noqa: F401

@@ -95,6 +95,12 @@ _SIGS = {
     "tm_noise": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, ctypes.c_long, ctypes.c_int, _vp]),
     "tm_contract": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                    _vp]),
+    "tm_momenta": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int)]),
+    "tm_contract_momentum": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, _dp, _vp]),
+    "tm_loops_momentum": (ctypes.c_int, [_vp, ctypes.POINTER(tm_loop_params), ctypes.c_int, _dp, _dp,
+                                         ctypes.POINTER(tm_loop_stats), _vp]),
     "tm_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int]),
     "tm_batch_destroy": (None, [_vp]),
     "tm_batch_last_error": (ctypes.c_char_p, [_vp]),
@@ -269,12 +275,48 @@ class Context:
                                  hist.ctypes.data_as(_dp) if hist is not None else None, _stream(stream)))
         return st, hist
 
+    def contract_momentum(self, eta, s, nrhs, estimators, p2max, mu_sign=1, stream=None):
+        n_est = bin(estimators).count("1")
+        n_mom = len(momenta(p2max))
+        out = np.zeros((n_est, n_mom, 16, self.L[3]), dtype=np.complex128)
+        self._check(tm_contract_momentum(self.h, _ptr(eta), _ptr(s), nrhs, estimators, mu_sign, p2max,
+                                         out.ctypes.data_as(_dp), _stream(stream)))
+        return out
+
+    def loops_momentum(self, params, p2max, per_noise=False, stream=None, allow_noconv=False):
+        n_est = bin(params.estimators).count("1")
+        n_mom = len(momenta(p2max))
+        Lt = self.L[3]
+        out = np.zeros((n_est, n_mom, 16, Lt), dtype=np.complex128)
+        n_noise = params.n_hp + params.n_lp
+        pn = (np.zeros((n_noise, 2, n_est, n_mom, 16, Lt), dtype=np.complex128)
+              if per_noise else None)
+        stats = tm_loop_stats()
+        st = tm_loops_momentum(self.h, ctypes.byref(params), p2max, out.ctypes.data_as(_dp),
+                               pn.ctypes.data_as(_dp) if pn is not None else None,
+                               ctypes.byref(stats), _stream(stream))
+        self._check(st, allow=(TM_ERR_NOCONV,) if allow_noconv else ())
+        return out, pn, stats, st
+
     def contract(self, eta, s, nrhs, estimators, mu_sign=1, stream=None):
         n_est = bin(estimators).count("1")
         out = np.zeros((n_est, 16, self.L[3]), dtype=np.complex128)
         self._check(tm_contract(self.h, _ptr(eta), _ptr(s), nrhs, estimators, mu_sign,
                                 out.ctypes.data_as(_dp), _stream(stream)))
         return out
+
+
+def momenta(p2max):
+    """Integer momentum vectors n (p = 2 pi n / L) with |n|^2 <= p2max, in the
+    library's order -> (n_mom, 3) int array."""
+    n = ctypes.c_int(0)
+    if tm_momenta(p2max, ctypes.byref(n), None) != TM_OK:
+        raise TMError(TM_ERR_ARG, "p2max must be >= 0")
+    out = np.zeros((n.value, 3), dtype=np.int32)
+    st = tm_momenta(p2max, ctypes.byref(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if st != TM_OK:
+        raise TMError(st, "tm_momenta failed")
+    return out
 
 
 class Batch:

@@ -319,38 +319,89 @@ extern "C" int tm_loops(tm_ctx *c, const tm_loop_params *p, double *loops, doubl
     });
 }
 
+namespace {
+
+// tm_contract and tm_contract_momentum: mom = null for p = 0 per time slice
+int contract_fields(tm_ctx *c, const double *eta, const double *s_, int nrhs, int estimators, int mu_sign,
+                    double *out, tm_stream stream, const std::vector<Momentum> *mom)
+{
+    TM_REQUIRE(s_ && out, "null pointer");
+    TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    TM_REQUIRE(estimators > 0 && (estimators & ~(TM_EST_STD | TM_EST_ONE_END)) == 0,
+               "contractions accept TM_EST_STD and TM_EST_ONE_END");
+    TM_REQUIRE(!(estimators & TM_EST_STD) || eta, "STD needs eta");
+    TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
+    hipStream_t s = hs(stream);
+    const size_t hb = half_bytes(c, TM_F64, nrhs);
+    void *se = ws_get(c, "c_se", hb), *so = ws_get(c, "c_so", hb);
+    launch_pack(c, se, so, s_, nrhs, TM_F64, nullptr, s);
+    void *ee = nullptr, *eo = nullptr;
+    if (estimators & TM_EST_STD) {
+        ee = ws_get(c, "c_ee", hb);
+        eo = ws_get(c, "c_eo", hb);
+        launch_pack(c, ee, eo, eta, nrhs, TM_F64, nullptr, s);
+    }
+    const int Lt = c->geo.L[3];
+    const size_t per_m = (size_t)16 * Lt;
+    const int n_mom = mom ? (int)mom->size() : 1;
+    std::vector<cx<double>> C;
+    int k = 0;
+    auto one = [&](const void *ve, const void *vo, const void *we, const void *wo, bool g5pre, cx<double> coef) {
+        cx<double> *dst = (cx<double> *)out + per_m * n_mom * k++;
+        if (mom) {
+            outer_momenta_host(c, ve, vo, we, wo, nrhs, *mom, C, s);
+            for (int m = 0; m < n_mom; m++) loops_from_outer(c, C.data() + per_m * m, g5pre, coef, dst + per_m * m);
+        } else {
+            outer_slices_host(c, ve, vo, we, wo, nrhs, C, s);
+            loops_from_outer(c, C.data(), g5pre, coef, dst);
+        }
+    };
+    if (estimators & TM_EST_STD) one(se, so, ee, eo, false, cx<double>{1, 0});
+    if (estimators & TM_EST_ONE_END) one(se, so, se, so, true, cx<double>{0, 2.0 * eps_of(c, mu_sign)});
+    return TM_OK;
+}
+
+}  // namespace
+
 extern "C" int tm_contract(tm_ctx *c, const double *eta, const double *s_, int nrhs, int estimators, int mu_sign,
                            double *out, tm_stream stream)
 {
+    return guarded(c, [&]() { return contract_fields(c, eta, s_, nrhs, estimators, mu_sign, out, stream, nullptr); });
+}
+
+extern "C" int tm_momenta(int p2max, int *count, int *list)
+{
+    if (p2max < 0 || !count) return TM_ERR_ARG;
+    const std::vector<Momentum> m = momenta_list(p2max);
+    if (list) {
+        if (*count < (int)m.size()) return TM_ERR_ARG;
+        for (size_t k = 0; k < m.size(); k++)
+            for (int d = 0; d < 3; d++) list[3 * k + d] = m[k].n[d];
+    }
+    *count = (int)m.size();
+    return TM_OK;
+}
+
+extern "C" int tm_contract_momentum(tm_ctx *c, const double *eta, const double *s_, int nrhs, int estimators,
+                                    int mu_sign, int p2max, double *out, tm_stream stream)
+{
     return guarded(c, [&]() {
-        TM_REQUIRE(s_ && out, "null pointer");
-        TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
-        TM_REQUIRE(estimators > 0 && (estimators & ~(TM_EST_STD | TM_EST_ONE_END)) == 0,
-                   "tm_contract accepts TM_EST_STD and TM_EST_ONE_END");
-        TM_REQUIRE(!(estimators & TM_EST_STD) || eta, "STD needs eta");
-        TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
-        hipStream_t s = hs(stream);
-        const size_t hb = half_bytes(c, TM_F64, nrhs);
-        void *se = ws_get(c, "c_se", hb), *so = ws_get(c, "c_so", hb);
-        launch_pack(c, se, so, s_, nrhs, TM_F64, nullptr, s);
-        void *ee = nullptr, *eo = nullptr;
-        if (estimators & TM_EST_STD) {
-            ee = ws_get(c, "c_ee", hb);
-            eo = ws_get(c, "c_eo", hb);
-            launch_pack(c, ee, eo, eta, nrhs, TM_F64, nullptr, s);
-        }
-        const int Lt = c->geo.L[3];
-        const size_t per = (size_t)16 * Lt;
-        std::vector<cx<double>> C;
-        int k = 0;
-        if (estimators & TM_EST_STD) {
-            outer_slices_host(c, se, so, ee, eo, nrhs, C, s);
-            loops_from_outer(c, C, false, cx<double>{1, 0}, (cx<double> *)out + per * k++);
-        }
-        if (estimators & TM_EST_ONE_END) {
-            outer_slices_host(c, se, so, se, so, nrhs, C, s);
-            loops_from_outer(c, C, true, cx<double>{0, 2.0 * eps_of(c, mu_sign)}, (cx<double> *)out + per * k++);
-        }
-        return TM_OK;
+        check_momenta(c, p2max);
+        const std::vector<Momentum> mom = momenta_list(p2max);
+        return contract_fields(c, eta, s_, nrhs, estimators, mu_sign, out, stream, &mom);
+    });
+}
+
+extern "C" int tm_loops_momentum(tm_ctx *c, const tm_loop_params *p, int p2max, double *loops, double *per_noise,
+                                 tm_loop_stats *stats, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(c->have_gauge, "no gauge field set");
+        check_momenta(c, p2max);
+        const std::vector<Momentum> mom = momenta_list(p2max);
+        int st = run_loops(c, p, loops, per_noise, stats, hs(stream), &mom);
+        TM_HIP(hipStreamSynchronize(hs(stream)));
+        if (st == TM_ERR_NOCONV) c->err = "a high-precision solve missed its tolerance";
+        return st;
     });
 }

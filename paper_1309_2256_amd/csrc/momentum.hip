@@ -1,0 +1,180 @@
+// Momentum projection of the loops (sec. III, contraction kernels and the
+// Fourier step): the colour-traced Dirac outer products are formed per site,
+// C(x)[b][a] = sum_r sum_c v_{r,bc}(x) w*_{r,ac}(x), and transformed over the
+// spatial coordinates of each time slice,
+//   C_p(t) = sum_{x in t} e^{i p.x} C(x),  p = 2 pi (nx/Lx, ny/Ly, nz/Lz),
+// for every integer n with |n|^2 <= p2max.  The transform is separable, so it
+// runs as three direct one-dimensional transforms (x, then y, then z) over
+// the 2N+1 needed components per direction (N = floor(sqrt(p2max))), each a
+// fixed-order sum, followed by the selection of the momenta inside the
+// sphere.  Phases come from FP64 tables of e^{2 pi i k / L}, k = n x mod L.
+#include <cmath>
+
+#include "runtime.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Cf[e][s], e = 4 b + a, s = x + Lx (y + Ly (z + Lz t)) (canonical order)
+__global__ __launch_bounds__(kBlock) void k_outer_sites(const double2 *ve, const double2 *vo, const double2 *we,
+                                                        const double2 *wo, Geo g, long V, int nrhs, double2 *Cf)
+{
+    const long s = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= V) return;
+    const int x = (int)(s % g.L[0]);
+    const long q = s / g.L[0];
+    const int y = (int)(q % g.L[1]);
+    const long q2 = q / g.L[1];
+    const int z = (int)(q2 % g.L[2]);
+    const int t = (int)(q2 / g.L[2]);
+    const int p = (x + y + z + t) & 1;
+    const size_t i = (size_t)(s >> 1);
+    const double2 *v = p ? vo : ve, *w = p ? wo : we;
+    cx<double> C[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) C[e] = {0, 0};
+    for (int r = 0; r < nrhs; r++) {
+        cx<double> a[12], b[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const double2 va = v[(size_t)(r * 12 + k) * g.vh + i], vb = w[(size_t)(r * 12 + k) * g.vh + i];
+            a[k] = {va.x, va.y};
+            b[k] = {vb.x, vb.y};
+        }
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+            for (int sa = 0; sa < 4; sa++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) cmac_conj(C[sb * 4 + sa], b[sa * 3 + c], a[sb * 3 + c]);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; e++) Cf[(size_t)e * V + s] = make_double2(C[e].r, C[e].i);
+}
+
+// One direction of the transform: in [outer][n][inner] -> out[outer][W][inner]
+// with out[o][j][k] = sum_m ph[j][m] in[o][m][k] (fixed order in m).
+__global__ __launch_bounds__(kBlock) void k_dft_dim(const double2 *in, double2 *out, const double2 *ph, long outer,
+                                                    int n, int W, long inner)
+{
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long total = outer * W * inner;
+    if (idx >= total) return;
+    const long k = idx % inner;
+    const long rest = idx / inner;
+    const int j = (int)(rest % W);
+    const long o = rest / W;
+    const double2 *src = in + (o * n) * inner + k;
+    const double2 *f = ph + (long)j * n;
+    cx<double> acc = {0, 0};
+    for (int m = 0; m < n; m++) {
+        const double2 a = f[m], b = src[(long)m * inner];
+        cmac(acc, cx<double>{a.x, a.y}, cx<double>{b.x, b.y});
+    }
+    out[idx] = make_double2(acc.r, acc.i);
+}
+
+// out[m][t][e] = T[e][t][nz + N][ny + N][nx + N] for the listed momenta
+__global__ void k_pick_momenta(const double2 *T, const int *mom, int n_mom, int Lt, int W, int N, double2 *out)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_mom * Lt * 16) return;
+    const int e = idx % 16, t = (idx / 16) % Lt, m = idx / (16 * Lt);
+    const int nx = mom[3 * m] + N, ny = mom[3 * m + 1] + N, nz = mom[3 * m + 2] + N;
+    out[idx] = T[((((size_t)e * Lt + t) * W + nz) * W + ny) * W + nx];
+}
+
+// e^{2 pi i (j - N) x / L} for j < W, x < L, reduced mod L in integers
+std::vector<double2> phase_table(int L, int N)
+{
+    const int W = 2 * N + 1;
+    std::vector<double2> ph((size_t)W * L);
+    for (int j = 0; j < W; j++)
+        for (int x = 0; x < L; x++) {
+            const long k = (((long)(j - N) * x) % L + L) % L;
+            const double a = 2.0 * M_PI * (double)k / (double)L;
+            ph[(size_t)j * L + x] = make_double2(std::cos(a), std::sin(a));
+        }
+    return ph;
+}
+
+}  // namespace
+
+std::vector<Momentum> momenta_list(int p2max)
+{
+    std::vector<Momentum> out;
+    if (p2max < 0) return out;
+    int N = 0;
+    while ((N + 1) * (N + 1) <= p2max) N++;
+    for (int n2 = 0; n2 <= p2max; n2++)
+        for (int nx = -N; nx <= N; nx++)
+            for (int ny = -N; ny <= N; ny++)
+                for (int nz = -N; nz <= N; nz++)
+                    if (nx * nx + ny * ny + nz * nz == n2) out.push_back(Momentum{{nx, ny, nz}});
+    return out;
+}
+
+void check_momenta(tm_ctx *c, int p2max)
+{
+    TM_REQUIRE(p2max >= 0, "p2max must be >= 0");
+    int N = 0;
+    while ((N + 1) * (N + 1) <= p2max) N++;
+    for (int mu = 0; mu < 3; mu++)
+        TM_REQUIRE(2 * N < c->geo.L[mu], "momentum components must stay below L/2 in every spatial direction");
+}
+
+void outer_momenta_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
+                        const std::vector<Momentum> &mom, std::vector<cx<double>> &out, hipStream_t s)
+{
+    const Geo &g = c->geo;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    int N = 0;
+    for (const auto &m : mom)
+        for (int d = 0; d < 3; d++) N = std::max(N, std::abs(m.n[d]));
+    const int W = 2 * N + 1;
+    const long V = c->V;
+    double2 *Cf = (double2 *)ws_get(c, "mom_cf", sizeof(double2) * 16 * V);
+    hipLaunchKernelGGL(k_outer_sites, dim3((unsigned)((V + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const double2 *)ve, (const double2 *)vo, (const double2 *)we, (const double2 *)wo, g, V,
+                       nrhs, Cf);
+    TM_HIP(hipGetLastError());
+    // phase tables for x, y, z
+    std::vector<double2> px = phase_table(Lx, N), py = phase_table(Ly, N), pz = phase_table(Lz, N);
+    double2 *dph = (double2 *)ws_get(c, "mom_ph", sizeof(double2) * (size_t)W * (Lx + Ly + Lz));
+    upload(dph, px.data(), sizeof(double2) * px.size(), s);
+    upload(dph + px.size(), py.data(), sizeof(double2) * py.size(), s);
+    upload(dph + px.size() + py.size(), pz.data(), sizeof(double2) * pz.size(), s);
+    // x: [16 Lt Lz Ly][Lx][1] -> [16 Lt Lz Ly][W][1]
+    const long o1 = 16L * Lt * Lz * Ly;
+    double2 *T1 = (double2 *)ws_get(c, "mom_t1", sizeof(double2) * o1 * W);
+    long n1 = o1 * W;
+    hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const double2 *)Cf, T1, (const double2 *)dph, o1, Lx, W, 1L);
+    // y: [16 Lt Lz][Ly][W] -> [16 Lt Lz][W][W]
+    const long o2 = 16L * Lt * Lz;
+    double2 *T2 = (double2 *)ws_get(c, "mom_t2", sizeof(double2) * o2 * W * W);
+    long n2 = o2 * W * W;
+    hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n2 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const double2 *)T1, T2, (const double2 *)(dph + px.size()), o2, Ly, W, (long)W);
+    // z: [16 Lt][Lz][W W] -> [16 Lt][W][W W]
+    const long o3 = 16L * Lt;
+    double2 *T3 = (double2 *)ws_get(c, "mom_t3", sizeof(double2) * o3 * W * W * W);
+    long n3 = o3 * W * W * W;
+    hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n3 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const double2 *)T2, T3, (const double2 *)(dph + px.size() + py.size()), o3, Lz, W,
+                       (long)W * W);
+    TM_HIP(hipGetLastError());
+    const int n_mom = (int)mom.size();
+    std::vector<int> ml(3 * n_mom);
+    for (int m = 0; m < n_mom; m++)
+        for (int d = 0; d < 3; d++) ml[3 * m + d] = mom[m].n[d];
+    int *dm = (int *)ws_get(c, "mom_list", sizeof(int) * 3 * n_mom);
+    upload(dm, ml.data(), sizeof(int) * ml.size(), s);
+    double2 *dout = (double2 *)ws_get(c, "mom_out", sizeof(double2) * n_mom * Lt * 16);
+    hipLaunchKernelGGL(k_pick_momenta, dim3((n_mom * Lt * 16 + 255) / 256), dim3(256), 0, s, (const double2 *)T3,
+                       (const int *)dm, n_mom, Lt, W, N, dout);
+    TM_HIP(hipGetLastError());
+    out.resize((size_t)n_mom * Lt * 16);
+    download(c, out.data(), dout, sizeof(double2) * out.size(), s);
+}

@@ -96,17 +96,31 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
 void outer_slices_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
                        std::vector<cx<double>> &out, hipStream_t s);
 // Loops from outer products: L_n(t) = coef * sum_ab G[a][b] C[t][b][a] with
-// G = Gamma_n (pre = false) or gamma5 Gamma_n (pre = true); out [16][Lt]
-void loops_from_outer(tm_ctx *c, const std::vector<cx<double>> &C, bool g5pre, cx<double> coef,
-                      cx<double> *out);
+// G = Gamma_n (pre = false) or gamma5 Gamma_n (pre = true); C [Lt][16],
+// out [16][Lt]
+void loops_from_outer(tm_ctx *c, const cx<double> *C, bool g5pre, cx<double> coef, cx<double> *out);
+
+// spatial momentum p = 2 pi (n_x / L_x, n_y / L_y, n_z / L_z)
+struct Momentum {
+    int n[3];
+};
+// all n with |n|^2 <= p2max, by |n|^2 then lexicographically; (0,0,0) first
+std::vector<Momentum> momenta_list(int p2max);
+// every |n_i| must stay below L_i / 2 (distinct momenta on the lattice)
+void check_momenta(tm_ctx *c, int p2max);
+// momentum-projected outer products, out [n_mom][Lt][16] (momentum.hip)
+void outer_momenta_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
+                        const std::vector<Momentum> &mom, std::vector<cx<double>> &out, hipStream_t s);
 // exactly known part of the hopping expansion for ultra-local insertions
 void hpe_exact_part(tm_ctx *c, double epsp, cx<double> *out /* [16][Lt] */);
 
 // per-noise loops of one noise vector's sources (ee, eo) and solutions (se,
-// so), estimators in mask order, into dst [n_est][16][Lt]; uses c->stream
+// so), estimators in mask order, into dst [n_est][16][Lt], or with mom
+// [n_est][n_mom][16][Lt]; uses c->stream
 void contract_noise(tm_ctx *c, int estimators, const void *ee, const void *eo, const void *se, const void *so,
-                    int nrhs, double epsp, cx<double> *dst);
+                    int nrhs, double epsp, cx<double> *dst, const std::vector<Momentum> *mom = nullptr);
 hipStream_t s_of(tm_ctx *c);
 
+// loops [n_est][16][Lt] (mom = null) or [n_est][n_mom][16][Lt]
 int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noise, tm_loop_stats *stats,
-              hipStream_t s);
+              hipStream_t s, const std::vector<Momentum> *mom = nullptr);

@@ -491,7 +491,7 @@ void outer_slices_host(tm_ctx *c, const void *ve, const void *vo, const void *we
     download(c, out.data(), d, sizeof(double) * 32 * Lt, s);
 }
 
-void loops_from_outer(tm_ctx *c, const std::vector<cx<double>> &C, bool g5pre, cx<double> coef, cx<double> *out)
+void loops_from_outer(tm_ctx *c, const cx<double> *C, bool g5pre, cx<double> coef, cx<double> *out)
 {
     const int Lt = c->geo.L[3];
     cx<double> g5[4][4];
@@ -536,33 +536,39 @@ void hpe_exact_part(tm_ctx *c, double e, cx<double> *out)
 }
 
 void contract_noise(tm_ctx *c, int estimators, const void *ee, const void *eo, const void *se, const void *so,
-                    int nrhs, double epsp, cx<double> *dst)
+                    int nrhs, double epsp, cx<double> *dst, const std::vector<Momentum> *mom)
 {
     const int Lt = c->geo.L[3];
-    const size_t per = (size_t)16 * Lt;
+    const size_t per_m = (size_t)16 * Lt;
+    const int n_mom = mom ? (int)mom->size() : 1;
+    const size_t per = per_m * n_mom;
     const size_t f64 = field_bytes(c, TM_F64, nrhs);
     std::vector<cx<double>> C;
+    // outer products of (v, w), then the Gamma insertions per momentum
+    auto outer_loops = [&](const void *ve, const void *vo, const void *we, const void *wo, bool g5pre,
+                           cx<double> coef, cx<double> *out) {
+        if (mom) {
+            outer_momenta_host(c, ve, vo, we, wo, nrhs, *mom, C, s_of(c));
+            for (int m = 0; m < n_mom; m++) loops_from_outer(c, C.data() + per_m * m, g5pre, coef, out + per_m * m);
+        } else {
+            outer_slices_host(c, ve, vo, we, wo, nrhs, C, s_of(c));
+            loops_from_outer(c, C.data(), g5pre, coef, out);
+        }
+    };
     int k = 0;
-    if (estimators & TM_EST_STD) {
-        outer_slices_host(c, se, so, ee, eo, nrhs, C, s_of(c));
-        loops_from_outer(c, C, false, cx<double>{1, 0}, dst + per * k++);
-    }
-    if (estimators & TM_EST_ONE_END) {
-        outer_slices_host(c, se, so, se, so, nrhs, C, s_of(c));
-        loops_from_outer(c, C, true, cx<double>{0, 2.0 * epsp}, dst + per * k++);
-    }
+    if (estimators & TM_EST_STD) outer_loops(se, so, ee, eo, false, cx<double>{1, 0}, dst + per * k++);
+    if (estimators & TM_EST_ONE_END) outer_loops(se, so, se, so, true, cx<double>{0, 2.0 * epsp}, dst + per * k++);
     if (estimators & TM_EST_HPE) {
         void *he = ws_get(c, "l_h_e", f64), *ho = ws_get(c, "l_h_o", f64);
         copy_field(he, se, f64, s_of(c));
         copy_field(ho, so, f64, s_of(c));
         op_bh_power(c, he, ho, nrhs, epsp, 4, s_of(c));
-        outer_slices_host(c, he, ho, ee, eo, nrhs, C, s_of(c));
-        loops_from_outer(c, C, false, cx<double>{1, 0}, dst + per * k++);
+        outer_loops(he, ho, ee, eo, false, cx<double>{1, 0}, dst + per * k++);
     }
 }
 
 int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noise, tm_loop_stats *stats,
-              hipStream_t s)
+              hipStream_t s, const std::vector<Momentum> *mom)
 {
     const double t0 = now_s();
     TM_REQUIRE(p != nullptr && loops != nullptr, "null argument");
@@ -585,8 +591,9 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
     const size_t f64 = field_bytes(c, TM_F64, nrhs);
     void *ee = ws_get(c, "l_eta_e", f64), *eo = ws_get(c, "l_eta_o", f64);
     void *se = ws_get(c, "l_s_e", f64), *so = ws_get(c, "l_s_o", f64);
-    const size_t per = (size_t)16 * Lt;
-    // per-noise loops [noise][prec 0 hp, 1 lp][est][16][Lt]
+    // per estimator: [n_mom][16][Lt] (one momentum, p = 0, without mom)
+    const size_t per = (size_t)16 * Lt * (mom ? mom->size() : 1);
+    // per-noise loops [noise][prec 0 hp, 1 lp][est][per]
     std::vector<cx<double>> pn((size_t)n_noise * 2 * n_est * per, cx<double>{0, 0});
     tm_loop_stats st{};
     int status = TM_OK;
@@ -594,7 +601,7 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
 
     auto contract = [&](int noise, int slot) {
         contract_noise(c, p->estimators, ee, eo, se, so, nrhs, epsp,
-                       &pn[((size_t)noise * 2 + slot) * n_est * per]);
+                       &pn[((size_t)noise * 2 + slot) * n_est * per], mom);
     };
 
     for (int k = 0; k < n_noise; k++) {
@@ -627,7 +634,9 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
     }
 
     // TSM combination (eq. estiTSM) or the plain mean, per estimator
-    std::vector<cx<double>> ex(per);
+    // the exact HPE part is the same at every site: it enters p = 0 only
+    // (the first 16 Lt entries; momenta_list puts (0,0,0) first)
+    std::vector<cx<double>> ex(per, cx<double>{0, 0});
     if (p->estimators & TM_EST_HPE) hpe_exact_part(c, epsp, ex.data());
     for (int k = 0; k < n_est; k++) {
         cx<double> *dst = (cx<double> *)loops + (size_t)k * per;

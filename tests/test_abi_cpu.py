@@ -71,3 +71,26 @@ def test_ptc_structs_and_null_context():
     assert P.tm_ptc_apply(None, None, None, 1, None) == P.TM_ERR_ARG
     assert P.tm_ptc_pairs_reserve(None, 1, P.TM_F32) == P.TM_ERR_ARG
     assert P.tm_ptc_train(None, None, None, None, None) == P.TM_ERR_ARG
+
+
+@pytest.mark.parametrize("p2max", [0, 1, 2, 3, 4, 9, 12])
+def test_momentum_list_matches_oracle(p2max):
+    """tm_momenta is host logic: same vectors, same order as the oracle's
+    enumeration, and argument errors come back as TM_ERR_ARG."""
+    import numpy as np
+    import oracle as O
+    import paper_1309_2256_amd as P
+    assert np.array_equal(P.momenta(p2max), O.momenta(p2max))
+    n = ctypes.c_int(0)
+    assert P.tm_momenta(-1, ctypes.byref(n), None) == P.TM_ERR_ARG
+    assert P.tm_momenta(p2max, None, None) == P.TM_ERR_ARG
+    small = (ctypes.c_int * 3)()
+    n.value = 0
+    if p2max > 0:
+        assert P.tm_momenta(p2max, ctypes.byref(n), small) == P.TM_ERR_ARG
+
+
+def test_momentum_calls_on_null_context():
+    import paper_1309_2256_amd as P
+    assert P.tm_contract_momentum(None, None, None, 1, 1, 1, 0, None, None) == P.TM_ERR_ARG
+    assert P.tm_loops_momentum(None, None, 0, None, None, None, None) == P.TM_ERR_ARG
