@@ -17,8 +17,11 @@ marshals arguments and writes out the estimator formulas of the paper:
   * stochastic estimate of M^-1 and the standard loop (section II.A, eqs.
     estiM and loopSt),
   * the Truncated Solver Method combination (section II.B, eq. estiTSM),
-  * the one-end trick (section II.C, eq. loopVv),
-  * the Hopping Parameter Expansion (section II.E, eqs. HPE and loopHPE1).
+  * the one-end trick (section II.C, eq. loopVv) and its generalised form
+    (eq. loopStD),
+  * the Hopping Parameter Expansion (section II.E, eqs. HPE and loopHPE1),
+  * one-derivative insertions (the covariant-derivative contraction of
+    section III) and the momentum projection (the Fourier step of section III).
 """
 import ctypes
 import os
@@ -261,17 +264,115 @@ def hpe_exact(L, kappa, eps, t_bc, U):
 
 # ---------------------------------------------------------------- estimators
 
-EST_STD, EST_ONE_END, EST_HPE = 1, 2, 4
+EST_STD, EST_ONE_END, EST_HPE, EST_GEN_ONE_END = 1, 2, 4, 8
+EST_ALL_ORDER = (EST_STD, EST_ONE_END, EST_HPE, EST_GEN_ONE_END)
 
 
-def loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators):
+def wilson(L, kappa, t_bc, U, psi):
+    """D_W psi = (1 + H) psi: the operator M without its twisted-mass term."""
+    return apply_M(L, kappa, 0.0, t_bc, U, psi)
+
+
+def g5_field(psi):
+    return np.einsum("ab,...bc->...ac", gamma(15), psi)
+
+
+def contract_gen(L, kappa, t_bc, U, s):
+    """2 sum_{x in t} s^dag gamma5 Gamma_n gamma5 D_W s (eq. loopStD) -> (16, Lt),
+    written as 2 (gamma5 s)^dag Gamma_n (gamma5 D_W s) (gamma5 is Hermitian)."""
+    s = _spinor(L, s)
+    return 2.0 * contract_std(L, g5_field(s), g5_field(wilson(L, kappa, t_bc, U, s)))
+
+
+def _shift(L, f, mu, step):
+    """The field at x + step * mu_hat, as an array over x (periodic wrap)."""
+    c = list(_site_coords(L))
+    c[mu] = (c[mu] + step) % L[mu]
+    return f[c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))]
+
+
+def _phased_links(L, t_bc, U):
+    """U_mu(x) with the fermion time-boundary factor on links from t = Lt-1 to 0."""
+    U = _links(L, U).copy()
+    t = _site_coords(L)[3]
+    U[3, t == L[3] - 1] *= t_bc
+    return U
+
+
+def derivative_outer(L, t_bc, U, left, right):
+    """Spin matrices P_mu(x)[a][b] of the one-derivative bilinear with the
+    symmetric left-right covariant derivative attributed to site x,
+      left^dag G D_mu right (x) = sum_ab G[a][b] P_mu(x)[a][b],
+      P_mu = 1/4 [ l(x)^* U_mu(x) r(x+mu) - l(x)^* U_mu(x-mu)^dag r(x-mu)
+                   - l(x+mu)^* U_mu(x)^dag r(x) + l(x-mu)^* U_mu(x-mu) r(x) ]
+    with colour contracted through the link in each term -> (4, V, 4, 4)."""
+    Uph = _phased_links(L, t_bc, U)
+    l, r = _spinor(L, left), _spinor(L, right)
+    out = np.zeros((4, volume(L), 4, 4), dtype=np.complex128)
+    for mu in range(4):
+        Uf = Uph[mu]                      # U_mu(x)
+        Ub = _shift(L, Uph[mu], mu, -1)   # U_mu(x - mu)
+        t1 = np.einsum("xac,xcd,xbd->xab", l.conj(), Uf, _shift(L, r, mu, 1))
+        t2 = np.einsum("xac,xdc,xbd->xab", l.conj(), Ub.conj(), _shift(L, r, mu, -1))
+        t3 = np.einsum("xad,xcd,xbc->xab", _shift(L, l, mu, 1).conj(), Uf.conj(), r)
+        t4 = np.einsum("xad,xdc,xbc->xab", _shift(L, l, mu, -1).conj(), Ub, r)
+        out[mu] = 0.25 * (t1 - t2 - t3 + t4)
+    return out
+
+
+def _gammas(form):
+    g5 = gamma(15)
+    Gs = [gamma(n) for n in range(16)]
+    if form == "g5":
+        Gs = [g5 @ G for G in Gs]
+    elif form == "g5g5":
+        Gs = [g5 @ G @ g5 for G in Gs]
+    return np.array(Gs)
+
+
+def insertion_densities(L, kappa, eps, t_bc, U, eta, s, estimator, derivative=False):
+    """Per-site loop densities of one (source, solution) pair -> (n_ins, V),
+    n_ins = 16 ultra-local Gamma_n, then (derivative) 16 per direction mu:
+      STD      eta^dag X s                       (eq. loopSt)
+      ONE_END  2 i eps s^dag gamma5 X s          (eq. loopVv)
+      GEN      2 s^dag gamma5 X gamma5 D_W s     (eq. loopStD)
+      HPE      eta^dag X (BH)^4 s                (eq. loopHPE1, ultra-local only)."""
+    if estimator == EST_STD:
+        left, right, form, coef = eta, s, "", 1.0
+    elif estimator == EST_ONE_END:
+        left, right, form, coef = s, s, "g5", 2j * eps
+    elif estimator == EST_GEN_ONE_END:
+        left, right, form, coef = s, wilson(L, kappa, t_bc, U, s), "g5g5", 2.0
+    elif estimator == EST_HPE:
+        assert not derivative, "HPE takes ultra-local insertions only"
+        left, right, form, coef = eta, bh_power(L, kappa, eps, t_bc, U, s, 4), "", 1.0
+    else:
+        raise ValueError(estimator)
+    Gs = _gammas(form)
+    l, r = _spinor(L, left), _spinor(L, right)
+    local = np.einsum("nab,xac,xbc->nx", Gs, l.conj(), r)
+    if not derivative:
+        return coef * local
+    P = derivative_outer(L, t_bc, U, l, r)
+    der = np.einsum("nab,mxab->mnx", Gs, P).reshape(64, -1)
+    return coef * np.concatenate([local, der])
+
+
+def slice_sums(L, dens):
+    """sum over each time slice (t is the slowest site index) -> (..., Lt)."""
+    return dens.reshape(dens.shape[:-1] + (L[3], -1)).sum(axis=-1)
+
+
+def loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators, derivative=False):
     """Per-noise loops from the sources of one noise vector (one entry per
-    dilution component) and their solutions.  Returns {estimator: (16, Lt)}.
+    dilution component) and their solutions.  Returns {estimator: (n_ins, Lt)}.
 
     STD:     sum_d eta_d^dag Gamma s_d                  (eq. loopSt)
     ONE_END: 2 i eps sum_d s_d^dag gamma5 Gamma s_d     (eq. loopVv, lhs)
     HPE:     sum_d eta_d^dag Gamma (BH)^4 s_d           (eq. loopHPE1); the
              exactly known part is added once per estimate, not per noise.
+    GEN:     2 sum_d s_d^dag gamma5 Gamma gamma5 D_W s_d (eq. loopStD)
+    With derivative the one-derivative insertions follow the 16 local ones.
     """
     out = {}
     if estimators & EST_STD:
@@ -279,8 +380,17 @@ def loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators):
     if estimators & EST_ONE_END:
         out[EST_ONE_END] = sum(contract_oneend(L, eps, s) for s in sols)
     if estimators & EST_HPE:
+        assert not derivative, "HPE takes ultra-local insertions only"
         out[EST_HPE] = sum(contract_std(L, e, bh_power(L, kappa, eps, t_bc, U, s, 4))
                            for e, s in zip(etas, sols))
+    if estimators & EST_GEN_ONE_END:
+        out[EST_GEN_ONE_END] = sum(contract_gen(L, kappa, t_bc, U, s) for s in sols)
+    if derivative:
+        for e in (EST_STD, EST_ONE_END, EST_GEN_ONE_END):
+            if estimators & e:
+                der = sum(slice_sums(L, insertion_densities(L, kappa, eps, t_bc, U, et, s, e, True)[16:])
+                          for et, s in zip(etas, sols))
+                out[e] = np.concatenate([out[e], der])
     return out
 
 
@@ -337,20 +447,30 @@ def contract_momentum(L, eps, eta, s, estimators, moms):
     return out
 
 
-def loops_momentum_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators, moms):
-    """As loops_for_solution, momentum resolved: {estimator: (n_mom, 16, Lt)}."""
+def contract_insertions(L, kappa, eps, t_bc, U, eta, s, estimators, derivative, moms):
+    """Momentum-resolved loops of given fields for any estimators and
+    insertions -> {estimator: (n_mom, n_ins, Lt)}."""
+    out = {}
+    for e in EST_ALL_ORDER:
+        if estimators & e:
+            d = insertion_densities(L, kappa, eps, t_bc, U, eta, s, e, derivative)
+            out[e] = np.transpose(project_momenta(L, d, moms), (1, 0, 2))
+    return out
+
+
+def loops_momentum_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators, moms,
+                                derivative=False):
+    """As loops_for_solution, momentum resolved: {estimator: (n_mom, n_ins, Lt)}."""
     out = {}
     for e, s in zip(etas, sols):
-        part = contract_momentum(L, eps, e, s, estimators & (EST_STD | EST_ONE_END), moms)
-        if estimators & EST_HPE:
-            part[EST_HPE] = contract_momentum(L, eps, e, bh_power(L, kappa, eps, t_bc, U, s, 4),
-                                              EST_STD, moms)[EST_STD]
+        part = contract_insertions(L, kappa, eps, t_bc, U, e, s, estimators, derivative, moms)
         for k, v in part.items():
             out[k] = out.get(k, 0) + v
     return out
 
 
-def loops_momentum(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, moms, dilution=False):
+def loops_momentum(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, moms, dilution=False,
+                   derivative=False):
     """As loops, momentum resolved ({estimator: (n_mom, 16, Lt)}).  The exact
     HPE part is the same at every site of a slice, so its Fourier sum over the
     slice vanishes for p != 0 and it enters p = 0 only."""
@@ -360,7 +480,7 @@ def loops_momentum(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, moms,
         etas = dilute_spin_colour(eta) if dilution else [eta]
         sols, _, _ = solve_sources(L, kappa, eps, t_bc, U, etas, tol)
         per_noise.append(loops_momentum_for_solution(L, kappa, eps, t_bc, U, etas, sols,
-                                                     estimators, moms))
+                                                     estimators, moms, derivative))
     mean = {e: sum(p[e] for p in per_noise) / n_noise for e in per_noise[0]}
     if estimators & EST_HPE:
         assert tuple(moms[0]) == (0, 0, 0)
@@ -394,16 +514,18 @@ def solve_sources(L, kappa, eps, t_bc, U, srcs, tol, maxiter=100000):
 
 
 def loops(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, dilution=False,
-          noise_offset=0):
+          noise_offset=0, derivative=False):
     """Plain stochastic loop estimate from n_noise Z4 noise vectors solved to
-    tol (mean over noises, eq. estiM / loopSt / loopVv / loopHPE1).
-    Returns ({estimator: (16, Lt)}, per_noise list of {estimator: (16, Lt)})."""
+    tol (mean over noises, eq. estiM / loopSt / loopVv / loopHPE1 / loopStD).
+    Returns ({estimator: (n_ins, Lt)}, per_noise list of {estimator: (n_ins, Lt)}),
+    n_ins = 16, or 80 with the one-derivative insertions."""
     per_noise = []
     for r in range(noise_offset, noise_offset + n_noise):
         eta = noise_z4(L, seed, r)
         etas = dilute_spin_colour(eta) if dilution else [eta]
         sols, _, _ = solve_sources(L, kappa, eps, t_bc, U, etas, tol)
-        per_noise.append(loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators))
+        per_noise.append(loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators,
+                                            derivative))
     mean = {e: sum(p[e] for p in per_noise) / n_noise for e in per_noise[0]}
     if estimators & EST_HPE:
         mean[EST_HPE] = mean[EST_HPE] + hpe_exact(L, kappa, eps, t_bc, U)

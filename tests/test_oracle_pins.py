@@ -486,3 +486,106 @@ def test_loops_momentum_zero_momentum_is_loops():
     for e in (O.EST_STD, O.EST_ONE_END, O.EST_HPE):
         assert np.abs(mm[e][0] - ref[e]).max() < 1e-10 * np.abs(ref[e]).max()
     assert np.abs(mm[O.EST_HPE][1:] - pn[0][O.EST_HPE][1:]).max() == 0
+
+
+# ---------------------------------------------------------------- generalised one-end, derivatives
+
+def unit_source_loops(L, kappa, eps, t_bc, U, Sinv, estimator, derivative):
+    """Full dilution: every unit source j with solution column j of a dense
+    inverse, contracted by the oracle's estimator and summed -> (n_ins, Lt)."""
+    V = int(np.prod(L))
+    tot = 0
+    for j in range(12 * V):
+        e = np.zeros((V, 4, 3), dtype=complex)
+        e.reshape(-1)[j] = 1
+        sol = Sinv[:, j].reshape(V, 4, 3)
+        tot = tot + O.slice_sums(L, O.insertion_densities(L, kappa, eps, t_bc, U, e, sol,
+                                                          estimator, derivative))
+    return tot
+
+
+@pytest.fixture(scope="module")
+def dense4():
+    """4x2x2x4 lattice, random links: dense M(+mu), M(-mu) and their inverses."""
+    L, kappa, eps = (4, 2, 2, 4), 0.124, 0.09
+    U = S.gauge_links(L, 0.5, 23)
+    Mu = dense(lambda v: O.apply_M(L, kappa, eps, -1, U, v), L)
+    Md = dense(lambda v: O.apply_M(L, kappa, -eps, -1, U, v), L)
+    return dict(L=L, kappa=kappa, eps=eps, U=U, Mui=np.linalg.inv(Mu), Mdi=np.linalg.inv(Md))
+
+
+def test_generalised_one_end_local_dense(dense2):
+    """eq. loopStD with full dilution equals Tr_t(Gamma M_u^-1) + Tr_t(Gamma M_d^-1)
+    for all 16 Gamma (dense LU traces), through the per-slice C contraction."""
+    d = dense2
+    L, kappa, eps, U = d["L"], d["kappa"], d["eps"], d["U"]
+    V = int(np.prod(L))
+    tot = 0
+    for j in range(12 * V):
+        tot = tot + O.contract_gen(L, kappa, -1, U, d["Mi"][:, j].reshape(V, 4, 3))
+    want = slice_traces(L, d["Mi"]) + slice_traces(L, d["Mdi"])
+    assert np.abs(tot - want).max() < 1e-11
+
+
+def test_derivative_free_field_closed_form():
+    """U = 1: the one-derivative STD loop with full dilution equals
+    (V_s / V) sum_p i sin(p_mu) tr[Gamma_n S(p)], S(p) the inverse of
+    A + i sum_nu gamma_nu 2 kappa sin p_nu + i eps gamma5 (times 1 in colour),
+    p_t = (2n + 1) pi / Lt; all 16 x 4 insertions at every time slice."""
+    L, kappa, eps = (4, 2, 2, 4), 0.124, 0.1
+    U = S.unit_links(L)
+    V, Lt = int(np.prod(L)), L[3]
+    Si = np.linalg.inv(dense(lambda v: O.apply_M(L, kappa, eps, -1, U, v), L))
+    got = unit_source_loops(L, kappa, eps, -1, U, Si, O.EST_STD, True)[16:].reshape(4, 16, Lt)
+    gam = [O.gamma(n) for n in (1, 2, 4, 8)]      # gamma_x, gamma_y, gamma_z, gamma_t
+    want = np.zeros((4, 16), dtype=complex)
+    for p in momenta(L, -1):
+        A = 1 - 2 * kappa * np.cos(p).sum()
+        Mp = A * np.eye(4) + 1j * eps * G5
+        for nu in range(4):
+            Mp = Mp + 2j * kappa * np.sin(p[nu]) * gam[nu]
+        Sp = np.linalg.inv(Mp)
+        for mu in range(4):
+            for n in range(16):
+                want[mu, n] += 1j * np.sin(p[mu]) * 3 * np.trace(O.gamma(n) @ Sp)
+    want *= (V // Lt) / V
+    assert np.abs(want).max() > 1e-2
+    assert np.abs(got - want[:, :, None]).max() < 1e-12
+    # the ultra-local block is the plain per-slice contraction
+    loc = unit_source_loops(L, kappa, eps, -1, U, Si, O.EST_STD, False)
+    assert np.abs(loc - sum(O.contract_std(L, np.eye(12 * V)[j].reshape(V, 4, 3),
+                                           Si[:, j].reshape(V, 4, 3))
+                            for j in range(12 * V))).max() < 1e-12
+
+
+def test_derivative_dense_operator_form(dense4):
+    """Random links: the one-derivative STD loop with full dilution equals
+    (1/4) Tr_t[Gamma (nabla_mu M^-1 + M^-1 nabla_mu)], nabla_mu = T_{+mu} - T_{-mu}
+    built densely from the parallel transports (the bilinear's operator form:
+    the right-derivative terms give Gamma nabla, the left-derivative terms
+    nabla Gamma, both restricted to the slice by cyclicity)."""
+    d = dense4
+    L, kappa, eps, U = d["L"], d["kappa"], d["eps"], d["U"]
+    got = unit_source_loops(L, kappa, eps, -1, U, d["Mui"], O.EST_STD, True)[16:]
+    for mu in range(4):
+        nab = dense(lambda v: O.transport(L, -1, U, 1 + mu, v) - O.transport(L, -1, U, 5 + mu, v), L)
+        K = nab @ d["Mui"] + d["Mui"] @ nab
+        want = 0.25 * slice_traces(L, K)
+        assert np.abs(got[16 * mu:16 * mu + 16] - want).max() < 1e-12, mu
+
+
+def test_derivative_and_local_estimator_identities(dense4):
+    """For every one of the 80 insertions X (local and one-derivative), with
+    full dilution of s = M_u^-1 eta:  GEN = Tr(M_u^-1 X) + Tr(M_d^-1 X)
+    (eq. loopStD) and ONE_END = Tr(M_d^-1 X) - Tr(M_u^-1 X) (eq. loopVv),
+    the traces being the STD estimator on M_u^-1 and M_d^-1 columns."""
+    d = dense4
+    L, kappa, eps, U = d["L"], d["kappa"], d["eps"], d["U"]
+    tu = unit_source_loops(L, kappa, eps, -1, U, d["Mui"], O.EST_STD, True)
+    td = unit_source_loops(L, kappa, -eps, -1, U, d["Mdi"], O.EST_STD, True)
+    gen = unit_source_loops(L, kappa, eps, -1, U, d["Mui"], O.EST_GEN_ONE_END, True)
+    one = unit_source_loops(L, kappa, eps, -1, U, d["Mui"], O.EST_ONE_END, True)
+    scale = np.abs(tu).max()
+    assert np.abs(gen - (tu + td)).max() < 1e-11 * scale
+    assert np.abs(one - (td - tu)).max() < 1e-11 * scale
+    assert np.abs(tu[16:]).max() > 1e-3 * scale       # the derivative block is not trivially zero
