@@ -237,7 +237,9 @@ def main():
 def momentum_leg(P, torch, dev, ctx, L, nrhs, p2max=9, reps=3):
     """Momentum projection on 32^3x64: standard and one-end loops of 12
     resident right-hand sides (complex128 fields) for every momentum with
-    |n|^2 <= 9, against the per-slice (p = 0 only) contraction."""
+    |n|^2 <= 9, against the per-slice (p = 0 only) contraction; and the
+    paper's full loop output, 160 insertions (16 local + 64 one-derivative,
+    one-end and generalised one-end) at the same momenta."""
     V = int(np.prod(L))
     g = torch.Generator(device=dev)
     g.manual_seed(7)
@@ -245,10 +247,14 @@ def momentum_leg(P, torch, dev, ctx, L, nrhs, p2max=9, reps=3):
     sol = torch.randn((nrhs, V, 4, 3), dtype=torch.complex128, device=dev, generator=g)
     est = P.TM_EST_STD | P.TM_EST_ONE_END
     n_mom = len(P.momenta(p2max))
-    res = {"workload": "32^3x64, %d RHS, STD + one-end loops, %d momenta (|n|^2 <= %d)"
+    res = {"workload": "32^3x64, %d RHS, STD + one-end loops, %d momenta (|n|^2 <= %d); "
+                       "160 insertions: one-end + generalised one-end, local + one-derivative"
                        % (nrhs, n_mom, p2max)}
+    est160 = P.TM_EST_ONE_END | P.TM_EST_GEN_ONE_END
     for name, fn in (("per_slice", lambda: ctx.contract(eta, sol, nrhs, est)),
-                     ("momentum", lambda: ctx.contract_momentum(eta, sol, nrhs, est, p2max))):
+                     ("momentum", lambda: ctx.contract_momentum(eta, sol, nrhs, est, p2max)),
+                     ("insertions160", lambda: ctx.contract_momentum(eta, sol, nrhs, est160, p2max,
+                                                                    derivative=1))):
         fn()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -256,8 +262,9 @@ def momentum_leg(P, torch, dev, ctx, L, nrhs, p2max=9, reps=3):
             fn()
         torch.cuda.synchronize()
         res[name + "_ms"] = (time.perf_counter() - t) / reps * 1e3
-    print("[bench/momentum] per-slice %.1f ms, %d momenta %.1f ms"
-          % (res["per_slice_ms"], n_mom, res["momentum_ms"]), file=sys.stderr, flush=True)
+    print("[bench/momentum] per-slice %.1f ms, %d momenta %.1f ms, 160 insertions x %d momenta "
+          "%.1f ms" % (res["per_slice_ms"], n_mom, res["momentum_ms"], n_mom,
+                       res["insertions160_ms"]), file=sys.stderr, flush=True)
     del eta, sol
     torch.cuda.empty_cache()
     return res

@@ -195,9 +195,24 @@ enum {
     TM_EST_ONE_END = 2, /* 2 i eps sum_x s^dag gamma5 Gamma_n s  (eq. loopVv);
                            estimates Tr_t(Gamma M_d^-1) - Tr_t(Gamma M_u^-1)
                            for s = M_u^-1 eta (mu_sign = +1)                    */
-    TM_EST_HPE = 4      /* exact part + sum_x eta^dag Gamma_n (BH)^4 s (eqs. HPE,
-                           loopHPE1); requires every L_mu >= 4                  */
+    TM_EST_HPE = 4,     /* exact part + sum_x eta^dag Gamma_n (BH)^4 s (eqs. HPE,
+                           loopHPE1); requires every L_mu >= 4; ultra-local
+                           insertions only                                      */
+    TM_EST_GEN_ONE_END = 8 /* 2 sum_x s^dag gamma5 Gamma_n gamma5 D_W s, D_W = 1 + H
+                           (eq. loopStD, generalised one-end trick); estimates
+                           Tr_t(Gamma M_u^-1) + Tr_t(Gamma M_d^-1)             */
 };
+
+/* Insertions per estimator.  derivative = 0: the 16 ultra-local Gamma_n.
+ * derivative = 1: also the one-derivative insertions of sec. III (the
+ * covariant-derivative kernel), n_ins = 80, insertion 16 (1 + mu) + n for
+ * direction mu = 0..3 (x, y, z, t): the bilinear w^dag Gamma_n D_mu v with
+ * the symmetric left-right covariant derivative attributed to site x,
+ *   1/4 [w^dag(x) G U_mu(x) v(x+mu) - w^dag(x) G U_mu(x-mu)^dag v(x-mu)
+ *        - w^dag(x+mu) U_mu(x)^dag G v(x) + w^dag(x-mu) U_mu(x-mu) G v(x)],
+ * time-boundary phase on links that cross t = Lt-1 <-> 0; (w, v, G) = (eta,
+ * s, Gamma_n) for STD, (s, s, gamma5 Gamma_n) times 2 i eps for ONE_END,
+ * (s, D_W s, gamma5 Gamma_n gamma5) times 2 for GEN_ONE_END. */
 
 typedef enum { TM_DIL_NONE = 0, TM_DIL_SPIN_COLOUR = 1 } tm_dilution;
 
@@ -211,7 +226,8 @@ typedef struct {
     int dilution;         /* tm_dilution                                          */
     int estimators;       /* TM_EST_* mask                                        */
     int mu_sign;          /* flavour inverted: +1 u, -1 d                         */
-    int reserved;
+    int derivative;       /* 0: 16 ultra-local insertions; 1: also one-derivative
+                             (80 insertions); not with TM_EST_HPE              */
     tm_solve_params hp;   /* high-precision solve parameters                      */
     tm_solve_params lp;   /* low-precision solve parameters (n_lp > 0)            */
 } tm_loop_params;
@@ -226,9 +242,10 @@ typedef struct {
 /* Estimate the disconnected loops L_n(t) for the 16 Gamma_n at every time
  * slice t from Z4 volume noise.  Noise vector r has entries i^k, k the top two
  * bits of SplitMix64 output ((r*V + s)*4 + spin)*3 + colour of `seed`.
- *   loops      host, [n_est][16][Lt] complex double, estimators in mask order
- *              (STD, ONE_END, HPE); the TSM combination (or plain mean).
- *   per_noise  host or NULL: [n_noise][2][n_est][16][Lt] complex double,
+ *   loops      host, [n_est][n_ins][Lt] complex double, estimators in mask
+ *              order (STD, ONE_END, HPE, GEN_ONE_END); the TSM combination
+ *              (or plain mean).
+ *   per_noise  host or NULL: [n_noise][2][n_est][n_ins][Lt] complex double,
  *              index 0 = high precision, 1 = low precision (zero when absent),
  *              n_noise = n_hp + n_lp.  The HPE entries hold only the
  *              stochastic part; its exact part is added to `loops` once.
@@ -238,9 +255,10 @@ int tm_loops(tm_ctx *ctx, const tm_loop_params *p, double *loops, double *per_no
              tm_loop_stats *stats, tm_stream stream);
 
 /* Contract given full FP64 spinors (device, canonical, nrhs each) into
- * per-time-slice loops for the estimators in `estimators` (STD uses eta and s,
- * ONE_END uses s only; HPE is not accepted here).  Sums over the nrhs pairs.
- * out: host [n_est][16][Lt] complex double. */
+ * per-time-slice loops of the 16 ultra-local insertions for the estimators in
+ * `estimators` (STD uses eta and s, ONE_END and GEN_ONE_END use s only and
+ * GEN_ONE_END the gauge field; HPE is not accepted here).  Sums over the nrhs
+ * pairs.  out: host [n_est][16][Lt] complex double. */
 int tm_contract(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int estimators,
                 int mu_sign, double *out, tm_stream stream);
 
@@ -256,14 +274,15 @@ int tm_contract(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int e
  * receives [count][3] integers n and must hold *count entries on input. */
 int tm_momenta(int p2max, int *count, int *list);
 
-/* As tm_contract, momentum resolved: out host [n_est][n_mom][16][Lt] complex
- * double. */
+/* As tm_contract, momentum resolved and with the insertions of `derivative`
+ * (0 or 1, see the insertion list above): out host [n_est][n_mom][n_ins][Lt]
+ * complex double.  p2max = 0 gives the per-time-slice sums. */
 int tm_contract_momentum(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int estimators, int mu_sign,
-                         int p2max, double *out, tm_stream stream);
+                         int derivative, int p2max, double *out, tm_stream stream);
 
-/* As tm_loops, momentum resolved: loops host [n_est][n_mom][16][Lt];
- * per_noise host [n_noise][2][n_est][n_mom][16][Lt] or NULL.  The exact HPE
- * part (the same at every site) enters p = 0 only. */
+/* As tm_loops, momentum resolved: loops host [n_est][n_mom][n_ins][Lt];
+ * per_noise host [n_noise][2][n_est][n_mom][n_ins][Lt] or NULL.  The exact
+ * HPE part (the same at every site) enters p = 0 only. */
 int tm_loops_momentum(tm_ctx *ctx, const tm_loop_params *p, int p2max, double *loops, double *per_noise,
                       tm_loop_stats *stats, tm_stream stream);
 
@@ -295,7 +314,7 @@ int tm_batch_solve(tm_batch *batch, double *const *x, const double *const *b, co
 /* Per-instance loops (sec. II, as tm_loops) with p[i].n_hp noise vectors of
  * high-precision solves each (n_lp must be 0), all instances' sources solved
  * in one batch; p[i].hp must agree across instances in solver, inner_prec and
- * check_every.  loops[i]: host [n_est_i][16][Lt_i] complex double; stats:
+ * check_every.  loops[i]: host [n_est_i][n_ins_i][Lt_i] complex double; stats:
  * host array of n entries or NULL. */
 int tm_batch_loops(tm_batch *batch, const tm_loop_params *p, double *const *loops,
                    tm_loop_stats *stats, tm_stream stream);

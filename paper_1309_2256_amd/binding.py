@@ -27,7 +27,7 @@ TM_F64, TM_F32, TM_F16, TM_BF16 = 0, 1, 2, 3
 (TM_HOP_EO, TM_HOP_OE, TM_RINV_HOP_OE, TM_SCHUR, TM_SCHUR_DAG, TM_NORMAL, TM_FULL, TM_FULL_DAG,
  TM_RINV_HOP_EO) = range(9)
 TM_CG_F64, TM_CG_MIXED, TM_CG_LOW, TM_FGMRES, TM_FGMRES_PTC = 0, 1, 2, 3, 4
-TM_EST_STD, TM_EST_ONE_END, TM_EST_HPE = 1, 2, 4
+TM_EST_STD, TM_EST_ONE_END, TM_EST_HPE, TM_EST_GEN_ONE_END = 1, 2, 4, 8
 TM_DIL_NONE, TM_DIL_SPIN_COLOUR = 0, 1
 
 STATUS_NAMES = {0: "TM_OK", -1: "TM_ERR_ARG", -2: "TM_ERR_HIP", -3: "TM_ERR_OOM",
@@ -55,7 +55,7 @@ class tm_solve_stats(ctypes.Structure):
 class tm_loop_params(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("n_hp", ctypes.c_int), ("n_lp", ctypes.c_int),
                 ("noise_offset", ctypes.c_int), ("dilution", ctypes.c_int),
-                ("estimators", ctypes.c_int), ("mu_sign", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("estimators", ctypes.c_int), ("mu_sign", ctypes.c_int), ("derivative", ctypes.c_int),
                 ("hp", tm_solve_params), ("lp", tm_solve_params)]
 
 
@@ -98,7 +98,7 @@ _SIGS = {
     "tm_momenta": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_int)]),
     "tm_contract_momentum": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                            ctypes.c_int, _dp, _vp]),
+                                            ctypes.c_int, ctypes.c_int, _dp, _vp]),
     "tm_loops_momentum": (ctypes.c_int, [_vp, ctypes.POINTER(tm_loop_params), ctypes.c_int, _dp, _dp,
                                          ctypes.POINTER(tm_loop_stats), _vp]),
     "tm_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int]),
@@ -216,9 +216,10 @@ class Context:
     def loops(self, params, per_noise=False, stream=None, allow_noconv=False):
         n_est = bin(params.estimators).count("1")
         Lt = self.L[3]
-        out = np.zeros((n_est, 16, Lt), dtype=np.complex128)
+        n_ins = n_insertions(params.derivative)
+        out = np.zeros((n_est, n_ins, Lt), dtype=np.complex128)
         n_noise = params.n_hp + params.n_lp
-        pn = np.zeros((n_noise, 2, n_est, 16, Lt), dtype=np.complex128) if per_noise else None
+        pn = np.zeros((n_noise, 2, n_est, n_ins, Lt), dtype=np.complex128) if per_noise else None
         stats = tm_loop_stats()
         st = tm_loops(self.h, ctypes.byref(params), out.ctypes.data_as(_dp),
                       pn.ctypes.data_as(_dp) if pn is not None else None, ctypes.byref(stats),
@@ -275,21 +276,24 @@ class Context:
                                  hist.ctypes.data_as(_dp) if hist is not None else None, _stream(stream)))
         return st, hist
 
-    def contract_momentum(self, eta, s, nrhs, estimators, p2max, mu_sign=1, stream=None):
+    def contract_momentum(self, eta, s, nrhs, estimators, p2max, mu_sign=1, derivative=0,
+                          stream=None):
         n_est = bin(estimators).count("1")
         n_mom = len(momenta(p2max))
-        out = np.zeros((n_est, n_mom, 16, self.L[3]), dtype=np.complex128)
-        self._check(tm_contract_momentum(self.h, _ptr(eta), _ptr(s), nrhs, estimators, mu_sign, p2max,
-                                         out.ctypes.data_as(_dp), _stream(stream)))
+        out = np.zeros((n_est, n_mom, n_insertions(derivative), self.L[3]), dtype=np.complex128)
+        self._check(tm_contract_momentum(self.h, _ptr(eta), _ptr(s), nrhs, estimators, mu_sign,
+                                         derivative, p2max, out.ctypes.data_as(_dp),
+                                         _stream(stream)))
         return out
 
     def loops_momentum(self, params, p2max, per_noise=False, stream=None, allow_noconv=False):
         n_est = bin(params.estimators).count("1")
         n_mom = len(momenta(p2max))
         Lt = self.L[3]
-        out = np.zeros((n_est, n_mom, 16, Lt), dtype=np.complex128)
+        n_ins = n_insertions(params.derivative)
+        out = np.zeros((n_est, n_mom, n_ins, Lt), dtype=np.complex128)
         n_noise = params.n_hp + params.n_lp
-        pn = (np.zeros((n_noise, 2, n_est, n_mom, 16, Lt), dtype=np.complex128)
+        pn = (np.zeros((n_noise, 2, n_est, n_mom, n_ins, Lt), dtype=np.complex128)
               if per_noise else None)
         stats = tm_loop_stats()
         st = tm_loops_momentum(self.h, ctypes.byref(params), p2max, out.ctypes.data_as(_dp),
@@ -304,6 +308,11 @@ class Context:
         self._check(tm_contract(self.h, _ptr(eta), _ptr(s), nrhs, estimators, mu_sign,
                                 out.ctypes.data_as(_dp), _stream(stream)))
         return out
+
+
+def n_insertions(derivative):
+    """Insertions per estimator: 16 ultra-local, 80 with one-derivative ones."""
+    return 80 if derivative else 16
 
 
 def momenta(p2max):
@@ -364,7 +373,8 @@ class Batch:
         pa = (tm_loop_params * n)(*params_list)
         outs = []
         for c, p in zip(self.contexts, params_list):
-            outs.append(np.zeros((bin(p.estimators).count("1"), 16, c.L[3]), dtype=np.complex128))
+            outs.append(np.zeros((bin(p.estimators).count("1"), n_insertions(p.derivative), c.L[3]),
+                                 dtype=np.complex128))
         la = (_dp * n)(*[o.ctypes.data_as(_dp) for o in outs])
         stats = (tm_loop_stats * n)()
         st = tm_batch_loops(self.h, pa, la, stats, _stream(stream))

@@ -323,41 +323,30 @@ namespace {
 
 // tm_contract and tm_contract_momentum: mom = null for p = 0 per time slice
 int contract_fields(tm_ctx *c, const double *eta, const double *s_, int nrhs, int estimators, int mu_sign,
-                    double *out, tm_stream stream, const std::vector<Momentum> *mom)
+                    int derivative, double *out, tm_stream stream, const std::vector<Momentum> *mom)
 {
     TM_REQUIRE(s_ && out, "null pointer");
     TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
-    TM_REQUIRE(estimators > 0 && (estimators & ~(TM_EST_STD | TM_EST_ONE_END)) == 0,
-               "contractions accept TM_EST_STD and TM_EST_ONE_END");
+    TM_REQUIRE(estimators > 0 && (estimators & ~(TM_EST_STD | TM_EST_ONE_END | TM_EST_GEN_ONE_END)) == 0,
+               "contractions accept TM_EST_STD, TM_EST_ONE_END and TM_EST_GEN_ONE_END");
     TM_REQUIRE(!(estimators & TM_EST_STD) || eta, "STD needs eta");
     TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
+    TM_REQUIRE(derivative == 0 || derivative == 1, "derivative must be 0 or 1");
+    TM_REQUIRE(c->have_gauge || !(derivative || (estimators & TM_EST_GEN_ONE_END)),
+               "derivative insertions and GEN_ONE_END need the gauge field");
     hipStream_t s = hs(stream);
     const size_t hb = half_bytes(c, TM_F64, nrhs);
     void *se = ws_get(c, "c_se", hb), *so = ws_get(c, "c_so", hb);
     launch_pack(c, se, so, s_, nrhs, TM_F64, nullptr, s);
-    void *ee = nullptr, *eo = nullptr;
+    void *ee = se, *eo = so;
     if (estimators & TM_EST_STD) {
         ee = ws_get(c, "c_ee", hb);
         eo = ws_get(c, "c_eo", hb);
         launch_pack(c, ee, eo, eta, nrhs, TM_F64, nullptr, s);
     }
-    const int Lt = c->geo.L[3];
-    const size_t per_m = (size_t)16 * Lt;
-    const int n_mom = mom ? (int)mom->size() : 1;
-    std::vector<cx<double>> C;
-    int k = 0;
-    auto one = [&](const void *ve, const void *vo, const void *we, const void *wo, bool g5pre, cx<double> coef) {
-        cx<double> *dst = (cx<double> *)out + per_m * n_mom * k++;
-        if (mom) {
-            outer_momenta_host(c, ve, vo, we, wo, nrhs, *mom, C, s);
-            for (int m = 0; m < n_mom; m++) loops_from_outer(c, C.data() + per_m * m, g5pre, coef, dst + per_m * m);
-        } else {
-            outer_slices_host(c, ve, vo, we, wo, nrhs, C, s);
-            loops_from_outer(c, C.data(), g5pre, coef, dst);
-        }
-    };
-    if (estimators & TM_EST_STD) one(se, so, ee, eo, false, cx<double>{1, 0});
-    if (estimators & TM_EST_ONE_END) one(se, so, se, so, true, cx<double>{0, 2.0 * eps_of(c, mu_sign)});
+    c->stream = s;
+    contract_noise(c, estimators, derivative, ee, eo, se, so, nrhs, eps_of(c, mu_sign), (cx<double> *)out, mom);
+    TM_HIP(hipStreamSynchronize(s));
     return TM_OK;
 }
 
@@ -366,7 +355,7 @@ int contract_fields(tm_ctx *c, const double *eta, const double *s_, int nrhs, in
 extern "C" int tm_contract(tm_ctx *c, const double *eta, const double *s_, int nrhs, int estimators, int mu_sign,
                            double *out, tm_stream stream)
 {
-    return guarded(c, [&]() { return contract_fields(c, eta, s_, nrhs, estimators, mu_sign, out, stream, nullptr); });
+    return guarded(c, [&]() { return contract_fields(c, eta, s_, nrhs, estimators, mu_sign, 0, out, stream, nullptr); });
 }
 
 extern "C" int tm_momenta(int p2max, int *count, int *list)
@@ -383,12 +372,12 @@ extern "C" int tm_momenta(int p2max, int *count, int *list)
 }
 
 extern "C" int tm_contract_momentum(tm_ctx *c, const double *eta, const double *s_, int nrhs, int estimators,
-                                    int mu_sign, int p2max, double *out, tm_stream stream)
+                                    int mu_sign, int derivative, int p2max, double *out, tm_stream stream)
 {
     return guarded(c, [&]() {
         check_momenta(c, p2max);
         const std::vector<Momentum> mom = momenta_list(p2max);
-        return contract_fields(c, eta, s_, nrhs, estimators, mu_sign, out, stream, &mom);
+        return contract_fields(c, eta, s_, nrhs, estimators, mu_sign, derivative, out, stream, &mom);
     });
 }
 

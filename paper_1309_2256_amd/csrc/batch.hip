@@ -282,7 +282,10 @@ extern "C" int tm_batch_loops(tm_batch *b, const tm_loop_params *p, double *cons
         for (int i = 0; i < n; i++) {
             TM_REQUIRE(loops[i], "null loop output");
             TM_REQUIRE(p[i].n_hp >= 1 && p[i].n_lp == 0, "batched loops take high-precision noises only (n_lp = 0)");
-            TM_REQUIRE(p[i].estimators > 0 && p[i].estimators < 8, "bad estimator mask");
+            TM_REQUIRE(p[i].estimators > 0 && p[i].estimators < 16, "bad estimator mask");
+            TM_REQUIRE(p[i].derivative == 0 || p[i].derivative == 1, "derivative must be 0 or 1");
+            TM_REQUIRE(!(p[i].derivative && (p[i].estimators & TM_EST_HPE)),
+                       "HPE takes ultra-local insertions only (derivative = 0)");
             TM_REQUIRE(p[i].dilution == TM_DIL_NONE || p[i].dilution == TM_DIL_SPIN_COLOUR, "bad dilution");
             TM_REQUIRE(p[i].mu_sign == 1 || p[i].mu_sign == -1, "mu_sign must be +1 or -1");
             TM_REQUIRE(p[i].noise_offset >= 0, "noise_offset must be >= 0");
@@ -320,14 +323,18 @@ extern "C" int tm_batch_loops(tm_batch *b, const tm_loop_params *p, double *cons
             SolveOut r = S[i].finalize(s);
             if (r.status != TM_OK && status == TM_OK) status = r.status;
             const int Lt = c->geo.L[3];
-            const size_t per = (size_t)16 * Lt;
-            int n_est = 0;
-            for (int k = 0; k < 3; k++) n_est += (p[i].estimators >> k) & 1;
+            const size_t per = (size_t)n_insertions(p[i].derivative) * Lt;
+            int n_est = 0, hpe_slot = -1;
+            for (int k = 0; k < 4; k++)
+                if ((p[i].estimators >> k) & 1) {
+                    if ((1 << k) == TM_EST_HPE) hpe_slot = n_est;
+                    n_est++;
+                }
             const double epsp = eps_of(c, p[i].mu_sign);
             const size_t one = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * per_noise[i];
             std::vector<cx<double>> acc(n_est * per, cx<double>{0, 0}), one_loop(n_est * per);
             for (int k = 0; k < p[i].n_hp; k++) {
-                contract_noise(c, p[i].estimators, (char *)ee[i] + one * k, (char *)eo[i] + one * k,
+                contract_noise(c, p[i].estimators, p[i].derivative, (char *)ee[i] + one * k, (char *)eo[i] + one * k,
                                (char *)se[i] + one * k, (char *)so[i] + one * k, per_noise[i], epsp, one_loop.data());
                 for (size_t j = 0; j < acc.size(); j++) acc[j] = acc[j] + one_loop[j];
             }
@@ -335,7 +342,7 @@ extern "C" int tm_batch_loops(tm_batch *b, const tm_loop_params *p, double *cons
             if (p[i].estimators & TM_EST_HPE) hpe_exact_part(c, epsp, ex.data());
             cx<double> *dst = (cx<double> *)loops[i];
             for (int k = 0; k < n_est; k++) {
-                const bool hpe = k == n_est - 1 && (p[i].estimators & TM_EST_HPE);
+                const bool hpe = k == hpe_slot;
                 for (size_t j = 0; j < per; j++)
                     dst[k * per + j] = (1.0 / p[i].n_hp) * acc[k * per + j] + (hpe ? ex[j] : cx<double>{0, 0});
             }

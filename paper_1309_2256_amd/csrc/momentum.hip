@@ -1,7 +1,13 @@
 // Momentum projection of the loops (sec. III, contraction kernels and the
 // Fourier step): the colour-traced Dirac outer products are formed per site,
-// C(x)[b][a] = sum_r sum_c v_{r,bc}(x) w*_{r,ac}(x), and transformed over the
-// spatial coordinates of each time slice,
+// C(x)[b][a] = sum_r sum_c v_{r,bc}(x) w*_{r,ac}(x) for ultra-local
+// insertions, and for the one-derivative insertions (the covariant-derivative
+// kernel of sec. III) in each direction mu
+//   D_mu(x)[b][a] = 1/4 sum_r sum_c [(nabla_mu v)_{bc} w*_{ac} - v_{bc} (nabla_mu w)*_{ac}],
+//   nabla_mu f(x) = U_mu(x) f(x + mu) - U_mu(x - mu)^dag f(x - mu)
+// (the symmetric left-right derivative of the bilinear w^dag Gamma D_mu v
+// attributed to x, time-boundary phase included).  Then they are transformed
+// over the spatial coordinates of each time slice,
 //   C_p(t) = sum_{x in t} e^{i p.x} C(x),  p = 2 pi (nx/Lx, ny/Ly, nz/Lz),
 // for every integer n with |n|^2 <= p2max.  The transform is separable, so it
 // runs as three direct one-dimensional transforms (x, then y, then z) over
@@ -53,6 +59,101 @@ __global__ __launch_bounds__(kBlock) void k_outer_sites(const double2 *ve, const
     for (int e = 0; e < 16; e++) Cf[(size_t)e * V + s] = make_double2(C[e].r, C[e].i);
 }
 
+// D_mu(x) for mu = blockIdx.y; Cf[mu][e][s] with e = 4 b + a
+__global__ __launch_bounds__(kBlock) void k_outer_deriv_sites(const double2 *ve, const double2 *vo, const double2 *we,
+                                                              const double2 *wo, const double2 *l0, const double2 *l1,
+                                                              Geo g, long V, int nrhs, double2 *Cf)
+{
+    const long s = (long)blockIdx.x * kBlock + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (s >= V) return;
+    int c4[4];
+    c4[0] = (int)(s % g.L[0]);
+    const long q = s / g.L[0];
+    c4[1] = (int)(q % g.L[1]);
+    const long q2 = q / g.L[1];
+    c4[2] = (int)(q2 % g.L[2]);
+    c4[3] = (int)(q2 / g.L[2]);
+    const int p = (c4[0] + c4[1] + c4[2] + c4[3]) & 1;
+    const size_t i = (size_t)(s >> 1);
+    const size_t vh = (size_t)g.vh;
+    int cf[4] = {c4[0], c4[1], c4[2], c4[3]}, cb[4] = {c4[0], c4[1], c4[2], c4[3]};
+    cf[mu] = cf[mu] + 1 == g.L[mu] ? 0 : cf[mu] + 1;
+    cb[mu] = cb[mu] == 0 ? g.L[mu] - 1 : cb[mu] - 1;
+    const size_t jf = (size_t)eo_index(g, cf[0], cf[1], cf[2], cf[3]);
+    const size_t jb = (size_t)eo_index(g, cb[0], cb[1], cb[2], cb[3]);
+    // links[p][d][9][vh]: d = mu forward U_mu(x), d = 4 + mu backward U_mu(x - mu)^dag (phases included)
+    const double2 *lk = p ? l1 : l0;
+    cx<double> Uf[9], Ub[9];
+#pragma unroll
+    for (int e = 0; e < 9; e++) {
+        const double2 a = lk[((size_t)mu * 9 + e) * vh + i], b = lk[((size_t)(4 + mu) * 9 + e) * vh + i];
+        Uf[e] = {a.x, a.y};
+        Ub[e] = {b.x, b.y};
+    }
+    const double2 *vs = p ? vo : ve, *vn = p ? ve : vo, *ws = p ? wo : we, *wn = p ? we : wo;
+    cx<double> C[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) C[e] = {0, 0};
+    // nabla f at x for spin a of field f (other-parity neighbours)
+    auto nabla = [&](const double2 *f, size_t base, int a, cx<double> out[3]) {
+        cx<double> ff[3], fb[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const double2 x1 = f[(base + a * 3 + c) * vh + jf], x2 = f[(base + a * 3 + c) * vh + jb];
+            ff[c] = {x1.x, x1.y};
+            fb[c] = {x2.x, x2.y};
+        }
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            cx<double> acc = {0, 0}, accb = {0, 0};
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                cmac(acc, Uf[3 * r + c], ff[c]);
+                cmac(accb, Ub[3 * r + c], fb[c]);
+            }
+            out[r] = {acc.r - accb.r, acc.i - accb.i};
+        }
+    };
+    for (int r = 0; r < nrhs; r++) {
+        const size_t base = (size_t)r * 12;
+        cx<double> wx[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const double2 a = ws[(base + k) * vh + i];
+            wx[k] = {a.x, a.y};
+        }
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++) {
+            cx<double> gv[3];
+            nabla(vn, base, sb, gv);
+#pragma unroll
+            for (int sa = 0; sa < 4; sa++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) cmac_conj(C[sb * 4 + sa], wx[sa * 3 + c], gv[c]);
+        }
+        cx<double> vx[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const double2 a = vs[(base + k) * vh + i];
+            vx[k] = {a.x, a.y};
+        }
+#pragma unroll
+        for (int sa = 0; sa < 4; sa++) {
+            cx<double> gw[3];
+            nabla(wn, base, sa, gw);
+#pragma unroll
+            for (int c = 0; c < 3; c++) gw[c] = {-gw[c].r, -gw[c].i};
+#pragma unroll
+            for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) cmac_conj(C[sb * 4 + sa], gw[c], vx[sb * 3 + c]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; e++) Cf[((size_t)mu * 16 + e) * V + s] = make_double2(0.25 * C[e].r, 0.25 * C[e].i);
+}
+
 // One direction of the transform: in [outer][n][inner] -> out[outer][W][inner]
 // with out[o][j][k] = sum_m ph[j][m] in[o][m][k] (fixed order in m).
 __global__ __launch_bounds__(kBlock) void k_dft_dim(const double2 *in, double2 *out, const double2 *ph, long outer,
@@ -75,14 +176,15 @@ __global__ __launch_bounds__(kBlock) void k_dft_dim(const double2 *in, double2 *
     out[idx] = make_double2(acc.r, acc.i);
 }
 
-// out[m][t][e] = T[e][t][nz + N][ny + N][nx + N] for the listed momenta
-__global__ void k_pick_momenta(const double2 *T, const int *mom, int n_mom, int Lt, int W, int N, double2 *out)
+// out[m][blk][t][e] = T[16 blk + e][t][nz + N][ny + N][nx + N] for the listed momenta
+__global__ void k_pick_momenta(const double2 *T, const int *mom, int n_mom, int nblk, int Lt, int W, int N,
+                               double2 *out)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n_mom * Lt * 16) return;
-    const int e = idx % 16, t = (idx / 16) % Lt, m = idx / (16 * Lt);
+    if (idx >= n_mom * nblk * Lt * 16) return;
+    const int e = idx % 16, t = (idx / 16) % Lt, blk = (idx / (16 * Lt)) % nblk, m = idx / (16 * Lt * nblk);
     const int nx = mom[3 * m] + N, ny = mom[3 * m + 1] + N, nz = mom[3 * m + 2] + N;
-    out[idx] = T[((((size_t)e * Lt + t) * W + nz) * W + ny) * W + nx];
+    out[idx] = T[((((size_t)(16 * blk + e) * Lt + t) * W + nz) * W + ny) * W + nx];
 }
 
 // e^{2 pi i (j - N) x / L} for j < W, x < L, reduced mod L in integers
@@ -124,43 +226,42 @@ void check_momenta(tm_ctx *c, int p2max)
         TM_REQUIRE(2 * N < c->geo.L[mu], "momentum components must stay below L/2 in every spatial direction");
 }
 
-void outer_momenta_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
-                        const std::vector<Momentum> &mom, std::vector<cx<double>> &out, hipStream_t s)
+namespace {
+
+// Fourier sums of per-site components Cf[ncomp][V] (ncomp = 16 nblk) over each
+// time slice for the listed momenta -> host out[n_mom][nblk][Lt][16]
+void project_components(tm_ctx *c, const double2 *Cf, int nblk, const std::vector<Momentum> &mom,
+                        std::vector<cx<double>> &out, hipStream_t s)
 {
     const Geo &g = c->geo;
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const long ncomp = 16L * nblk;
     int N = 0;
     for (const auto &m : mom)
         for (int d = 0; d < 3; d++) N = std::max(N, std::abs(m.n[d]));
     const int W = 2 * N + 1;
-    const long V = c->V;
-    double2 *Cf = (double2 *)ws_get(c, "mom_cf", sizeof(double2) * 16 * V);
-    hipLaunchKernelGGL(k_outer_sites, dim3((unsigned)((V + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       (const double2 *)ve, (const double2 *)vo, (const double2 *)we, (const double2 *)wo, g, V,
-                       nrhs, Cf);
-    TM_HIP(hipGetLastError());
     // phase tables for x, y, z
     std::vector<double2> px = phase_table(Lx, N), py = phase_table(Ly, N), pz = phase_table(Lz, N);
     double2 *dph = (double2 *)ws_get(c, "mom_ph", sizeof(double2) * (size_t)W * (Lx + Ly + Lz));
     upload(dph, px.data(), sizeof(double2) * px.size(), s);
     upload(dph + px.size(), py.data(), sizeof(double2) * py.size(), s);
     upload(dph + px.size() + py.size(), pz.data(), sizeof(double2) * pz.size(), s);
-    // x: [16 Lt Lz Ly][Lx][1] -> [16 Lt Lz Ly][W][1]
-    const long o1 = 16L * Lt * Lz * Ly;
+    // x: [ncomp Lt Lz Ly][Lx][1] -> [ncomp Lt Lz Ly][W][1]
+    const long o1 = ncomp * Lt * Lz * Ly;
     double2 *T1 = (double2 *)ws_get(c, "mom_t1", sizeof(double2) * o1 * W);
-    long n1 = o1 * W;
-    hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       (const double2 *)Cf, T1, (const double2 *)dph, o1, Lx, W, 1L);
-    // y: [16 Lt Lz][Ly][W] -> [16 Lt Lz][W][W]
-    const long o2 = 16L * Lt * Lz;
+    const long n1 = o1 * W;
+    hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, Cf, T1,
+                       (const double2 *)dph, o1, Lx, W, 1L);
+    // y: [ncomp Lt Lz][Ly][W] -> [ncomp Lt Lz][W][W]
+    const long o2 = ncomp * Lt * Lz;
     double2 *T2 = (double2 *)ws_get(c, "mom_t2", sizeof(double2) * o2 * W * W);
-    long n2 = o2 * W * W;
+    const long n2 = o2 * W * W;
     hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n2 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        (const double2 *)T1, T2, (const double2 *)(dph + px.size()), o2, Ly, W, (long)W);
-    // z: [16 Lt][Lz][W W] -> [16 Lt][W][W W]
-    const long o3 = 16L * Lt;
+    // z: [ncomp Lt][Lz][W W] -> [ncomp Lt][W][W W]
+    const long o3 = ncomp * Lt;
     double2 *T3 = (double2 *)ws_get(c, "mom_t3", sizeof(double2) * o3 * W * W * W);
-    long n3 = o3 * W * W * W;
+    const long n3 = o3 * W * W * W;
     hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n3 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        (const double2 *)T2, T3, (const double2 *)(dph + px.size() + py.size()), o3, Lz, W,
                        (long)W * W);
@@ -171,10 +272,38 @@ void outer_momenta_host(tm_ctx *c, const void *ve, const void *vo, const void *w
         for (int d = 0; d < 3; d++) ml[3 * m + d] = mom[m].n[d];
     int *dm = (int *)ws_get(c, "mom_list", sizeof(int) * 3 * n_mom);
     upload(dm, ml.data(), sizeof(int) * ml.size(), s);
-    double2 *dout = (double2 *)ws_get(c, "mom_out", sizeof(double2) * n_mom * Lt * 16);
-    hipLaunchKernelGGL(k_pick_momenta, dim3((n_mom * Lt * 16 + 255) / 256), dim3(256), 0, s, (const double2 *)T3,
-                       (const int *)dm, n_mom, Lt, W, N, dout);
+    const int n_out = n_mom * nblk * Lt * 16;
+    double2 *dout = (double2 *)ws_get(c, "mom_out", sizeof(double2) * n_out);
+    hipLaunchKernelGGL(k_pick_momenta, dim3((n_out + 255) / 256), dim3(256), 0, s, (const double2 *)T3,
+                       (const int *)dm, n_mom, nblk, Lt, W, N, dout);
     TM_HIP(hipGetLastError());
-    out.resize((size_t)n_mom * Lt * 16);
+    out.resize((size_t)n_out);
     download(c, out.data(), dout, sizeof(double2) * out.size(), s);
+}
+
+}  // namespace
+
+void outer_momenta_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
+                        const std::vector<Momentum> &mom, std::vector<cx<double>> &out, hipStream_t s)
+{
+    const long V = c->V;
+    double2 *Cf = (double2 *)ws_get(c, "mom_cf", sizeof(double2) * 16 * V);
+    hipLaunchKernelGGL(k_outer_sites, dim3((unsigned)((V + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const double2 *)ve, (const double2 *)vo, (const double2 *)we, (const double2 *)wo, c->geo, V,
+                       nrhs, Cf);
+    TM_HIP(hipGetLastError());
+    project_components(c, Cf, 1, mom, out, s);
+}
+
+void outer_deriv_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
+                      const std::vector<Momentum> &mom, std::vector<cx<double>> &out, hipStream_t s)
+{
+    TM_REQUIRE(c->have_gauge, "no gauge field set");
+    const long V = c->V;
+    double2 *Cf = (double2 *)ws_get(c, "mom_cfd", sizeof(double2) * 64 * V);
+    hipLaunchKernelGGL(k_outer_deriv_sites, dim3((unsigned)((V + kBlock - 1) / kBlock), 4), dim3(kBlock), 0, s,
+                       (const double2 *)ve, (const double2 *)vo, (const double2 *)we, (const double2 *)wo,
+                       (const double2 *)c->links64[0], (const double2 *)c->links64[1], c->geo, V, nrhs, Cf);
+    TM_HIP(hipGetLastError());
+    project_components(c, Cf, 4, mom, out, s);
 }

@@ -95,10 +95,16 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
 // FP64 halves -> host [Lt][16] complex
 void outer_slices_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
                        std::vector<cx<double>> &out, hipStream_t s);
+// Spin matrix inserted for Gamma_n: Gamma_n, gamma5 Gamma_n (one-end) or
+// gamma5 Gamma_n gamma5 (generalised one-end)
+enum GammaForm { G_PLAIN = 0, G_G5_LEFT = 1, G_G5_BOTH = 2 };
 // Loops from outer products: L_n(t) = coef * sum_ab G[a][b] C[t][b][a] with
-// G = Gamma_n (pre = false) or gamma5 Gamma_n (pre = true); C [Lt][16],
-// out [16][Lt]
-void loops_from_outer(tm_ctx *c, const cx<double> *C, bool g5pre, cx<double> coef, cx<double> *out);
+// G from GammaForm; C [Lt][16], out [16][Lt]
+void loops_from_outer(tm_ctx *c, const cx<double> *C, GammaForm form, cx<double> coef, cx<double> *out);
+
+// insertions per estimator: the 16 ultra-local Gamma_n, with derivative also
+// the 4 x 16 one-derivative insertions (index 16 (1 + mu) + n)
+inline int n_insertions(int derivative) { return derivative ? 80 : 16; }
 
 // spatial momentum p = 2 pi (n_x / L_x, n_y / L_y, n_z / L_z)
 struct Momentum {
@@ -111,16 +117,23 @@ void check_momenta(tm_ctx *c, int p2max);
 // momentum-projected outer products, out [n_mom][Lt][16] (momentum.hip)
 void outer_momenta_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
                         const std::vector<Momentum> &mom, std::vector<cx<double>> &out, hipStream_t s);
+// one-derivative outer products D_mu, out [n_mom][4 mu][Lt][16] (momentum.hip)
+void outer_deriv_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
+                      const std::vector<Momentum> &mom, std::vector<cx<double>> &out, hipStream_t s);
+// D_W f = f + H f (no twist) on FP64 half fields
+void op_wilson(tm_ctx *c, void *oe, void *oo, const void *fe, const void *fo, int nrhs, hipStream_t s);
 // exactly known part of the hopping expansion for ultra-local insertions
 void hpe_exact_part(tm_ctx *c, double epsp, cx<double> *out /* [16][Lt] */);
 
 // per-noise loops of one noise vector's sources (ee, eo) and solutions (se,
-// so), estimators in mask order, into dst [n_est][16][Lt], or with mom
-// [n_est][n_mom][16][Lt]; uses c->stream
-void contract_noise(tm_ctx *c, int estimators, const void *ee, const void *eo, const void *se, const void *so,
-                    int nrhs, double epsp, cx<double> *dst, const std::vector<Momentum> *mom = nullptr);
+// so), estimators in mask order, into dst [n_est][n_ins][Lt], or with mom
+// [n_est][n_mom][n_ins][Lt] (n_ins = n_insertions(derivative)); uses
+// c->stream.  HPE takes ultra-local insertions only.
+void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, const void *eo, const void *se,
+                    const void *so, int nrhs, double epsp, cx<double> *dst,
+                    const std::vector<Momentum> *mom = nullptr);
 hipStream_t s_of(tm_ctx *c);
 
-// loops [n_est][16][Lt] (mom = null) or [n_est][n_mom][16][Lt]
+// loops [n_est][n_ins][Lt] (mom = null) or [n_est][n_mom][n_ins][Lt]
 int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noise, tm_loop_stats *stats,
               hipStream_t s, const std::vector<Momentum> *mom = nullptr);

@@ -491,7 +491,7 @@ void outer_slices_host(tm_ctx *c, const void *ve, const void *vo, const void *we
     download(c, out.data(), d, sizeof(double) * 32 * Lt, s);
 }
 
-void loops_from_outer(tm_ctx *c, const cx<double> *C, bool g5pre, cx<double> coef, cx<double> *out)
+void loops_from_outer(tm_ctx *c, const cx<double> *C, GammaForm form, cx<double> coef, cx<double> *out)
 {
     const int Lt = c->geo.L[3];
     cx<double> g5[4][4];
@@ -501,7 +501,7 @@ void loops_from_outer(tm_ctx *c, const cx<double> *C, bool g5pre, cx<double> coe
         gamma_n(n, G);
         for (int a = 0; a < 4; a++)
             for (int b = 0; b < 4; b++) {
-                if (!g5pre) {
+                if (form == G_PLAIN) {
                     X[a][b] = G[a][b];
                 } else {
                     cx<double> acc{0, 0};
@@ -509,6 +509,17 @@ void loops_from_outer(tm_ctx *c, const cx<double> *C, bool g5pre, cx<double> coe
                     X[a][b] = acc;
                 }
             }
+        if (form == G_G5_BOTH) {
+            cx<double> Y[4][4];
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    cx<double> acc{0, 0};
+                    for (int k = 0; k < 4; k++) acc = acc + X[a][k] * g5[k][b];
+                    Y[a][b] = acc;
+                }
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) X[a][b] = Y[a][b];
+        }
         for (int t = 0; t < Lt; t++) {
             cx<double> acc{0, 0};
             for (int a = 0; a < 4; a++)
@@ -535,35 +546,60 @@ void hpe_exact_part(tm_ctx *c, double e, cx<double> *out)
         for (int t = 0; t < Lt; t++) out[(size_t)n * Lt + t] = n == 0 ? c0 : n == 15 ? c15 : cx<double>{0, 0};
 }
 
-void contract_noise(tm_ctx *c, int estimators, const void *ee, const void *eo, const void *se, const void *so,
-                    int nrhs, double epsp, cx<double> *dst, const std::vector<Momentum> *mom)
+void op_wilson(tm_ctx *c, void *oe, void *oo, const void *fe, const void *fo, int nrhs, hipStream_t s)
+{
+    const double k = c->kappa;
+    op_dslash(c, oe, fo, fe, nrhs, TM_F64, 0, 0, sd_scalar(-k), sd_scalar(1), s);
+    op_dslash(c, oo, fe, fo, nrhs, TM_F64, 1, 0, sd_scalar(-k), sd_scalar(1), s);
+}
+
+void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, const void *eo, const void *se,
+                    const void *so, int nrhs, double epsp, cx<double> *dst, const std::vector<Momentum> *mom)
 {
     const int Lt = c->geo.L[3];
-    const size_t per_m = (size_t)16 * Lt;
+    const size_t per_ins = (size_t)16 * Lt;  // one block of 16 insertions
+    const int n_ins = n_insertions(derivative);
     const int n_mom = mom ? (int)mom->size() : 1;
+    const size_t per_m = (size_t)Lt * n_ins;
     const size_t per = per_m * n_mom;
     const size_t f64 = field_bytes(c, TM_F64, nrhs);
+    static const std::vector<Momentum> zero{Momentum{{0, 0, 0}}};
     std::vector<cx<double>> C;
-    // outer products of (v, w), then the Gamma insertions per momentum
-    auto outer_loops = [&](const void *ve, const void *vo, const void *we, const void *wo, bool g5pre,
-                           cx<double> coef, cx<double> *out) {
+    // outer products of (right v, left w), then the Gamma insertions per momentum
+    auto outer_loops = [&](const void *ve, const void *vo, const void *we, const void *wo, GammaForm form,
+                           cx<double> coef, bool deriv, cx<double> *out) {
         if (mom) {
             outer_momenta_host(c, ve, vo, we, wo, nrhs, *mom, C, s_of(c));
-            for (int m = 0; m < n_mom; m++) loops_from_outer(c, C.data() + per_m * m, g5pre, coef, out + per_m * m);
+            for (int m = 0; m < n_mom; m++) loops_from_outer(c, C.data() + per_ins * m, form, coef, out + per_m * m);
         } else {
             outer_slices_host(c, ve, vo, we, wo, nrhs, C, s_of(c));
-            loops_from_outer(c, C.data(), g5pre, coef, out);
+            loops_from_outer(c, C.data(), form, coef, out);
         }
+        if (!deriv) return;
+        // D_mu blocks [n_mom][4][Lt][16]; per time slice = the zero momentum
+        outer_deriv_host(c, ve, vo, we, wo, nrhs, mom ? *mom : zero, C, s_of(c));
+        for (int m = 0; m < n_mom; m++)
+            for (int mu = 0; mu < 4; mu++)
+                loops_from_outer(c, C.data() + per_ins * (4 * m + mu), form, coef,
+                                 out + per_m * m + per_ins * (1 + mu));
     };
     int k = 0;
-    if (estimators & TM_EST_STD) outer_loops(se, so, ee, eo, false, cx<double>{1, 0}, dst + per * k++);
-    if (estimators & TM_EST_ONE_END) outer_loops(se, so, se, so, true, cx<double>{0, 2.0 * epsp}, dst + per * k++);
+    if (estimators & TM_EST_STD)
+        outer_loops(se, so, ee, eo, G_PLAIN, cx<double>{1, 0}, derivative, dst + per * k++);
+    if (estimators & TM_EST_ONE_END)
+        outer_loops(se, so, se, so, G_G5_LEFT, cx<double>{0, 2.0 * epsp}, derivative, dst + per * k++);
     if (estimators & TM_EST_HPE) {
         void *he = ws_get(c, "l_h_e", f64), *ho = ws_get(c, "l_h_o", f64);
         copy_field(he, se, f64, s_of(c));
         copy_field(ho, so, f64, s_of(c));
         op_bh_power(c, he, ho, nrhs, epsp, 4, s_of(c));
-        outer_loops(he, ho, ee, eo, false, cx<double>{1, 0}, dst + per * k++);
+        outer_loops(he, ho, ee, eo, G_PLAIN, cx<double>{1, 0}, false, dst + per * k++);
+    }
+    if (estimators & TM_EST_GEN_ONE_END) {
+        // 2 s^dag gamma5 X gamma5 D_W s (eq. loopStD): right field D_W s, left s
+        void *we = ws_get(c, "l_w_e", f64), *wo = ws_get(c, "l_w_o", f64);
+        op_wilson(c, we, wo, se, so, nrhs, s_of(c));
+        outer_loops(we, wo, se, so, G_G5_BOTH, cx<double>{2, 0}, derivative, dst + per * k++);
     }
 }
 
@@ -573,7 +609,10 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
     const double t0 = now_s();
     TM_REQUIRE(p != nullptr && loops != nullptr, "null argument");
     TM_REQUIRE(p->n_hp >= 0 && p->n_lp >= 0 && p->n_hp + p->n_lp >= 1, "need at least one noise vector");
-    TM_REQUIRE(p->estimators > 0 && p->estimators < 8, "bad estimator mask");
+    TM_REQUIRE(p->estimators > 0 && p->estimators < 16, "bad estimator mask");
+    TM_REQUIRE(p->derivative == 0 || p->derivative == 1, "derivative must be 0 or 1");
+    TM_REQUIRE(!(p->derivative && (p->estimators & TM_EST_HPE)),
+               "HPE takes ultra-local insertions only (derivative = 0)");
     TM_REQUIRE(p->dilution == TM_DIL_NONE || p->dilution == TM_DIL_SPIN_COLOUR, "bad dilution");
     TM_REQUIRE(p->mu_sign == 1 || p->mu_sign == -1, "mu_sign must be +1 or -1");
     TM_REQUIRE(p->noise_offset >= 0, "noise_offset must be >= 0");
@@ -585,14 +624,14 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
     const int n_noise = p->n_hp + p->n_lp;
     const double epsp = eps_of(c, p->mu_sign);
     int n_est = 0;
-    int est_ids[3];
-    for (int b = 0; b < 3; b++)
+    int est_ids[4];
+    for (int b = 0; b < 4; b++)
         if (p->estimators & (1 << b)) est_ids[n_est++] = 1 << b;
     const size_t f64 = field_bytes(c, TM_F64, nrhs);
     void *ee = ws_get(c, "l_eta_e", f64), *eo = ws_get(c, "l_eta_o", f64);
     void *se = ws_get(c, "l_s_e", f64), *so = ws_get(c, "l_s_o", f64);
-    // per estimator: [n_mom][16][Lt] (one momentum, p = 0, without mom)
-    const size_t per = (size_t)16 * Lt * (mom ? mom->size() : 1);
+    // per estimator: [n_mom][n_ins][Lt] (one momentum, p = 0, without mom)
+    const size_t per = (size_t)n_insertions(p->derivative) * Lt * (mom ? mom->size() : 1);
     // per-noise loops [noise][prec 0 hp, 1 lp][est][per]
     std::vector<cx<double>> pn((size_t)n_noise * 2 * n_est * per, cx<double>{0, 0});
     tm_loop_stats st{};
@@ -600,7 +639,7 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
     c->stream = s;
 
     auto contract = [&](int noise, int slot) {
-        contract_noise(c, p->estimators, ee, eo, se, so, nrhs, epsp,
+        contract_noise(c, p->estimators, p->derivative, ee, eo, se, so, nrhs, epsp,
                        &pn[((size_t)noise * 2 + slot) * n_est * per], mom);
     };
 

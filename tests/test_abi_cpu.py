@@ -92,5 +92,5 @@ def test_momentum_list_matches_oracle(p2max):
 
 def test_momentum_calls_on_null_context():
     import paper_1309_2256_amd as P
-    assert P.tm_contract_momentum(None, None, None, 1, 1, 1, 0, None, None) == P.TM_ERR_ARG
+    assert P.tm_contract_momentum(None, None, None, 1, 1, 1, 0, 0, None, None) == P.TM_ERR_ARG
     assert P.tm_loops_momentum(None, None, 0, None, None, None, None) == P.TM_ERR_ARG
