@@ -238,6 +238,27 @@ def dilute_spin_colour(eta):
     return out
 
 
+def dilute_time(L, etas, period):
+    """Time dilution with coherent sources (section II.D): every source is
+    split into `period` sources, number o keeping the slices t = o (mod
+    period); period = Lt gives one slice per source."""
+    t = np.arange(volume(L)) // (L[0] * L[1] * L[2])
+    out = []
+    for e in etas:
+        for o in range(period):
+            m = np.array(e, dtype=np.complex128, copy=True)
+            m[t % period != o] = 0
+            out.append(m)
+    return out
+
+
+def noise_sources(L, seed, r, dilution=False, t_period=0):
+    """The sources of noise vector r: spin-colour and/or time diluted."""
+    eta = noise_z4(L, seed, r)
+    etas = list(dilute_spin_colour(eta)) if dilution else [eta]
+    return dilute_time(L, etas, t_period) if t_period else etas
+
+
 # ---------------------------------------------------------------- contractions
 
 def contract_std(L, eta, s):
@@ -470,14 +491,13 @@ def loops_momentum_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators, 
 
 
 def loops_momentum(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, moms, dilution=False,
-                   derivative=False):
+                   derivative=False, t_period=0):
     """As loops, momentum resolved ({estimator: (n_mom, 16, Lt)}).  The exact
     HPE part is the same at every site of a slice, so its Fourier sum over the
     slice vanishes for p != 0 and it enters p = 0 only."""
     per_noise = []
     for r in range(n_noise):
-        eta = noise_z4(L, seed, r)
-        etas = dilute_spin_colour(eta) if dilution else [eta]
+        etas = noise_sources(L, seed, r, dilution, t_period)
         sols, _, _ = solve_sources(L, kappa, eps, t_bc, U, etas, tol)
         per_noise.append(loops_momentum_for_solution(L, kappa, eps, t_bc, U, etas, sols,
                                                      estimators, moms, derivative))
@@ -514,15 +534,14 @@ def solve_sources(L, kappa, eps, t_bc, U, srcs, tol, maxiter=100000):
 
 
 def loops(L, kappa, eps, t_bc, U, seed, n_noise, tol, estimators, dilution=False,
-          noise_offset=0, derivative=False):
+          noise_offset=0, derivative=False, t_period=0):
     """Plain stochastic loop estimate from n_noise Z4 noise vectors solved to
     tol (mean over noises, eq. estiM / loopSt / loopVv / loopHPE1 / loopStD).
     Returns ({estimator: (n_ins, Lt)}, per_noise list of {estimator: (n_ins, Lt)}),
     n_ins = 16, or 80 with the one-derivative insertions."""
     per_noise = []
     for r in range(noise_offset, noise_offset + n_noise):
-        eta = noise_z4(L, seed, r)
-        etas = dilute_spin_colour(eta) if dilution else [eta]
+        etas = noise_sources(L, seed, r, dilution, t_period)
         sols, _, _ = solve_sources(L, kappa, eps, t_bc, U, etas, tol)
         per_noise.append(loops_for_solution(L, kappa, eps, t_bc, U, etas, sols, estimators,
                                             derivative))

@@ -589,3 +589,34 @@ def test_derivative_and_local_estimator_identities(dense4):
     assert np.abs(gen - (tu + td)).max() < 1e-11 * scale
     assert np.abs(one - (td - tu)).max() < 1e-11 * scale
     assert np.abs(tu[16:]).max() > 1e-3 * scale       # the derivative block is not trivially zero
+
+
+# ---------------------------------------------------------------- time dilution
+
+@pytest.mark.parametrize("period", [1, 2, 4])
+def test_time_dilution_dense_formula(dense4, period):
+    """Coherent time dilution (sec. II.D): per noise, the STD and HPE loops at
+    slice t equal sum_{x in t} sum_{y: t_y = t (mod P)} eta(x)^dag Gamma K(x, y)
+    eta(y) with K = M^-1 and (BH)^4 M^-1 as dense matrices; P = 1 is the
+    volume-source estimate."""
+    d = dense4
+    L, kappa, eps, U = d["L"], d["kappa"], d["eps"], d["U"]
+    V, Lt = int(np.prod(L)), L[3]
+    etas = O.noise_sources(L, 77, 3, False, period)
+    assert len(etas) == period
+    assert np.abs(sum(etas) - O.noise_z4(L, 77, 3)).max() == 0
+    sols = [(d["Mui"] @ e.ravel()).reshape(V, 4, 3) for e in etas]
+    got = O.loops_for_solution(L, kappa, eps, -1, U, etas, sols, O.EST_STD | O.EST_HPE)
+    BH4 = dense(lambda v: O.bh_power(L, kappa, eps, -1, U, v, 4), L)
+    eta = O.noise_z4(L, 77, 3).ravel()
+    tsite = np.repeat(np.arange(V) // (V // Lt), 12)
+    same = (tsite[:, None] % period) == (tsite[None, :] % period)
+    for e, K in ((O.EST_STD, d["Mui"]), (O.EST_HPE, BH4 @ d["Mui"])):
+        Km = np.where(same, K, 0)
+        y = Km @ eta
+        want = np.zeros((16, Lt), dtype=complex)
+        for n in range(16):
+            Gc = np.kron(np.eye(V), np.kron(O.gamma(n), np.eye(3)))
+            dens = (eta.conj() * (Gc @ y)).reshape(V, 12).sum(1)
+            want[n] = dens.reshape(Lt, -1).sum(1)
+        assert np.abs(got[e] - want).max() < 1e-12, e
