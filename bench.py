@@ -41,7 +41,7 @@ def main():
     ap.add_argument("--ptc-rhs", type=int, default=4,
                     help="right-hand sides of the FGMRES runs (memory: ~12 GB each)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the TSM/HPE (16^3x32) and uneven-batch legs")
+                    help="skip the momentum, TSM/HPE, time-dilution and uneven-batch legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the workload (one 32^3x64 lattice, noise vectors "
@@ -229,6 +229,7 @@ def main():
     if not args.no_extra:
         out["tsm_hpe_c2"] = tsm_leg(P, S, torch, dev)
         out["uneven_batch_c4"] = batch_leg(P, S, torch, dev)
+        out["time_dilution_c2"] = time_dilution_leg(P, S, torch, dev)
     if not args.no_ptc:
         out["ptc_c5"] = ptc_leg(args, P, S, torch, dev)
     print(json.dumps(out), flush=True)
@@ -309,6 +310,38 @@ def tsm_leg(P, S, torch, dev):
                      "max_res_lp": st.max_res_lp, "status": status}
         print("[bench/tsm] %s: %d HP (%.0f it) + %d LP (%.1f it) solves in %.2fs"
               % (name, st.n_solves_hp, it_hp, st.n_solves_lp, it_lp, dt), file=sys.stderr, flush=True)
+    ctx.close()
+    return res
+
+
+def time_dilution_leg(P, S, torch, dev):
+    """Time dilution with coherent sources on 16^3x32 (the paper's strategy
+    for heavier quarks): one Z4 noise (seed 202) split into 4 sources on the
+    slices t = o (mod 4) (8 slices apart) x 12 spin-colour components, 48
+    mixed-CG solves to 1e-9 in batches of 12, STD + HPE loops with the
+    single-time-slice contraction; against the same noise as volume sources
+    (12 solves)."""
+    ctx, cfg = make_context(P, S, torch, dev, "c2")
+    res = {"workload": "16^3x32, links exp(i 0.2 H) seed 102, kappa 0.124, 2 kappa mu 0.0028; 1 Z4 "
+                       "noise x 12 spin-colour, time dilution period 4 (48 sources) vs volume "
+                       "sources (12); mixed CG to 1e-9; STD + HPE loops"}
+    for name, period in (("period4", 4), ("volume", 0)):
+        p = P.tm_loop_params()
+        p.seed, p.n_hp, p.n_lp = S.NOISE_SEEDS["c2"], 1, 0
+        p.dilution, p.estimators, p.mu_sign = P.TM_DIL_SPIN_COLOUR, P.TM_EST_STD | P.TM_EST_HPE, 1
+        p.t_period = period
+        p.hp = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+        ctx.loops(p)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, st, status = ctx.loops(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        res[name] = {"seconds": dt, "n_solves": st.n_solves_hp,
+                     "iters_per_solve": st.iters_hp / st.n_solves_hp, "max_res": st.max_res_hp,
+                     "solves_per_s": st.n_solves_hp / dt, "status": status}
+        print("[bench/tdil] %s: %d solves (%.0f it) in %.2fs" % (name, st.n_solves_hp,
+              st.iters_hp / st.n_solves_hp, dt), file=sys.stderr, flush=True)
     ctx.close()
     return res
 

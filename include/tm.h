@@ -228,6 +228,14 @@ typedef struct {
     int mu_sign;          /* flavour inverted: +1 u, -1 d                         */
     int derivative;       /* 0: 16 ultra-local insertions; 1: also one-derivative
                              (80 insertions); not with TM_EST_HPE              */
+    int t_period;         /* 0: volume sources.  P > 0 (a divisor of Lt): time
+                             dilution with coherent sources (sec. II.D): each
+                             noise (and spin-colour component) is split into P
+                             sources, source o on the slices t = o (mod P), all
+                             solved (in batches of up to 12 RHS) and summed;
+                             P = Lt is plain time dilution.  The ultra-local
+                             STD and HPE contractions visit only each source's
+                             own slices (the single-time-slice contraction).  */
     tm_solve_params hp;   /* high-precision solve parameters                      */
     tm_solve_params lp;   /* low-precision solve parameters (n_lp > 0)            */
 } tm_loop_params;
@@ -240,7 +248,7 @@ typedef struct {
 } tm_loop_stats;
 
 /* Estimate the disconnected loops L_n(t) for the 16 Gamma_n at every time
- * slice t from Z4 volume noise.  Noise vector r has entries i^k, k the top two
+ * slice t from Z4 noise (volume sources, or time-diluted, see t_period).  Noise vector r has entries i^k, k the top two
  * bits of SplitMix64 output ((r*V + s)*4 + spin)*3 + colour of `seed`.
  *   loops      host, [n_est][n_ins][Lt] complex double, estimators in mask
  *              order (STD, ONE_END, HPE, GEN_ONE_END); the TSM combination

@@ -305,11 +305,12 @@ def contract_gen(L, kappa, t_bc, U, s):
     return 2.0 * contract_std(L, g5_field(s), g5_field(wilson(L, kappa, t_bc, U, s)))
 
 
-def _shift(L, f, mu, step):
-    """The field at x + step * mu_hat, as an array over x (periodic wrap)."""
-    c = list(_site_coords(L))
+def _nbr(L, sites, mu, step):
+    """Site index of x + step * mu_hat for each site x in `sites` (periodic)."""
+    c = [sites % L[0], (sites // L[0]) % L[1], (sites // (L[0] * L[1])) % L[2],
+         sites // (L[0] * L[1] * L[2])]
     c[mu] = (c[mu] + step) % L[mu]
-    return f[c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))]
+    return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))
 
 
 def _phased_links(L, t_bc, U):
@@ -320,23 +321,34 @@ def _phased_links(L, t_bc, U):
     return U
 
 
-def derivative_outer(L, t_bc, U, left, right):
+def derivative_outer(L, t_bc, U, left, right, sites=None):
     """Spin matrices P_mu(x)[a][b] of the one-derivative bilinear with the
     symmetric left-right covariant derivative attributed to site x,
       left^dag G D_mu right (x) = sum_ab G[a][b] P_mu(x)[a][b],
       P_mu = 1/4 [ l(x)^* U_mu(x) r(x+mu) - l(x)^* U_mu(x-mu)^dag r(x-mu)
                    - l(x+mu)^* U_mu(x)^dag r(x) + l(x-mu)^* U_mu(x-mu) r(x) ]
-    with colour contracted through the link in each term -> (4, V, 4, 4)."""
+    with colour contracted through the link in each term -> (4, n_sites, 4, 4)
+    for the given sites (default: all, in site order)."""
     Uph = _phased_links(L, t_bc, U)
     l, r = _spinor(L, left), _spinor(L, right)
-    out = np.zeros((4, volume(L), 4, 4), dtype=np.complex128)
+    x = np.arange(volume(L)) if sites is None else np.asarray(sites)
+    out = np.zeros((4, len(x), 4, 4), dtype=np.complex128)
+
+    def mv(W, f):          # colour matrix W(x) times f(x) on each spin: [b][c] = sum_d W_cd f_bd
+        return f @ W.transpose(0, 2, 1)
+
+    def outer(w, v):       # [a][b] = sum_c w*_{ac} v_{bc}
+        return w.conj() @ v.transpose(0, 2, 1)
+
     for mu in range(4):
-        Uf = Uph[mu]                      # U_mu(x)
-        Ub = _shift(L, Uph[mu], mu, -1)   # U_mu(x - mu)
-        t1 = np.einsum("xac,xcd,xbd->xab", l.conj(), Uf, _shift(L, r, mu, 1))
-        t2 = np.einsum("xac,xdc,xbd->xab", l.conj(), Ub.conj(), _shift(L, r, mu, -1))
-        t3 = np.einsum("xad,xcd,xbc->xab", _shift(L, l, mu, 1).conj(), Uf.conj(), r)
-        t4 = np.einsum("xad,xdc,xbc->xab", _shift(L, l, mu, -1).conj(), Ub, r)
+        xf, xb = _nbr(L, x, mu, 1), _nbr(L, x, mu, -1)
+        Uf = Uph[mu][x]                                 # U_mu(x)
+        Ubd = Uph[mu][xb].conj().transpose(0, 2, 1)     # U_mu(x - mu)^dag
+        # l^dag(x+mu) U_mu(x)^dag = (U_mu(x) l(x+mu))^dag, and likewise backwards
+        t1 = outer(l[x], mv(Uf, r[xf]))
+        t2 = outer(l[x], mv(Ubd, r[xb]))
+        t3 = outer(mv(Uf, l[xf]), r[x])
+        t4 = outer(mv(Ubd, l[xb]), r[x])
         out[mu] = 0.25 * (t1 - t2 - t3 + t4)
     return out
 
@@ -351,8 +363,9 @@ def _gammas(form):
     return np.array(Gs)
 
 
-def insertion_densities(L, kappa, eps, t_bc, U, eta, s, estimator, derivative=False):
-    """Per-site loop densities of one (source, solution) pair -> (n_ins, V),
+def insertion_densities(L, kappa, eps, t_bc, U, eta, s, estimator, derivative=False, sites=None):
+    """Per-site loop densities of one (source, solution) pair -> (n_ins, V)
+    (or (n_ins, n_sites) at the given sites),
     n_ins = 16 ultra-local Gamma_n, then (derivative) 16 per direction mu:
       STD      eta^dag X s                       (eq. loopSt)
       ONE_END  2 i eps s^dag gamma5 X s          (eq. loopVv)
@@ -371,10 +384,11 @@ def insertion_densities(L, kappa, eps, t_bc, U, eta, s, estimator, derivative=Fa
         raise ValueError(estimator)
     Gs = _gammas(form)
     l, r = _spinor(L, left), _spinor(L, right)
-    local = np.einsum("nab,xac,xbc->nx", Gs, l.conj(), r)
+    x = np.arange(volume(L)) if sites is None else np.asarray(sites)
+    local = np.einsum("nab,xab->nx", Gs, l[x].conj() @ r[x].transpose(0, 2, 1))
     if not derivative:
         return coef * local
-    P = derivative_outer(L, t_bc, U, l, r)
+    P = derivative_outer(L, t_bc, U, l, r, x)
     der = np.einsum("nab,mxab->mnx", Gs, P).reshape(64, -1)
     return coef * np.concatenate([local, der])
 
@@ -442,15 +456,26 @@ def _bilinear(L, left, right, G):
     return np.einsum("xac,ab,xbc->x", left.conj(), G, right)
 
 
-def project_momenta(L, dens, moms):
-    """sum_{x in t} e^{+i p.x} dens[..., x], p = 2 pi n / L -> (..., n_mom, Lt)."""
-    x, y, z, _ = _site_coords(L)
+def project_momenta(L, dens, moms, slices=None):
+    """sum_{x in t} e^{+i p.x} dens[..., x], p = 2 pi n / L -> (..., n_mom, Lt).
+    With `slices`, dens holds the sites of those time slices only (in site
+    order) and the other slices stay zero."""
+    Vs = L[0] * L[1] * L[2]
+    ts = list(range(L[3])) if slices is None else list(slices)
+    sites = np.concatenate([np.arange(t * Vs, (t + 1) * Vs) for t in ts])
+    x, y, z = sites % L[0], (sites // L[0]) % L[1], (sites // (L[0] * L[1])) % L[2]
     out = np.zeros(dens.shape[:-1] + (len(moms), L[3]), dtype=np.complex128)
     for m, (nx, ny, nz) in enumerate(moms):
         ph = np.exp(2j * np.pi * (nx * x / L[0] + ny * y / L[1] + nz * z / L[2]))
-        # t is the slowest index of the site order: one row per time slice
-        out[..., m, :] = (dens * ph).reshape(dens.shape[:-1] + (L[3], -1)).sum(axis=-1)
+        # one row of Vs sites per listed time slice
+        out[..., m, ts] = (dens * ph).reshape(dens.shape[:-1] + (len(ts), Vs)).sum(axis=-1)
     return out
+
+
+def slice_sites(L, slices):
+    """Site indices of the given time slices, in site order."""
+    Vs = L[0] * L[1] * L[2]
+    return np.concatenate([np.arange(t * Vs, (t + 1) * Vs) for t in slices])
 
 
 def contract_momentum(L, eps, eta, s, estimators, moms):
@@ -468,14 +493,17 @@ def contract_momentum(L, eps, eta, s, estimators, moms):
     return out
 
 
-def contract_insertions(L, kappa, eps, t_bc, U, eta, s, estimators, derivative, moms):
+def contract_insertions(L, kappa, eps, t_bc, U, eta, s, estimators, derivative, moms,
+                        slices=None):
     """Momentum-resolved loops of given fields for any estimators and
-    insertions -> {estimator: (n_mom, n_ins, Lt)}."""
+    insertions -> {estimator: (n_mom, n_ins, Lt)}; with `slices` only those
+    time slices are evaluated (the others are zero)."""
     out = {}
+    sites = None if slices is None else slice_sites(L, slices)
     for e in EST_ALL_ORDER:
         if estimators & e:
-            d = insertion_densities(L, kappa, eps, t_bc, U, eta, s, e, derivative)
-            out[e] = np.transpose(project_momenta(L, d, moms), (1, 0, 2))
+            d = insertion_densities(L, kappa, eps, t_bc, U, eta, s, e, derivative, sites)
+            out[e] = np.transpose(project_momenta(L, d, moms, slices), (1, 0, 2))
     return out
 
 

@@ -56,6 +56,7 @@ class tm_loop_params(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("n_hp", ctypes.c_int), ("n_lp", ctypes.c_int),
                 ("noise_offset", ctypes.c_int), ("dilution", ctypes.c_int),
                 ("estimators", ctypes.c_int), ("mu_sign", ctypes.c_int), ("derivative", ctypes.c_int),
+                ("t_period", ctypes.c_int),
                 ("hp", tm_solve_params), ("lp", tm_solve_params)]
 
 

@@ -284,6 +284,7 @@ extern "C" int tm_batch_loops(tm_batch *b, const tm_loop_params *p, double *cons
             TM_REQUIRE(p[i].n_hp >= 1 && p[i].n_lp == 0, "batched loops take high-precision noises only (n_lp = 0)");
             TM_REQUIRE(p[i].estimators > 0 && p[i].estimators < 16, "bad estimator mask");
             TM_REQUIRE(p[i].derivative == 0 || p[i].derivative == 1, "derivative must be 0 or 1");
+            TM_REQUIRE(p[i].t_period == 0, "batched loops take volume sources (t_period = 0)");
             TM_REQUIRE(!(p[i].derivative && (p[i].estimators & TM_EST_HPE)),
                        "HPE takes ultra-local insertions only (derivative = 0)");
             TM_REQUIRE(p[i].dilution == TM_DIL_NONE || p[i].dilution == TM_DIL_SPIN_COLOUR, "bad dilution");

@@ -126,8 +126,11 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c)
 // Z4 noise number r: entry (site s, spin a, colour c) is i^k, k = top two bits
 // of output ((r*V + s)*4 + a)*3 + c.  dilution = 1 writes 12 right-hand sides,
 // source d = 3a + c holding only that component.
+// RHS j = q * nsc + d (nsc = 12 with spin-colour dilution, else 1): the noise
+// restricted to spin-colour component d (when diluted) and, with time
+// dilution (t_period > 0), to the slices t = o_first + q (mod t_period).
 __global__ __launch_bounds__(kBlock) void k_noise(double2 *even, double2 *odd, Geo g, long V, uint64_t seed,
-                                                  long r, int dilution)
+                                                  long r, int dilution, int t_period, int o_first, int n_off)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.vh) return;
@@ -144,12 +147,14 @@ __global__ __launch_bounds__(kBlock) void k_noise(double2 *even, double2 *odd, G
         eta[k] = q == 0 ? make_double2(1, 0) : q == 1 ? make_double2(0, 1) : q == 2 ? make_double2(-1, 0)
                                                                                    : make_double2(0, -1);
     }
-    if (!dilution) {
-        for (int k = 0; k < 12; k++) dst[(size_t)k * g.vh + i] = eta[k];
-    } else {
-        for (int d = 0; d < 12; d++)
-            for (int k = 0; k < 12; k++)
-                dst[(size_t)(d * 12 + k) * g.vh + i] = (k == d) ? eta[k] : make_double2(0, 0);
+    const int nsc = dilution ? 12 : 1;
+    for (int q = 0; q < n_off; q++) {
+        const bool on = t_period == 0 || t % t_period == o_first + q;
+        for (int d = 0; d < nsc; d++)
+            for (int k = 0; k < 12; k++) {
+                const bool keep = on && (!dilution || k == d);
+                dst[(size_t)((q * nsc + d) * 12 + k) * g.vh + i] = keep ? eta[k] : make_double2(0, 0);
+            }
     }
 }
 
@@ -165,10 +170,11 @@ __device__ __forceinline__ double wave_sum(double v)
 // Per time slice and block: C[b][a] = sum_{x, rhs, colour} v_{b c}(x) conj(w_{a c}(x)),
 // both parities, FP64; partial[t][blk][32].
 template <typename S>
+// time slices t = t0 + dt * blockIdx.y
 __global__ __launch_bounds__(kBlock) void k_outer(const S *ve, const S *vo, const S *we, const S *wo, Geo g,
-                                                  int nrhs, double *part)
+                                                  int nrhs, int t0, int dt, double *part)
 {
-    const int t = blockIdx.y;
+    const int t = t0 + dt * (int)blockIdx.y;
     const int il = blockIdx.x * kBlock + threadIdx.x;
     cx<double> C[16];
 #pragma unroll
@@ -212,12 +218,14 @@ __global__ __launch_bounds__(kBlock) void k_outer(const S *ve, const S *vo, cons
     }
 }
 
-__global__ void k_outer_finish(const double *part, int nblk, double *out)
+// slices not visited by k_outer (t != t0 mod dt, or t < t0) are zero
+__global__ void k_outer_finish(const double *part, int nblk, int t0, int dt, double *out)
 {
     const int t = blockIdx.x;
     const int j = threadIdx.x;  // 32 values
     double s = 0;
-    for (int b = 0; b < nblk; b++) s += part[((size_t)t * nblk + b) * 32 + j];
+    if (t >= t0 && (t - t0) % dt == 0)
+        for (int b = 0; b < nblk; b++) s += part[((size_t)t * nblk + b) * 32 + j];
     out[(size_t)t * 32 + j] = s;
 }
 
@@ -285,22 +293,25 @@ void launch_links_to_f16(tm_ctx *c, hipStream_t s)
     TM_HIP(hipGetLastError());
 }
 
-void launch_noise(tm_ctx *c, void *even, void *odd, uint64_t seed, long r, int dilution, hipStream_t s)
+void launch_noise(tm_ctx *c, void *even, void *odd, uint64_t seed, long r, int dilution, hipStream_t s,
+                  int t_period, int o_first, int n_off)
 {
     dim3 grid((c->geo.vh + kBlock - 1) / kBlock, 2);
     hipLaunchKernelGGL(k_noise, grid, dim3(kBlock), 0, s, (double2 *)even, (double2 *)odd, c->geo, c->V, seed,
-                       r, dilution);
+                       r, dilution, t_period, o_first, n_off);
     TM_HIP(hipGetLastError());
 }
 
 void launch_outer_slices(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
-                         double *dev_out, hipStream_t s)
+                         double *dev_out, hipStream_t s, int t0, int dt)
 {
     const int nblk = (c->geo.vsh + kBlock - 1) / kBlock;
     const int Lt = c->geo.L[3];
+    TM_REQUIRE(t0 >= 0 && t0 < Lt && dt >= 1, "bad time-slice selection");
+    const int n_t = (Lt - t0 + dt - 1) / dt;
     double *part = (double *)ws_get(c, "outer_part", sizeof(double) * 32 * nblk * Lt);
-    hipLaunchKernelGGL(k_outer<double2>, dim3(nblk, Lt), dim3(kBlock), 0, s, (const double2 *)ve,
-                       (const double2 *)vo, (const double2 *)we, (const double2 *)wo, c->geo, nrhs, part);
-    hipLaunchKernelGGL(k_outer_finish, dim3(Lt), dim3(32), 0, s, (const double *)part, nblk, dev_out);
+    hipLaunchKernelGGL(k_outer<double2>, dim3(nblk, n_t), dim3(kBlock), 0, s, (const double2 *)ve,
+                       (const double2 *)vo, (const double2 *)we, (const double2 *)wo, c->geo, nrhs, t0, dt, part);
+    hipLaunchKernelGGL(k_outer_finish, dim3(Lt), dim3(32), 0, s, (const double *)part, nblk, t0, dt, dev_out);
     TM_HIP(hipGetLastError());
 }

@@ -94,7 +94,7 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
 // Colour-traced Dirac outer products per time slice, C[t][b][a] = sum v_b w_a^*,
 // FP64 halves -> host [Lt][16] complex
 void outer_slices_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
-                       std::vector<cx<double>> &out, hipStream_t s);
+                       std::vector<cx<double>> &out, hipStream_t s, int t0 = 0, int dt = 1);
 // Spin matrix inserted for Gamma_n: Gamma_n, gamma5 Gamma_n (one-end) or
 // gamma5 Gamma_n gamma5 (generalised one-end)
 enum GammaForm { G_PLAIN = 0, G_G5_LEFT = 1, G_G5_BOTH = 2 };
@@ -129,9 +129,16 @@ void hpe_exact_part(tm_ctx *c, double epsp, cx<double> *out /* [16][Lt] */);
 // so), estimators in mask order, into dst [n_est][n_ins][Lt], or with mom
 // [n_est][n_mom][n_ins][Lt] (n_ins = n_insertions(derivative)); uses
 // c->stream.  HPE takes ultra-local insertions only.
+// Time-diluted sources of one solve batch: RHS group q (nsc RHS each) has its
+// source on the slices t = o_first + q (mod period); the ultra-local STD and
+// HPE contractions of group q then only visit those slices (the
+// single-time-slice contraction), the source being zero elsewhere.
+struct TimeDil {
+    int period, o_first, n_off, nsc;
+};
 void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, const void *eo, const void *se,
                     const void *so, int nrhs, double epsp, cx<double> *dst,
-                    const std::vector<Momentum> *mom = nullptr);
+                    const std::vector<Momentum> *mom = nullptr, const TimeDil *td = nullptr);
 hipStream_t s_of(tm_ctx *c);
 
 // loops [n_est][n_ins][Lt] (mom = null) or [n_est][n_mom][n_ins][Lt]

@@ -482,11 +482,11 @@ SolveOut solve_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void 
 // ---------------------------------------------------------------- loops
 
 void outer_slices_host(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo, int nrhs,
-                       std::vector<cx<double>> &out, hipStream_t s)
+                       std::vector<cx<double>> &out, hipStream_t s, int t0, int dt)
 {
     const int Lt = c->geo.L[3];
     double *d = (double *)ws_get(c, "outer_out", sizeof(double) * 32 * Lt);
-    launch_outer_slices(c, ve, vo, we, wo, nrhs, d, s);
+    launch_outer_slices(c, ve, vo, we, wo, nrhs, d, s, t0, dt);
     out.resize((size_t)16 * Lt);
     download(c, out.data(), d, sizeof(double) * 32 * Lt, s);
 }
@@ -554,7 +554,8 @@ void op_wilson(tm_ctx *c, void *oe, void *oo, const void *fe, const void *fo, in
 }
 
 void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, const void *eo, const void *se,
-                    const void *so, int nrhs, double epsp, cx<double> *dst, const std::vector<Momentum> *mom)
+                    const void *so, int nrhs, double epsp, cx<double> *dst, const std::vector<Momentum> *mom,
+                    const TimeDil *td)
 {
     const int Lt = c->geo.L[3];
     const size_t per_ins = (size_t)16 * Lt;  // one block of 16 insertions
@@ -565,10 +566,22 @@ void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, c
     const size_t f64 = field_bytes(c, TM_F64, nrhs);
     static const std::vector<Momentum> zero{Momentum{{0, 0, 0}}};
     std::vector<cx<double>> C;
-    // outer products of (right v, left w), then the Gamma insertions per momentum
+    // outer products of (right v, left w), then the Gamma insertions per momentum;
+    // slice_ok: w is the time-diluted source itself, so group q of a
+    // time-diluted batch contributes on its source slices only
     auto outer_loops = [&](const void *ve, const void *vo, const void *we, const void *wo, GammaForm form,
-                           cx<double> coef, bool deriv, cx<double> *out) {
-        if (mom) {
+                           cx<double> coef, bool deriv, cx<double> *out, bool slice_ok = false) {
+        if (!mom && slice_ok && td && td->period > 0) {
+            const size_t grp = (size_t)td->nsc * 12 * c->geo.vh * sizeof(double2);
+            std::vector<cx<double>> acc((size_t)16 * Lt, cx<double>{0, 0});
+            for (int q = 0; q < td->n_off; q++) {
+                outer_slices_host(c, (const char *)ve + q * grp, (const char *)vo + q * grp,
+                                  (const char *)we + q * grp, (const char *)wo + q * grp, td->nsc, C, s_of(c),
+                                  td->o_first + q, td->period);
+                for (size_t j = 0; j < acc.size(); j++) acc[j] = acc[j] + C[j];
+            }
+            loops_from_outer(c, acc.data(), form, coef, out);
+        } else if (mom) {
             outer_momenta_host(c, ve, vo, we, wo, nrhs, *mom, C, s_of(c));
             for (int m = 0; m < n_mom; m++) loops_from_outer(c, C.data() + per_ins * m, form, coef, out + per_m * m);
         } else {
@@ -585,7 +598,7 @@ void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, c
     };
     int k = 0;
     if (estimators & TM_EST_STD)
-        outer_loops(se, so, ee, eo, G_PLAIN, cx<double>{1, 0}, derivative, dst + per * k++);
+        outer_loops(se, so, ee, eo, G_PLAIN, cx<double>{1, 0}, derivative, dst + per * k++, true);
     if (estimators & TM_EST_ONE_END)
         outer_loops(se, so, se, so, G_G5_LEFT, cx<double>{0, 2.0 * epsp}, derivative, dst + per * k++);
     if (estimators & TM_EST_HPE) {
@@ -593,7 +606,7 @@ void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, c
         copy_field(he, se, f64, s_of(c));
         copy_field(ho, so, f64, s_of(c));
         op_bh_power(c, he, ho, nrhs, epsp, 4, s_of(c));
-        outer_loops(he, ho, ee, eo, G_PLAIN, cx<double>{1, 0}, false, dst + per * k++);
+        outer_loops(he, ho, ee, eo, G_PLAIN, cx<double>{1, 0}, false, dst + per * k++, true);
     }
     if (estimators & TM_EST_GEN_ONE_END) {
         // 2 s^dag gamma5 X gamma5 D_W s (eq. loopStD): right field D_W s, left s
@@ -620,7 +633,13 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
         for (int mu = 0; mu < 4; mu++)
             TM_REQUIRE(c->geo.L[mu] >= 4, "HPE needs every L_mu >= 4");
     const int Lt = c->geo.L[3];
-    const int nrhs = p->dilution == TM_DIL_SPIN_COLOUR ? 12 : 1;
+    TM_REQUIRE(p->t_period >= 0 && p->t_period <= Lt && (p->t_period == 0 || Lt % p->t_period == 0),
+               "t_period must be 0 or a divisor of Lt");
+    const int nsc = p->dilution == TM_DIL_SPIN_COLOUR ? 12 : 1;
+    // time dilution: t_period offsets per noise, solved in batches of up to 12 RHS
+    const int n_offsets = p->t_period > 0 ? p->t_period : 1;
+    const int per_batch = p->t_period > 0 ? std::max(1, std::min(n_offsets, 12 / nsc)) : 1;
+    const int nrhs = per_batch * nsc;
     const int n_noise = p->n_hp + p->n_lp;
     const double epsp = eps_of(c, p->mu_sign);
     int n_est = 0;
@@ -638,37 +657,45 @@ int run_loops(tm_ctx *c, const tm_loop_params *p, double *loops, double *per_noi
     int status = TM_OK;
     c->stream = s;
 
-    auto contract = [&](int noise, int slot) {
-        contract_noise(c, p->estimators, p->derivative, ee, eo, se, so, nrhs, epsp,
-                       &pn[((size_t)noise * 2 + slot) * n_est * per], mom);
+    std::vector<cx<double>> part(n_est * per);
+    // per-noise loops summed over the time-dilution batches of the noise
+    auto contract = [&](int noise, int slot, int nr, const TimeDil *td) {
+        contract_noise(c, p->estimators, p->derivative, ee, eo, se, so, nr, epsp, part.data(), mom, td);
+        cx<double> *dst = &pn[((size_t)noise * 2 + slot) * n_est * per];
+        for (size_t j = 0; j < part.size(); j++) dst[j] = dst[j] + part[j];
     };
 
     for (int k = 0; k < n_noise; k++) {
         const long r = (long)p->noise_offset + k;
-        launch_noise(c, ee, eo, p->seed, r, p->dilution, s);
-        if (k < p->n_hp) {
-            tm_solve_params hp = p->hp;
-            hp.mu_sign = p->mu_sign;
-            SolveOut so_ = solve_halves(c, se, so, ee, eo, nrhs, hp, s);
-            for (auto &q : so_.st) {
-                st.n_solves_hp++;
-                st.iters_hp += q.iters;
-                st.max_res_hp = std::max(st.max_res_hp, q.true_rel_res);
+        for (int o = 0; o < n_offsets; o += per_batch) {
+            const int n_off = std::min(per_batch, n_offsets - o);
+            const int nr = n_off * nsc;
+            const TimeDil td{p->t_period, o, n_off, nsc};
+            launch_noise(c, ee, eo, p->seed, r, p->dilution, s, p->t_period, o, n_off);
+            if (k < p->n_hp) {
+                tm_solve_params hp = p->hp;
+                hp.mu_sign = p->mu_sign;
+                SolveOut so_ = solve_halves(c, se, so, ee, eo, nr, hp, s);
+                for (auto &q : so_.st) {
+                    st.n_solves_hp++;
+                    st.iters_hp += q.iters;
+                    st.max_res_hp = std::max(st.max_res_hp, q.true_rel_res);
+                }
+                if (so_.status != TM_OK && status == TM_OK) status = so_.status;
+                contract(k, 0, nr, &td);
             }
-            if (so_.status != TM_OK && status == TM_OK) status = so_.status;
-            contract(k, 0);
-        }
-        if (p->n_lp > 0) {
-            tm_solve_params lp = p->lp;
-            lp.mu_sign = p->mu_sign;
-            SolveOut so_ = solve_halves(c, se, so, ee, eo, nrhs, lp, s);
-            for (auto &q : so_.st) {
-                st.n_solves_lp++;
-                st.iters_lp += q.iters;
-                st.max_res_lp = std::max(st.max_res_lp, q.true_rel_res);
+            if (p->n_lp > 0) {
+                tm_solve_params lp = p->lp;
+                lp.mu_sign = p->mu_sign;
+                SolveOut so_ = solve_halves(c, se, so, ee, eo, nr, lp, s);
+                for (auto &q : so_.st) {
+                    st.n_solves_lp++;
+                    st.iters_lp += q.iters;
+                    st.max_res_lp = std::max(st.max_res_lp, q.true_rel_res);
+                }
+                if (so_.status == TM_ERR_NAN) status = TM_ERR_NAN;
+                contract(k, 1, nr, &td);
             }
-            if (so_.status == TM_ERR_NAN) status = TM_ERR_NAN;
-            contract(k, 1);
         }
     }
 

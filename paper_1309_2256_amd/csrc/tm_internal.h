@@ -389,9 +389,14 @@ void launch_unpack(tm_ctx *c, double *full, const void *even, const void *odd, i
 void launch_gauge_ingest(tm_ctx *c, const double *U, hipStream_t s);
 void launch_links_to_f32(tm_ctx *c, hipStream_t s);
 void launch_links_to_f16(tm_ctx *c, hipStream_t s);
-// Z4 noise for noise index r into FP64 half fields; dilution 1: 12 rhs
-void launch_noise(tm_ctx *c, void *even, void *odd, uint64_t seed, long r, int dilution, hipStream_t s);
+// Z4 noise for noise index r into FP64 half fields: n_off x (12 with
+// spin-colour dilution, else 1) RHS; with t_period > 0 RHS group q keeps the
+// slices t = o_first + q (mod t_period) only (time dilution, coherent when
+// t_period < Lt)
+void launch_noise(tm_ctx *c, void *even, void *odd, uint64_t seed, long r, int dilution, hipStream_t s,
+                  int t_period = 0, int o_first = 0, int n_off = 1);
 // per time slice 4x4 colour-traced outer products C[b][a](t) = sum_x sum_c v_{bc} w*_{ac}
-// accumulated over nrhs pairs and both parities, FP64; out device [Lt][16] complex
+// accumulated over nrhs pairs and both parities, FP64; out device [Lt][16] complex.
+// Only the slices t0, t0 + dt, ... are computed; the others are zero.
 void launch_outer_slices(tm_ctx *c, const void *ve, const void *vo, const void *we, const void *wo,
-                         int nrhs, double *dev_out /* [Lt][16][2] */, hipStream_t s);
+                         int nrhs, double *dev_out /* [Lt][16][2] */, hipStream_t s, int t0 = 0, int dt = 1);

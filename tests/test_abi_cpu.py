@@ -37,7 +37,7 @@ def test_binding_struct_sizes_match_header():
     assert ctypes.sizeof(P.tm_lattice) == 4 * 4 + 8 + 8 + 4 + 4  # padded to 8
     assert ctypes.sizeof(P.tm_solve_params) == 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(P.tm_solve_stats) == 4 * 4 + 3 * 8
-    assert ctypes.sizeof(P.tm_loop_params) == 8 + 7 * 4 + 4 + 2 * ctypes.sizeof(P.tm_solve_params)
+    assert ctypes.sizeof(P.tm_loop_params) == 8 + 8 * 4 + 2 * ctypes.sizeof(P.tm_solve_params)
 
 
 @pytest.mark.parametrize("L", [(3, 4, 4, 4), (4, 4, 4, 5), (0, 4, 4, 4), (4, 4, -2, 4)])

@@ -620,3 +620,18 @@ def test_time_dilution_dense_formula(dense4, period):
             dens = (eta.conj() * (Gc @ y)).reshape(V, 12).sum(1)
             want[n] = dens.reshape(Lt, -1).sum(1)
         assert np.abs(got[e] - want).max() < 1e-12, e
+
+
+def test_site_restricted_evaluation_matches_whole_lattice():
+    """Evaluating the densities at a subset of time slices (used at full
+    lattice size) gives the whole-lattice values on those slices."""
+    L, kappa, eps = (4, 4, 2, 6), 0.124, 0.05
+    U = S.gauge_links(L, 0.4, 31)
+    eta, s = S.random_spinor(L, 32), S.random_spinor(L, 33)
+    moms = O.momenta(1)
+    full = O.contract_insertions(L, kappa, eps, -1, U, eta, s, 1 | 2 | 8, True, moms)
+    part = O.contract_insertions(L, kappa, eps, -1, U, eta, s, 1 | 2 | 8, True, moms,
+                                 slices=[0, 3, 5])
+    for e in full:
+        assert np.abs(part[e][..., [0, 3, 5]] - full[e][..., [0, 3, 5]]).max() < 1e-13
+        assert np.abs(part[e][..., [1, 2, 4]]).max() == 0
