@@ -87,6 +87,7 @@ _SIGS = {
     "tm_set_gauge": (ctypes.c_int, [_vp, _vp, _vp]),
     "tm_dslash": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, _vp]),
+    "tm_set_link_format": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tm_pack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _dp, _vp]),
     "tm_unpack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "tm_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(tm_solve_params),
@@ -187,6 +188,10 @@ class Context:
 
     def set_gauge(self, U, stream=None):
         self._check(tm_set_gauge(self.h, _ptr(U), _stream(stream)))
+
+    def set_link_format(self, params):
+        """Binary16 links of the FP16/BF16-spinor kernels: 18 or 12 parameters."""
+        self._check(tm_set_link_format(self.h, params))
 
     def dslash(self, out, inp, nrhs, kind, mu_sign=1, spinor_prec=TM_F64, link_prec=None,
                stream=None):

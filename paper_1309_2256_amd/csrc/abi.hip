@@ -59,6 +59,15 @@ void ensure_links16(tm_ctx *c, hipStream_t s)
     c->have_links16 = true;
 }
 
+void ensure_links12(tm_ctx *c, hipStream_t s)
+{
+    if (c->have_links12) return;
+    for (int p = 0; p < 2; p++)
+        if (!c->links12[p]) c->links12[p] = ws_get(c, p ? "links12_1" : "links12_0", (size_t)48 * c->geo.vh * 4);
+    launch_links_to_r12(c, s);
+    c->have_links12 = true;
+}
+
 namespace {
 
 template <typename F>
@@ -153,11 +162,21 @@ extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
         c->have_gauge = true;
         c->have_links32 = false;
         c->have_links16 = false;
+        c->have_links12 = false;
         return TM_OK;
     });
 }
 
 // ---------------------------------------------------------------- dslash
+
+extern "C" int tm_set_link_format(tm_ctx *c, int params)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(params == 18 || params == 12, "link format must be 18 or 12 parameters");
+        c->link_recon = params;
+        return TM_OK;
+    });
+}
 
 extern "C" int tm_dslash(tm_ctx *c, void *out, const void *in, int nrhs, int kind, int mu_sign, int spinor_prec,
                          int link_prec, tm_stream stream)

@@ -52,6 +52,7 @@ struct alignas(16) DParams {
     double *part;
     int nblk;       // site blocks
     int nb_t;       // site blocks per time slice (tiled traversal) or 0
+    int t_bc;       // time-boundary factor (rebuilds the third row of 12-parameter links)
 };
 
 // Block -> (site block, right-hand-side group).  Hardware dispatches
@@ -319,7 +320,8 @@ struct BufIO<b2> {
 };
 
 // link entry as held in registers: binary16 links stay binary16 (converted
-// inside the FMAs), FP32/FP64 links in the arithmetic type
+// inside the FMAs), FP32/FP64 links and rebuilt 12-parameter links in the
+// arithmetic type
 template <typename LS, typename T>
 struct LinkEl {
     using type = cx<T>;
@@ -348,14 +350,56 @@ __device__ __forceinline__ void load_spinor(rawc<typename RawT<SS>::L> psi[12], 
     for (int k = 0; k < 12; k++) psi[k] = BufIO<SS>::ldraw(sr, voff, k * vbytes);
 }
 
+// 12-parameter link (sec. IV, link reconstruction): the first two rows in
+// binary16, [8 directions][6][vh]; the third row of a special unitary matrix
+// is the complex conjugate of the cross product of the first two.  The stored
+// rows carry the time-boundary factor f = +-1, which cancels in the cross
+// product (f^2 = 1), so the rebuilt row is multiplied by f again on links
+// that cross the boundary.
+template <typename T>
+__device__ __forceinline__ void load_link12(cx<T> W[9], rsrc_t lr, int vbytes, int voff, bool cross, T tbc)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const rawc<_Float16> w = BufIO<h2>::ldraw(lr, voff, k * vbytes);
+        W[k] = {(T)w.r, (T)w.i};
+    }
+    // conj(a b - c d) for each entry of row0 x row1
+    auto cr = [](cx<T> a, cx<T> b, cx<T> c, cx<T> d) {
+        T re = a.r * b.r;
+        re = fma(-a.i, b.i, re);
+        re = fma(-c.r, d.r, re);
+        re = fma(c.i, d.i, re);
+        T im = a.r * b.i;
+        im = fma(a.i, b.r, im);
+        im = fma(-c.r, d.i, im);
+        im = fma(-c.i, d.r, im);
+        return cx<T>{re, -im};
+    };
+    W[6] = cr(W[1], W[5], W[2], W[4]);
+    W[7] = cr(W[2], W[3], W[0], W[5]);
+    W[8] = cr(W[0], W[4], W[1], W[3]);
+    if (cross) {
+#pragma unroll
+        for (int k = 6; k < 9; k++) W[k] = {tbc * W[k].r, tbc * W[k].i};
+    }
+}
+
 template <int MU, int S, typename SS, typename LS, typename T, int R>
 __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, const rsrc_t *sr, int dir, int j,
-                                       int i)
+                                       int i, int t)
 {
-    const LS *lbase = (const LS *)a.links + (size_t)dir * 9 * a.g.vh;
-    const rsrc_t lr = make_rsrc(lbase, (size_t)9 * a.g.vh * sizeof(LS));
     typename LinkEl<LS, T>::type W[9];
-    load_link<LS, T>(W, lr, a.g.vh * (int)sizeof(LS), i * (int)sizeof(LS));
+    if constexpr (std::is_same<LS, L12>::value) {
+        const h2 *lbase = (const h2 *)a.links + (size_t)dir * 6 * a.g.vh;
+        const rsrc_t lr = make_rsrc(lbase, (size_t)6 * a.g.vh * sizeof(h2));
+        const bool bnd = MU == 3 && (dir < 4 ? t == a.g.L[3] - 1 : t == 0);
+        load_link12<T>(W, lr, a.g.vh * (int)sizeof(h2), i * (int)sizeof(h2), bnd, (T)a.t_bc);
+    } else {
+        const LS *lbase = (const LS *)a.links + (size_t)dir * 9 * a.g.vh;
+        const rsrc_t lr = make_rsrc(lbase, (size_t)9 * a.g.vh * sizeof(LS));
+        load_link<LS, T>(W, lr, a.g.vh * (int)sizeof(LS), i * (int)sizeof(LS));
+    }
 #pragma unroll
     for (int rr = 0; rr < R; rr++) {
         rawc<typename RawT<SS>::L> psi[12];
@@ -447,14 +491,14 @@ __device__ __forceinline__ void dslash_block(const DParams<T> &a, int bhw, int n
         if (c[mu] < 0) c[mu] = a.g.L[mu] - 1;
         const int j = eo_index(a.g, c[0], c[1], c[2], c[3]);
         switch (d) {
-        case 0: do_dir<0, SF, SS, LS, T, R>(acc, a, sr, 0, j, i); break;
-        case 1: do_dir<1, SF, SS, LS, T, R>(acc, a, sr, 1, j, i); break;
-        case 2: do_dir<2, SF, SS, LS, T, R>(acc, a, sr, 2, j, i); break;
-        case 3: do_dir<3, SF, SS, LS, T, R>(acc, a, sr, 3, j, i); break;
-        case 4: do_dir<0, SB, SS, LS, T, R>(acc, a, sr, 4, j, i); break;
-        case 5: do_dir<1, SB, SS, LS, T, R>(acc, a, sr, 5, j, i); break;
-        case 6: do_dir<2, SB, SS, LS, T, R>(acc, a, sr, 6, j, i); break;
-        default: do_dir<3, SB, SS, LS, T, R>(acc, a, sr, 7, j, i); break;
+        case 0: do_dir<0, SF, SS, LS, T, R>(acc, a, sr, 0, j, i, t); break;
+        case 1: do_dir<1, SF, SS, LS, T, R>(acc, a, sr, 1, j, i, t); break;
+        case 2: do_dir<2, SF, SS, LS, T, R>(acc, a, sr, 2, j, i, t); break;
+        case 3: do_dir<3, SF, SS, LS, T, R>(acc, a, sr, 3, j, i, t); break;
+        case 4: do_dir<0, SB, SS, LS, T, R>(acc, a, sr, 4, j, i, t); break;
+        case 5: do_dir<1, SB, SS, LS, T, R>(acc, a, sr, 5, j, i, t); break;
+        case 6: do_dir<2, SB, SS, LS, T, R>(acc, a, sr, 6, j, i, t); break;
+        default: do_dir<3, SB, SS, LS, T, R>(acc, a, sr, 7, j, i, t); break;
         }
     }
 
@@ -595,6 +639,7 @@ DParams<T> fill_params(tm_ctx *c, const DslashCall &dc)
     a.own = dc.own;
     a.links = (std::is_same<LS, double2>::value ? c->links64
                : std::is_same<LS, h2>::value     ? c->links16
+               : std::is_same<LS, L12>::value    ? c->links12
                                                  : c->links32)[dc.out_parity];
     a.g = c->geo;
     a.p = dc.out_parity;
@@ -611,6 +656,7 @@ DParams<T> fill_params(tm_ctx *c, const DslashCall &dc)
     a.part = dc.part;
     a.nblk = dslash_site_blocks(c);
     a.nb_t = (c->geo.vsh % kBlock == 0 && (c->geo.vsh / kBlock) % 8 == 0) ? c->geo.vsh / kBlock : 0;
+    a.t_bc = c->t_bc;
     return a;
 }
 
@@ -662,8 +708,11 @@ template <typename SS, typename LS, typename T>
 void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 {
     const int n = dc.nrhs;
-    // tiles are tuned per (spinor precision, link storage, nrhs)
-    const auto key = std::make_pair(dc.spinor_prec + (std::is_same<LS, h2>::value ? 8 : 0), n);
+    // tiles are tuned per (spinor precision, link storage, operator form, nrhs):
+    // the fused epilogues favour other tiles than the plain store
+    const int lcode = std::is_same<LS, h2>::value ? 1 : std::is_same<LS, L12>::value ? 2 : 0;
+    const int form = dc.dag + 2 * (dc.has_own ? 1 : 0) + 4 * dc.epi;
+    const auto key = std::make_pair(dc.spinor_prec + 8 * lcode + 32 * form, n);
     auto it = c->rhs_tile.find(key);
     if (it != c->rhs_tile.end()) {
         launch_r<SS, LS, T>(c, dc, it->second, s);
@@ -674,15 +723,23 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     TM_HIP(hipStreamIsCapturing(s, &cs));
     const int def = sizeof(T) == 8 ? 1 : (n % 2 == 0 ? 2 : 1);
-    // repeated launches must give the same result: no fused update, output
-    // distinct from both inputs
-    const bool repeatable = dc.epi == 0 && dc.out != dc.in && dc.out != dc.own;
+    // timing launches must leave the caller's fields as they were: the output
+    // distinct from both inputs, and the in-place CG update of the fused form
+    // redirected to scratch fields (its block partials are rewritten by the
+    // real launch that follows)
+    DslashCall tc = dc;
+    const bool repeatable = dc.epi == EPI_CG || (dc.out != dc.in && dc.out != dc.own);
     if (fixed > 0 && fixed <= max_tile<T>() && n % fixed == 0) {
         c->rhs_tile[key] = fixed;
     } else if (!repeatable || cs != hipStreamCaptureStatusNone || n == 1) {
         launch_r<SS, LS, T>(c, dc, def, s);  // tune on a later plain launch
         return;
     } else {
+        if (dc.epi == EPI_CG) {  // not capturing here: allocation is allowed
+            const size_t fb = (size_t)prec_bytes(dc.spinor_prec) * 12 * c->geo.vh * n;
+            tc.r = ws_get(c, "tune_r", fb);
+            tc.rho = dc.rho ? ws_get(c, "tune_rho", fb) : nullptr;
+        }
         hipEvent_t e0, e1;
         TM_HIP(hipEventCreate(&e0));
         TM_HIP(hipEventCreate(&e1));
@@ -690,10 +747,10 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         int bestR = def;
         for (int R = 1; R <= max_tile<T>(); R++) {
             if (n % R) continue;
-            launch_r<SS, LS, T>(c, dc, R, s);  // warm
+            launch_r<SS, LS, T>(c, tc, R, s);  // warm
             TM_HIP(hipEventRecord(e0, s));
-            launch_r<SS, LS, T>(c, dc, R, s);
-            launch_r<SS, LS, T>(c, dc, R, s);
+            // enough launches that tiles a few percent apart are ranked reliably
+            for (int k = 0; k < 6; k++) launch_r<SS, LS, T>(c, tc, R, s);
             TM_HIP(hipEventRecord(e1, s));
             TM_HIP(hipEventSynchronize(e1));
             float ms = 0;
@@ -757,7 +814,7 @@ void multi_go(const MultiDslash &m, hipStream_t s)
 }
 
 template <typename F>
-void multi_dispatch(int prec, int R, F &&f)
+void multi_dispatch(int prec, bool recon12, int R, F &&f)
 {
     auto byR = [&](auto *tag) {
         using P3 = std::remove_pointer_t<decltype(tag)>;
@@ -777,11 +834,13 @@ void multi_dispatch(int prec, int R, F &&f)
     struct PF { using SS = float2; using LS = float2; using T = float; };
     struct PH { using SS = h2; using LS = h2; using T = float; };
     struct PB { using SS = b2; using LS = h2; using T = float; };
+    struct PH12 { using SS = h2; using LS = L12; using T = float; };
+    struct PB12 { using SS = b2; using LS = L12; using T = float; };
     switch (prec) {
     case TM_F64: byR((PD *)nullptr); break;
     case TM_F32: byR((PF *)nullptr); break;
-    case TM_F16: byR((PH *)nullptr); break;
-    case TM_BF16: byR((PB *)nullptr); break;
+    case TM_F16: recon12 ? byR((PH12 *)nullptr) : byR((PH *)nullptr); break;
+    case TM_BF16: recon12 ? byR((PB12 *)nullptr) : byR((PB *)nullptr); break;
     default: throw TmError{TM_ERR_ARG, "bad precision"};
     }
 }
@@ -803,15 +862,24 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
                        dcs[k].epi == m.epi,
                    "multi-instance calls must share precision and operator form");
         TM_REQUIRE(cs[k]->have_gauge, "no gauge field set");
+        TM_REQUIRE(cs[k]->link_recon == cs[0]->link_recon, "multi-instance calls must share the link format");
         if (m.prec == TM_F32) ensure_links32(cs[k], s);
-        if (m.prec == TM_F16 || m.prec == TM_BF16) ensure_links16(cs[k], s);
+        if (m.prec == TM_F16 || m.prec == TM_BF16) {
+            if (cs[k]->link_recon == 12)
+                ensure_links12(cs[k], s);
+            else
+                ensure_links16(cs[k], s);
+        }
     }
-    multi_dispatch(m.prec, R, [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs); });
+    m.recon12 = cs[0]->link_recon == 12;
+    multi_dispatch(m.prec, m.recon12, R,
+                   [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs); });
 }
 
 void multi_dslash_launch(const MultiDslash &m, hipStream_t s)
 {
-    multi_dispatch(m.prec, m.R, [&]<typename SS, typename LS, typename T, int RR>() { multi_go<SS, LS, T, RR>(m, s); });
+    multi_dispatch(m.prec, m.recon12, m.R,
+                   [&]<typename SS, typename LS, typename T, int RR>() { multi_go<SS, LS, T, RR>(m, s); });
 }
 
 int dslash_site_blocks(tm_ctx *c) { return (c->geo.vh + kBlock - 1) / kBlock; }
@@ -822,12 +890,16 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     switch (dc.spinor_prec) {
     case TM_F64: launch_rhs<double2, double2, double>(c, dc, s); break;
     case TM_F32: ensure_links32(c, s); launch_rhs<float2, float2, float>(c, dc, s); break;
-    // FP16/BF16 spinors: binary16 links (the solvers' choice) unless the
-    // caller asked for the FP32 copy
+    // FP16/BF16 spinors: binary16 links in the context's format (all 18
+    // parameters or 12 with the third row rebuilt; the solvers' choice)
+    // unless the caller asked for the FP32 copy
     case TM_F16:
         if (c->half_links_f32) {
             ensure_links32(c, s);
             launch_rhs<h2, float2, float>(c, dc, s);
+        } else if (c->link_recon == 12) {
+            ensure_links12(c, s);
+            launch_rhs<h2, L12, float>(c, dc, s);
         } else {
             ensure_links16(c, s);
             launch_rhs<h2, h2, float>(c, dc, s);
@@ -837,6 +909,9 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         if (c->half_links_f32) {
             ensure_links32(c, s);
             launch_rhs<b2, float2, float>(c, dc, s);
+        } else if (c->link_recon == 12) {
+            ensure_links12(c, s);
+            launch_rhs<b2, L12, float>(c, dc, s);
         } else {
             ensure_links16(c, s);
             launch_rhs<b2, h2, float>(c, dc, s);

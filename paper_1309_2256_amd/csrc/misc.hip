@@ -91,6 +91,18 @@ __global__ __launch_bounds__(kBlock) void k_gauge_ingest(double2 *l0, double2 *l
     }
 }
 
+// out[d][k][i] = binary16(in[d][k][i]) for the first two rows (k < 6) of
+// every link, d < 8, i < vh
+__global__ __launch_bounds__(kBlock) void k_d2h_rows(h2 *out, const double2 *in, long vh)
+{
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 48 * vh) return;
+    const long i = idx % vh, dk = idx / vh;
+    const long d = dk / 6, k = dk % 6;
+    const double2 v = in[(d * 9 + k) * vh + i];
+    out[idx] = h2{(_Float16)v.x, (_Float16)v.y};
+}
+
 __global__ __launch_bounds__(kBlock) void k_d2f(float2 *out, const double2 *in, size_t n)
 {
     for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
@@ -281,6 +293,15 @@ void launch_links_to_f32(tm_ctx *c, hipStream_t s)
     for (int p = 0; p < 2; p++)
         hipLaunchKernelGGL(k_d2f, dim3(2048), dim3(kBlock), 0, s, (float2 *)c->links32[p],
                            (const double2 *)c->links64[p], n);
+    TM_HIP(hipGetLastError());
+}
+
+void launch_links_to_r12(tm_ctx *c, hipStream_t s)
+{
+    const long n = 48L * c->geo.vh;
+    for (int p = 0; p < 2; p++)
+        hipLaunchKernelGGL(k_d2h_rows, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           (h2 *)c->links12[p], (const double2 *)c->links64[p], (long)c->geo.vh);
     TM_HIP(hipGetLastError());
 }
 

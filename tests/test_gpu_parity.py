@@ -235,6 +235,55 @@ def test_schur_low_precision(prec, links, bound, L):
     assert torch.equal(odd, outh[:3 * ctx.half_numel(prec, 1)])
 
 
+@pytest.mark.parametrize("prec,bound", [(P.TM_F16, 4e-3), (P.TM_BF16, 3e-2)])
+@pytest.mark.parametrize("t_bc", [-1, 1])
+@pytest.mark.parametrize("L", [(4, 4, 4, 8), (6, 4, 2, 6)])
+def test_link_format_12_parameters(prec, bound, t_bc, L):
+    """12-parameter binary16 links (third row rebuilt in the kernel, boundary
+    factor restored on the links that cross t = Lt-1 <-> 0): every operator
+    kind against the FP64 oracle at the storage rounding level, for both time
+    boundary conditions; RHS tiles bit-identical; the rebuilt operator
+    differs from the 18-parameter one only at the binary16 level."""
+    kappa, eps = 0.124, 0.0123
+    ctx, U = make_ctx(L, kappa, eps, 17, t_bc=t_bc)
+    nrhs = 2
+    v = S.random_spinor(L, 8, nrhs)
+    e, o = half_buf(ctx, prec, nrhs), half_buf(ctx, prec, nrhs)
+    ctx.pack(e, o, cuda(v), nrhs, prec)
+    ve = [mask_parity(L, v[r], 0) for r in range(nrhs)]
+    vo = [mask_parity(L, v[r], 1) for r in range(nrhs)]
+    cases = [
+        (P.TM_HOP_OE, e, 1, lambda r: mask_parity(L, O.hop(L, kappa, t_bc, U, ve[r]), 1)),
+        (P.TM_HOP_EO, o, 0, lambda r: mask_parity(L, O.hop(L, kappa, t_bc, U, vo[r]), 0)),
+        (P.TM_SCHUR, e, 0, lambda r: O.schur(L, kappa, eps, t_bc, U, ve[r])),
+        (P.TM_SCHUR_DAG, e, 0, lambda r: O.schur(L, kappa, eps, t_bc, U, ve[r], adj=True)),
+    ]
+    outs = {}
+    for fmt in (12, 18):
+        ctx.set_link_format(fmt)
+        for kind, inp, par, ref in cases:
+            outh = half_buf(ctx, prec, nrhs)
+            ctx.dslash(outh, inp, nrhs, kind, 1, prec, P.TM_F16)
+            full = torch.zeros((nrhs,) + v.shape[1:], dtype=torch.complex128, device=DEV)
+            if par == 0:
+                ctx.unpack(full, outh, half_buf(ctx, prec, nrhs), nrhs, prec)
+            else:
+                ctx.unpack(full, half_buf(ctx, prec, nrhs), outh, nrhs, prec)
+            got = host(full)
+            outs[(fmt, kind)] = got
+            for r in range(nrhs):
+                assert rel(got[r], ref(r)) < bound, (fmt, kind, r, rel(got[r], ref(r)))
+            if fmt == 12:
+                nb = ctx.half_numel(prec, 1)
+                one = half_buf(ctx, prec, 1)
+                ctx.dslash(one, inp[nb:2 * nb], 1, kind, 1, prec, P.TM_F16)
+                assert torch.equal(one, outh[nb:2 * nb]), kind
+    for kind, _, _, _ in cases:
+        assert 0 < rel(outs[(12, kind)], outs[(18, kind)]) < bound
+    with pytest.raises(P.TMError):
+        ctx.set_link_format(8)
+
+
 def test_dslash_rejects_bad_arguments():
     L = (4, 4, 4, 8)
     ctx, _ = make_ctx(L, 0.124, 0.01, 5)
@@ -271,10 +320,12 @@ def test_solve_fp64(mu_sign):
         assert stats[r].converged == 1 and stats[r].iters > 0
 
 
-@pytest.mark.parametrize("prec", [P.TM_F32, P.TM_F16, P.TM_BF16])
-def test_solve_mixed_reliable_updates(prec):
+@pytest.mark.parametrize("prec,fmt", [(P.TM_F32, 18), (P.TM_F16, 18), (P.TM_BF16, 18),
+                                      (P.TM_F16, 12), (P.TM_BF16, 12)])
+def test_solve_mixed_reliable_updates(prec, fmt):
     L, kappa, eps = (8, 8, 8, 8), 0.124, 0.005
     ctx, U = make_ctx(L, kappa, eps, 31, 0.3)
+    ctx.set_link_format(fmt)
     nrhs = 2
     b = S.random_spinor(L, 22, nrhs)
     x = torch.zeros_like(cuda(b))
