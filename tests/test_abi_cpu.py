@@ -94,3 +94,13 @@ def test_momentum_calls_on_null_context():
     import paper_1309_2256_amd as P
     assert P.tm_contract_momentum(None, None, None, 1, 1, 1, 0, 0, None, None) == P.TM_ERR_ARG
     assert P.tm_loops_momentum(None, None, 0, None, None, None, None) == P.TM_ERR_ARG
+
+
+def test_link_format_and_loop_entry_points_on_null_context():
+    import paper_1309_2256_amd as P
+    assert P.tm_set_link_format(None, 12) == P.TM_ERR_ARG
+    assert P.tm_loops(None, None, None, None, None, None) == P.TM_ERR_ARG
+    assert P.tm_loops_momentum(None, None, 0, None, None, None, None) == P.TM_ERR_ARG
+    assert ctypes.sizeof(P.tm_loop_params) == 8 + 8 * 4 + 2 * ctypes.sizeof(P.tm_solve_params)
+    p = P.tm_loop_params()
+    assert p.derivative == 0 and p.t_period == 0     # zero-initialised: local, volume sources
