@@ -32,7 +32,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dslash-reps", type=int, default=50)
+    ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-ptc", action="store_true",
@@ -129,7 +129,7 @@ def main():
     bufs = [torch.randn(nb // 2, dtype=torch.float16, device=dev) * 0.1 for _ in range(2)]
     outb = torch.empty(nb, dtype=torch.uint8, device=dev)
     ctx.set_link_format(LINK_PARAMS)  # the library default, stated for the byte count
-    for _ in range(3):
+    for _ in range(10):
         ctx.dslash(outb, bufs[0], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16, P.TM_F16)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -147,6 +147,35 @@ def main():
     alg_bytes = vh * nrhs * bytes_per_site_rhs
     achieved = alg_bytes / dslash_s / 1e9
     del bufs, outb
+
+    # the other Dslash forms the solvers run: FP64 1 RHS (plain solve and
+    # reliable updates), FP16 1 RHS (low-precision TSM solves without dilution)
+    def time_dslash(prec, n, reps=100):
+        nbytes = ctx.half_numel(prec, n)
+        dt_ = torch.float64 if prec == P.TM_F64 else torch.float16
+        ins = [torch.randn(nbytes // dt_.itemsize, dtype=dt_, device=dev) * 0.1 for _ in range(2)]
+        o = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        for _ in range(10):
+            ctx.dslash(o, ins[0], n, P.TM_RINV_HOP_OE, 1, prec)
+        torch.cuda.synchronize()
+        ev0.record()
+        for r in range(reps):
+            ctx.dslash(o, ins[r % 2], n, P.TM_RINV_HOP_OE, 1, prec)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    dslash_cases = {}
+    for name, prec, n, site_rhs_bytes in (
+            ("fp64_1rhs", P.TM_F64, 1, 192 + 192 + 8 * 9 * 16),
+            ("fp16_1rhs_12param_links", P.TM_F16, 1, 48 + 48 + 8 * 6 * 4)):
+        t_s = time_dslash(prec, n)
+        b_ = vh * n * site_rhs_bytes
+        dslash_cases[name] = {"us": t_s * 1e6, "algorithmic_bytes": b_,
+                              "algorithmic_tb_s": b_ / t_s / 1e12, "frac_of_8tb_s": b_ / t_s / 8e12}
+    dslash_cases["fp16_12rhs_12param_links"] = {
+        "us": dslash_s * 1e6, "algorithmic_bytes": alg_bytes, "algorithmic_tb_s": achieved / 1e3,
+        "frac_of_8tb_s": achieved / HBM_PEAK_GBS}
 
     # practical streaming ceiling (and the calibration kernel for the HBM
     # byte counters): a device-to-device copy of 1 GiB each way
@@ -178,7 +207,31 @@ def main():
         per_iter = (t2 - t1) / args.cpu_iters
         setup = max(t1 - per_iter, 0.0)
         cpu_solve_s = setup + plain_iters * per_iter
+        tc = time.perf_counter()
+        O.hop(L, kappa, -1, U, src)
+        hop_s = time.perf_counter() - tc
+        # the small lattices: a full oracle solve on 4^3x8, CG iterations on 16^3x32
+        small = {}
+        cf = S.CONFIGS["c1"]
+        Uc = S.gauge_links(cf["L"], cf["eps_links"], cf["seed"])
+        ec = O.noise_z4(cf["L"], S.NOISE_SEEDS["c1"], 0)
+        tc = time.perf_counter()
+        _, its, res = O.cgnr(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 1e-9)
+        dt_c = time.perf_counter() - tc
+        small["c1"] = {"lattice": list(cf["L"]), "iterations": int(its), "seconds": dt_c,
+                       "solves_per_s": 1.0 / dt_c, "residual": float(res)}
+        cf = S.CONFIGS["c2"]
+        Uc = S.gauge_links(cf["L"], cf["eps_links"], cf["seed"])
+        ec = O.noise_z4(cf["L"], S.NOISE_SEEDS["c2"], 0)
+        tc = time.perf_counter()
+        O.cgnr_iterations(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 1)
+        ta = time.perf_counter() - tc
+        tc = time.perf_counter()
+        O.cgnr_iterations(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 6)
+        tb = time.perf_counter() - tc
+        small["c2"] = {"lattice": list(cf["L"]), "per_iteration_s": (tb - ta) / 5}
         cpu = {"value": 1.0 / cpu_solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "per_iteration_s": per_iter, "full_lattice_hop_s": hop_s, "small_lattices": small,
                "sample": "FP64 oracle CGNR on the even-odd system, same source and lattice; "
                          "%d + %d CG iterations timed (%.1fs), %.2fs per iteration, scaled "
                          "to the %d iterations the plain FP64 GPU solve needed for 1e-9"
@@ -209,6 +262,7 @@ def main():
         "chosen_iters_per_solve": chosen_iters,
         "speedup_vs_plain": value / plain_value,
         "dslash_tb_s": achieved / 1e3,
+        "dslash_cases": dslash_cases,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
