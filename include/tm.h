@@ -69,7 +69,7 @@ typedef enum {
     TM_ERR_OOM = -3,         /* device allocation failed */
     TM_ERR_NOCONV = -4,      /* a solve reached maxiter; x holds the last iterate */
     TM_ERR_NAN = -5,         /* NaN/Inf met in a solver reduction */
-    TM_ERR_UNSUPPORTED = -6  /* valid request that this build does not implement */
+    TM_ERR_UNSUPPORTED = -6  /* valid request that the library does not implement   */
 } tm_status;
 
 typedef enum { TM_F64 = 0, TM_F32 = 1, TM_F16 = 2, TM_BF16 = 3 } tm_prec;
