@@ -114,6 +114,40 @@ def test_batch_loops(inst):
         assert err < 1e-7, (key, err)
 
 
+def test_batch_loops_insertions_and_gen(inst):
+    """Batched loops with the generalised one-end estimator and one-derivative
+    insertions (80 per estimator) and the HPE in mask order STD, HPE, GEN:
+    each instance against the single-lattice driver; time dilution is
+    rejected for batches."""
+    hp = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+    est = P.TM_EST_STD | P.TM_EST_GEN_ONE_END
+    plist = [loop_params(1050 + k, 1, est, hp) for k, d in enumerate(inst)]
+    for p in plist:
+        p.derivative = 1
+    batch = P.Batch([d["ctx"] for d in inst])
+    outs, stats, _ = batch.loops(plist)
+    for k, d in enumerate(inst):
+        assert outs[k].shape == (2, 80, d["cfg"]["L"][3])
+        single, _, _, _ = d["ctx"].loops(plist[k])
+        for e in range(2):
+            err = np.abs(outs[k][e] - single[e]).max() / np.abs(single[e]).max()
+            assert err < 1e-7, (d["name"], e, err)
+    est3 = P.TM_EST_STD | P.TM_EST_HPE | P.TM_EST_GEN_ONE_END
+    plist = [loop_params(1060 + k, 1, est3, hp) for k, d in enumerate(inst)]
+    outs, _, _ = batch.loops(plist)
+    for k, d in enumerate(inst):
+        single, _, _, _ = d["ctx"].loops(plist[k])
+        for e in range(3):
+            err = np.abs(outs[k][e] - single[e]).max() / np.abs(single[e]).max()
+            assert err < 1e-7, (d["name"], e, err)
+    bad = [loop_params(1, 1, P.TM_EST_STD, hp) for _ in inst]
+    bad[0].t_period = 2
+    with pytest.raises(P.TMError) as ei:
+        batch.loops(bad)
+    assert ei.value.status == P.TM_ERR_ARG
+    batch.close()
+
+
 def test_batch_argument_checks(inst):
     import ctypes
     arr = (ctypes.c_void_p * 2)(inst[0]["ctx"].h, inst[0]["ctx"].h)
