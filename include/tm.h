@@ -98,16 +98,17 @@ const char *tm_last_error(const tm_ctx *ctx);
  * them (each rounded once from FP64, to nearest even).  U is not retained. */
 int tm_set_gauge(tm_ctx *ctx, const double *U, tm_stream stream);
 
-/* Binary16 link format of the FP16/BF16-spinor kernels (tm_dslash with
- * link_prec TM_F16 and every mixed or low-precision solve):
+/* Link format of the FP64 kernels and of the FP16/BF16-spinor kernels
+ * (binary16 links; tm_dslash with link_prec TM_F64 or TM_F16 and every
+ * solve):
  *   18  all nine complex entries per link;
- *   12  (default) the first two rows only (sec. IV, 12-parameter reconstruction): the
- *       third row of the special unitary link is rebuilt in the kernel as the
- *       complex conjugate of the cross product of the first two, times the
- *       time-boundary factor on links that cross t = Lt-1 <-> 0.  Needs links
- *       in SU(3) (the gauge field given to tm_set_gauge).
- * The FP64 and FP32 kernels keep all 18.  Returns TM_ERR_ARG for other
- * values. */
+ *   12  (default) the first two rows only (sec. IV, 12-parameter
+ *       reconstruction): the third row of the special unitary link is
+ *       rebuilt in the kernel as the complex conjugate of the cross product of
+ *       the first two, times the time-boundary factor on links that cross
+ *       t = Lt-1 <-> 0.  Needs links in SU(3) (the gauge field given to
+ *       tm_set_gauge).
+ * The FP32 kernels keep all 18.  Returns TM_ERR_ARG for other values. */
 int tm_set_link_format(tm_ctx *ctx, int params);
 
 /* Operator kinds of tm_dslash. */

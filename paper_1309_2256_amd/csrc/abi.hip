@@ -68,6 +68,15 @@ void ensure_links12(tm_ctx *c, hipStream_t s)
     c->have_links12 = true;
 }
 
+void ensure_links12d(tm_ctx *c, hipStream_t s)
+{
+    if (c->have_links12d) return;
+    for (int p = 0; p < 2; p++)
+        if (!c->links12d[p]) c->links12d[p] = ws_get(c, p ? "links12d_1" : "links12d_0", (size_t)48 * c->geo.vh * 16);
+    launch_links_to_r12d(c, s);
+    c->have_links12d = true;
+}
+
 namespace {
 
 template <typename F>
@@ -163,6 +172,7 @@ extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
         c->have_links32 = false;
         c->have_links16 = false;
         c->have_links12 = false;
+        c->have_links12d = false;
         return TM_OK;
     });
 }

@@ -356,13 +356,17 @@ __device__ __forceinline__ void load_spinor(rawc<typename RawT<SS>::L> psi[12], 
 // rows carry the time-boundary factor f = +-1, which cancels in the cross
 // product (f^2 = 1), so the rebuilt row is multiplied by f again on links
 // that cross the boundary.
-template <typename T>
+template <typename RS, typename T>
 __device__ __forceinline__ void load_link12(cx<T> W[9], rsrc_t lr, int vbytes, int voff, bool cross, T tbc)
 {
 #pragma unroll
     for (int k = 0; k < 6; k++) {
-        const rawc<_Float16> w = BufIO<h2>::ldraw(lr, voff, k * vbytes);
-        W[k] = {(T)w.r, (T)w.i};
+        if constexpr (std::is_same<RS, h2>::value) {
+            const rawc<_Float16> w = BufIO<h2>::ldraw(lr, voff, k * vbytes);
+            W[k] = {(T)w.r, (T)w.i};
+        } else {
+            W[k] = BufIO<RS>::template ldlink<T>(lr, voff, k * vbytes);
+        }
     }
     // conj(a b - c d) for each entry of row0 x row1
     auto cr = [](cx<T> a, cx<T> b, cx<T> c, cx<T> d) {
@@ -390,11 +394,12 @@ __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, co
                                        int i, int t)
 {
     typename LinkEl<LS, T>::type W[9];
-    if constexpr (std::is_same<LS, L12>::value) {
-        const h2 *lbase = (const h2 *)a.links + (size_t)dir * 6 * a.g.vh;
-        const rsrc_t lr = make_rsrc(lbase, (size_t)6 * a.g.vh * sizeof(h2));
+    if constexpr (std::is_same<LS, L12>::value || std::is_same<LS, L12D>::value) {
+        using RS = std::conditional_t<std::is_same<LS, L12>::value, h2, double2>;
+        const RS *lbase = (const RS *)a.links + (size_t)dir * 6 * a.g.vh;
+        const rsrc_t lr = make_rsrc(lbase, (size_t)6 * a.g.vh * sizeof(RS));
         const bool bnd = MU == 3 && (dir < 4 ? t == a.g.L[3] - 1 : t == 0);
-        load_link12<T>(W, lr, a.g.vh * (int)sizeof(h2), i * (int)sizeof(h2), bnd, (T)a.t_bc);
+        load_link12<RS, T>(W, lr, a.g.vh * (int)sizeof(RS), i * (int)sizeof(RS), bnd, (T)a.t_bc);
     } else {
         const LS *lbase = (const LS *)a.links + (size_t)dir * 9 * a.g.vh;
         const rsrc_t lr = make_rsrc(lbase, (size_t)9 * a.g.vh * sizeof(LS));
@@ -640,6 +645,7 @@ DParams<T> fill_params(tm_ctx *c, const DslashCall &dc)
     a.links = (std::is_same<LS, double2>::value ? c->links64
                : std::is_same<LS, h2>::value     ? c->links16
                : std::is_same<LS, L12>::value    ? c->links12
+               : std::is_same<LS, L12D>::value   ? c->links12d
                                                  : c->links32)[dc.out_parity];
     a.g = c->geo;
     a.p = dc.out_parity;
@@ -710,7 +716,10 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     const int n = dc.nrhs;
     // tiles are tuned per (spinor precision, link storage, operator form, nrhs):
     // the fused epilogues favour other tiles than the plain store
-    const int lcode = std::is_same<LS, h2>::value ? 1 : std::is_same<LS, L12>::value ? 2 : 0;
+    const int lcode = std::is_same<LS, h2>::value    ? 1
+                      : std::is_same<LS, L12>::value ? 2
+                      : std::is_same<LS, L12D>::value ? 3
+                                                      : 0;
     const int form = dc.dag + 2 * (dc.has_own ? 1 : 0) + 4 * dc.epi;
     const auto key = std::make_pair(dc.spinor_prec + 8 * lcode + 32 * form, n);
     auto it = c->rhs_tile.find(key);
@@ -831,13 +840,14 @@ void multi_dispatch(int prec, bool recon12, int R, F &&f)
         }
     };
     struct PD { using SS = double2; using LS = double2; using T = double; };
+    struct PD12 { using SS = double2; using LS = L12D; using T = double; };
     struct PF { using SS = float2; using LS = float2; using T = float; };
     struct PH { using SS = h2; using LS = h2; using T = float; };
     struct PB { using SS = b2; using LS = h2; using T = float; };
     struct PH12 { using SS = h2; using LS = L12; using T = float; };
     struct PB12 { using SS = b2; using LS = L12; using T = float; };
     switch (prec) {
-    case TM_F64: byR((PD *)nullptr); break;
+    case TM_F64: recon12 ? byR((PD12 *)nullptr) : byR((PD *)nullptr); break;
     case TM_F32: byR((PF *)nullptr); break;
     case TM_F16: recon12 ? byR((PH12 *)nullptr) : byR((PH *)nullptr); break;
     case TM_BF16: recon12 ? byR((PB12 *)nullptr) : byR((PB *)nullptr); break;
@@ -864,6 +874,7 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
         TM_REQUIRE(cs[k]->have_gauge, "no gauge field set");
         TM_REQUIRE(cs[k]->link_recon == cs[0]->link_recon, "multi-instance calls must share the link format");
         if (m.prec == TM_F32) ensure_links32(cs[k], s);
+        if (m.prec == TM_F64 && cs[k]->link_recon == 12) ensure_links12d(cs[k], s);
         if (m.prec == TM_F16 || m.prec == TM_BF16) {
             if (cs[k]->link_recon == 12)
                 ensure_links12(cs[k], s);
@@ -888,7 +899,16 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 {
     TM_REQUIRE(c->have_gauge, "no gauge field set");
     switch (dc.spinor_prec) {
-    case TM_F64: launch_rhs<double2, double2, double>(c, dc, s); break;
+    // FP64 (the plain solver and the reliable updates): 12-parameter FP64
+    // links in the context's format, the third row rebuilt exactly up to rounding
+    case TM_F64:
+        if (c->link_recon == 12) {
+            ensure_links12d(c, s);
+            launch_rhs<double2, L12D, double>(c, dc, s);
+        } else {
+            launch_rhs<double2, double2, double>(c, dc, s);
+        }
+        break;
     case TM_F32: ensure_links32(c, s); launch_rhs<float2, float2, float>(c, dc, s); break;
     // FP16/BF16 spinors: binary16 links in the context's format (all 18
     // parameters or 12 with the third row rebuilt; the solvers' choice)

@@ -103,6 +103,16 @@ __global__ __launch_bounds__(kBlock) void k_d2h_rows(h2 *out, const double2 *in,
     out[idx] = h2{(_Float16)v.x, (_Float16)v.y};
 }
 
+// the same rows kept in FP64
+__global__ __launch_bounds__(kBlock) void k_d2d_rows(double2 *out, const double2 *in, long vh)
+{
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 48 * vh) return;
+    const long i = idx % vh, dk = idx / vh;
+    const long d = dk / 6, k = dk % 6;
+    out[idx] = in[(d * 9 + k) * vh + i];
+}
+
 __global__ __launch_bounds__(kBlock) void k_d2f(float2 *out, const double2 *in, size_t n)
 {
     for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
@@ -302,6 +312,15 @@ void launch_links_to_r12(tm_ctx *c, hipStream_t s)
     for (int p = 0; p < 2; p++)
         hipLaunchKernelGGL(k_d2h_rows, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                            (h2 *)c->links12[p], (const double2 *)c->links64[p], (long)c->geo.vh);
+    TM_HIP(hipGetLastError());
+}
+
+void launch_links_to_r12d(tm_ctx *c, hipStream_t s)
+{
+    const long n = 48L * c->geo.vh;
+    for (int p = 0; p < 2; p++)
+        hipLaunchKernelGGL(k_d2d_rows, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           (double2 *)c->links12d[p], (const double2 *)c->links64[p], (long)c->geo.vh);
     TM_HIP(hipGetLastError());
 }
 

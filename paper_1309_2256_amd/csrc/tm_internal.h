@@ -79,8 +79,10 @@ __host__ __device__ __forceinline__ void cmac_conj(cx<T> &acc, cx<T> a, cx<T> b)
 // ---------------------------------------------------------------- storage types
 
 // IEEE binary16 pair and bfloat16 pair, 4 bytes per complex value.
-// tag type of the 12-parameter binary16 link format (Dslash template argument)
+// tag types of the 12-parameter link formats (Dslash template argument):
+// binary16 rows and FP64 rows
 struct L12 {};
+struct L12D {};
 
 struct alignas(4) h2 {
     _Float16 x, y;
@@ -257,10 +259,13 @@ struct tm_ctx {
     void *links16[2] = {nullptr, nullptr};  // IEEE binary16 copy (FP16/BF16 spinors)
     // binary16 12-parameter copy: the first two rows, [8 directions][6][vh]
     void *links12[2] = {nullptr, nullptr};
+    // FP64 12-parameter copy, same layout
+    void *links12d[2] = {nullptr, nullptr};
     bool have_gauge = false;
     bool have_links32 = false;
     bool have_links16 = false;
     bool have_links12 = false;
+    bool have_links12d = false;
     // binary16 link format of the FP16/BF16-spinor kernels: 18 or 12
     // parameters (12 reads a third fewer link bytes; measured no slower at 12
     // RHS and 9-24% faster at 1-4 RHS per call)
@@ -288,6 +293,7 @@ void *host_stage(tm_ctx *c, size_t bytes);
 void ensure_links32(tm_ctx *c, hipStream_t s);
 void ensure_links16(tm_ctx *c, hipStream_t s);
 void ensure_links12(tm_ctx *c, hipStream_t s);
+void ensure_links12d(tm_ctx *c, hipStream_t s);
 
 // ---------------------------------------------------------------- dslash
 
@@ -403,6 +409,8 @@ void launch_links_to_f32(tm_ctx *c, hipStream_t s);
 void launch_links_to_f16(tm_ctx *c, hipStream_t s);
 // first two rows of every link, rounded once to binary16: [8][6][vh] per parity
 void launch_links_to_r12(tm_ctx *c, hipStream_t s);
+// first two rows of every link in FP64: [8][6][vh] per parity
+void launch_links_to_r12d(tm_ctx *c, hipStream_t s);
 // Z4 noise for noise index r into FP64 half fields: n_off x (12 with
 // spin-colour dilution, else 1) RHS; with t_period > 0 RHS group q keeps the
 // slices t = o_first + q (mod t_period) only (time dilution, coherent when

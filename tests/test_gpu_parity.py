@@ -284,6 +284,45 @@ def test_link_format_12_parameters(prec, bound, t_bc, L):
         ctx.set_link_format(8)
 
 
+@pytest.mark.parametrize("t_bc", [-1, 1])
+def test_link_format_12_parameters_fp64(t_bc):
+    """FP64 kernels with 12-parameter FP64 links (the plain solver and the
+    reliable updates): every operator kind within 1e-13 of the oracle for
+    both time boundary conditions, and within 1e-14 of the 18-parameter
+    result (the rebuilt third row differs only by rounding)."""
+    L, kappa, eps = (4, 4, 2, 6), 0.124, 0.0123
+    ctx, U = make_ctx(L, kappa, eps, 19, t_bc=t_bc)
+    nrhs = 2
+    v = S.random_spinor(L, 9, nrhs)
+    prec = P.TM_F64
+    e, o = half_buf(ctx, prec, nrhs), half_buf(ctx, prec, nrhs)
+    ctx.pack(e, o, cuda(v), nrhs, prec)
+    ve = [mask_parity(L, v[r], 0) for r in range(nrhs)]
+    cases = [
+        (P.TM_HOP_OE, e, 1, lambda r: mask_parity(L, O.hop(L, kappa, t_bc, U, ve[r]), 1)),
+        (P.TM_SCHUR, e, 0, lambda r: O.schur(L, kappa, eps, t_bc, U, ve[r])),
+        (P.TM_SCHUR_DAG, e, 0, lambda r: O.schur(L, kappa, eps, t_bc, U, ve[r], adj=True)),
+        (P.TM_NORMAL, e, 0, lambda r: O.schur(L, kappa, eps, t_bc, U,
+                                              O.schur(L, kappa, eps, t_bc, U, ve[r]), adj=True)),
+    ]
+    outs = {}
+    for fmt in (12, 18):
+        ctx.set_link_format(fmt)
+        for kind, inp, par, ref in cases:
+            outh = half_buf(ctx, prec, nrhs)
+            ctx.dslash(outh, inp, nrhs, kind, 1, prec, P.TM_F64)
+            full = torch.zeros((nrhs,) + v.shape[1:], dtype=torch.complex128, device=DEV)
+            if par == 0:
+                ctx.unpack(full, outh, half_buf(ctx, prec, nrhs), nrhs, prec)
+            else:
+                ctx.unpack(full, half_buf(ctx, prec, nrhs), outh, nrhs, prec)
+            outs[(fmt, kind)] = host(full)
+            for r in range(nrhs):
+                assert rel(outs[(fmt, kind)][r], ref(r)) < 1e-13, (fmt, kind, r)
+    for kind, _, _, _ in cases:
+        assert rel(outs[(12, kind)], outs[(18, kind)]) < 1e-14
+
+
 def test_dslash_rejects_bad_arguments():
     L = (4, 4, 4, 8)
     ctx, _ = make_ctx(L, 0.124, 0.01, 5)
