@@ -167,7 +167,7 @@ def main():
 
     dslash_cases = {}
     for name, prec, n, site_rhs_bytes in (
-            ("fp64_1rhs", P.TM_F64, 1, 192 + 192 + 8 * 9 * 16),
+            ("fp64_1rhs_12param_links", P.TM_F64, 1, 192 + 192 + 8 * (LINK_PARAMS // 2) * 16),
             ("fp16_1rhs_12param_links", P.TM_F16, 1, 48 + 48 + 8 * 6 * 4)):
         t_s = time_dslash(prec, n)
         b_ = vh * n * site_rhs_bytes
