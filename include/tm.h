@@ -98,8 +98,8 @@ const char *tm_last_error(const tm_ctx *ctx);
  * them (each rounded once from FP64, to nearest even).  U is not retained. */
 int tm_set_gauge(tm_ctx *ctx, const double *U, tm_stream stream);
 
-/* Link format of the FP64 kernels and of the FP16/BF16-spinor kernels
- * (binary16 links; tm_dslash with link_prec TM_F64 or TM_F16 and every
+/* Link format of the Dslash kernels (FP64 links for FP64 spinors, FP32 for
+ * FP32, binary16 for FP16/BF16 unless tm_dslash asks for FP32 links; every
  * solve):
  *   18  all nine complex entries per link;
  *   12  (default) the first two rows only (sec. IV, 12-parameter
@@ -108,7 +108,8 @@ int tm_set_gauge(tm_ctx *ctx, const double *U, tm_stream stream);
  *       the first two, times the time-boundary factor on links that cross
  *       t = Lt-1 <-> 0.  Needs links in SU(3) (the gauge field given to
  *       tm_set_gauge).
- * The FP32 kernels keep all 18.  Returns TM_ERR_ARG for other values. */
+ * FP16/BF16 spinors with FP32 links (tm_dslash, link_prec TM_F32) keep all
+ * 18.  Returns TM_ERR_ARG for other values. */
 int tm_set_link_format(tm_ctx *ctx, int params);
 
 /* Operator kinds of tm_dslash. */

@@ -77,6 +77,15 @@ void ensure_links12d(tm_ctx *c, hipStream_t s)
     c->have_links12d = true;
 }
 
+void ensure_links12f(tm_ctx *c, hipStream_t s)
+{
+    if (c->have_links12f) return;
+    for (int p = 0; p < 2; p++)
+        if (!c->links12f[p]) c->links12f[p] = ws_get(c, p ? "links12f_1" : "links12f_0", (size_t)48 * c->geo.vh * 8);
+    launch_links_to_r12f(c, s);
+    c->have_links12f = true;
+}
+
 namespace {
 
 template <typename F>
@@ -173,6 +182,7 @@ extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
         c->have_links16 = false;
         c->have_links12 = false;
         c->have_links12d = false;
+        c->have_links12f = false;
         return TM_OK;
     });
 }

@@ -394,8 +394,9 @@ __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, co
                                        int i, int t)
 {
     typename LinkEl<LS, T>::type W[9];
-    if constexpr (std::is_same<LS, L12>::value || std::is_same<LS, L12D>::value) {
-        using RS = std::conditional_t<std::is_same<LS, L12>::value, h2, double2>;
+    if constexpr (std::is_same<LS, L12>::value || std::is_same<LS, L12D>::value || std::is_same<LS, L12F>::value) {
+        using RS = std::conditional_t<std::is_same<LS, L12>::value, h2,
+                                      std::conditional_t<std::is_same<LS, L12D>::value, double2, float2>>;
         const RS *lbase = (const RS *)a.links + (size_t)dir * 6 * a.g.vh;
         const rsrc_t lr = make_rsrc(lbase, (size_t)6 * a.g.vh * sizeof(RS));
         const bool bnd = MU == 3 && (dir < 4 ? t == a.g.L[3] - 1 : t == 0);
@@ -646,6 +647,7 @@ DParams<T> fill_params(tm_ctx *c, const DslashCall &dc)
                : std::is_same<LS, h2>::value     ? c->links16
                : std::is_same<LS, L12>::value    ? c->links12
                : std::is_same<LS, L12D>::value   ? c->links12d
+               : std::is_same<LS, L12F>::value   ? c->links12f
                                                  : c->links32)[dc.out_parity];
     a.g = c->geo;
     a.p = dc.out_parity;
@@ -719,6 +721,7 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     const int lcode = std::is_same<LS, h2>::value    ? 1
                       : std::is_same<LS, L12>::value ? 2
                       : std::is_same<LS, L12D>::value ? 3
+                      : std::is_same<LS, L12F>::value ? 4
                                                       : 0;
     const int form = dc.dag + 2 * (dc.has_own ? 1 : 0) + 4 * dc.epi;
     const auto key = std::make_pair(dc.spinor_prec + 8 * lcode + 32 * form, n);
@@ -842,13 +845,14 @@ void multi_dispatch(int prec, bool recon12, int R, F &&f)
     struct PD { using SS = double2; using LS = double2; using T = double; };
     struct PD12 { using SS = double2; using LS = L12D; using T = double; };
     struct PF { using SS = float2; using LS = float2; using T = float; };
+    struct PF12 { using SS = float2; using LS = L12F; using T = float; };
     struct PH { using SS = h2; using LS = h2; using T = float; };
     struct PB { using SS = b2; using LS = h2; using T = float; };
     struct PH12 { using SS = h2; using LS = L12; using T = float; };
     struct PB12 { using SS = b2; using LS = L12; using T = float; };
     switch (prec) {
     case TM_F64: recon12 ? byR((PD12 *)nullptr) : byR((PD *)nullptr); break;
-    case TM_F32: byR((PF *)nullptr); break;
+    case TM_F32: recon12 ? byR((PF12 *)nullptr) : byR((PF *)nullptr); break;
     case TM_F16: recon12 ? byR((PH12 *)nullptr) : byR((PH *)nullptr); break;
     case TM_BF16: recon12 ? byR((PB12 *)nullptr) : byR((PB *)nullptr); break;
     default: throw TmError{TM_ERR_ARG, "bad precision"};
@@ -873,7 +877,12 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
                    "multi-instance calls must share precision and operator form");
         TM_REQUIRE(cs[k]->have_gauge, "no gauge field set");
         TM_REQUIRE(cs[k]->link_recon == cs[0]->link_recon, "multi-instance calls must share the link format");
-        if (m.prec == TM_F32) ensure_links32(cs[k], s);
+        if (m.prec == TM_F32) {
+            if (cs[k]->link_recon == 12)
+                ensure_links12f(cs[k], s);
+            else
+                ensure_links32(cs[k], s);
+        }
         if (m.prec == TM_F64 && cs[k]->link_recon == 12) ensure_links12d(cs[k], s);
         if (m.prec == TM_F16 || m.prec == TM_BF16) {
             if (cs[k]->link_recon == 12)
@@ -909,7 +918,15 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
             launch_rhs<double2, double2, double>(c, dc, s);
         }
         break;
-    case TM_F32: ensure_links32(c, s); launch_rhs<float2, float2, float>(c, dc, s); break;
+    case TM_F32:
+        if (c->link_recon == 12) {
+            ensure_links12f(c, s);
+            launch_rhs<float2, L12F, float>(c, dc, s);
+        } else {
+            ensure_links32(c, s);
+            launch_rhs<float2, float2, float>(c, dc, s);
+        }
+        break;
     // FP16/BF16 spinors: binary16 links in the context's format (all 18
     // parameters or 12 with the third row rebuilt; the solvers' choice)
     // unless the caller asked for the FP32 copy

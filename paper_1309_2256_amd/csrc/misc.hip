@@ -113,6 +113,17 @@ __global__ __launch_bounds__(kBlock) void k_d2d_rows(double2 *out, const double2
     out[idx] = in[(d * 9 + k) * vh + i];
 }
 
+// and rounded once to FP32
+__global__ __launch_bounds__(kBlock) void k_d2f_rows(float2 *out, const double2 *in, long vh)
+{
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 48 * vh) return;
+    const long i = idx % vh, dk = idx / vh;
+    const long d = dk / 6, k = dk % 6;
+    const double2 v = in[(d * 9 + k) * vh + i];
+    out[idx] = make_float2((float)v.x, (float)v.y);
+}
+
 __global__ __launch_bounds__(kBlock) void k_d2f(float2 *out, const double2 *in, size_t n)
 {
     for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
@@ -321,6 +332,15 @@ void launch_links_to_r12d(tm_ctx *c, hipStream_t s)
     for (int p = 0; p < 2; p++)
         hipLaunchKernelGGL(k_d2d_rows, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                            (double2 *)c->links12d[p], (const double2 *)c->links64[p], (long)c->geo.vh);
+    TM_HIP(hipGetLastError());
+}
+
+void launch_links_to_r12f(tm_ctx *c, hipStream_t s)
+{
+    const long n = 48L * c->geo.vh;
+    for (int p = 0; p < 2; p++)
+        hipLaunchKernelGGL(k_d2f_rows, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           (float2 *)c->links12f[p], (const double2 *)c->links64[p], (long)c->geo.vh);
     TM_HIP(hipGetLastError());
 }
 

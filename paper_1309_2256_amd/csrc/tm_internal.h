@@ -83,6 +83,7 @@ __host__ __device__ __forceinline__ void cmac_conj(cx<T> &acc, cx<T> a, cx<T> b)
 // binary16 rows and FP64 rows
 struct L12 {};
 struct L12D {};
+struct L12F {};
 
 struct alignas(4) h2 {
     _Float16 x, y;
@@ -259,13 +260,15 @@ struct tm_ctx {
     void *links16[2] = {nullptr, nullptr};  // IEEE binary16 copy (FP16/BF16 spinors)
     // binary16 12-parameter copy: the first two rows, [8 directions][6][vh]
     void *links12[2] = {nullptr, nullptr};
-    // FP64 12-parameter copy, same layout
+    // FP64 and FP32 12-parameter copies, same layout
     void *links12d[2] = {nullptr, nullptr};
+    void *links12f[2] = {nullptr, nullptr};
     bool have_gauge = false;
     bool have_links32 = false;
     bool have_links16 = false;
     bool have_links12 = false;
     bool have_links12d = false;
+    bool have_links12f = false;
     // binary16 link format of the FP16/BF16-spinor kernels: 18 or 12
     // parameters (12 reads a third fewer link bytes; measured no slower at 12
     // RHS and 9-24% faster at 1-4 RHS per call)
@@ -294,6 +297,7 @@ void ensure_links32(tm_ctx *c, hipStream_t s);
 void ensure_links16(tm_ctx *c, hipStream_t s);
 void ensure_links12(tm_ctx *c, hipStream_t s);
 void ensure_links12d(tm_ctx *c, hipStream_t s);
+void ensure_links12f(tm_ctx *c, hipStream_t s);
 
 // ---------------------------------------------------------------- dslash
 
@@ -411,6 +415,8 @@ void launch_links_to_f16(tm_ctx *c, hipStream_t s);
 void launch_links_to_r12(tm_ctx *c, hipStream_t s);
 // first two rows of every link in FP64: [8][6][vh] per parity
 void launch_links_to_r12d(tm_ctx *c, hipStream_t s);
+// first two rows of every link rounded once to FP32: [8][6][vh] per parity
+void launch_links_to_r12f(tm_ctx *c, hipStream_t s);
 // Z4 noise for noise index r into FP64 half fields: n_off x (12 with
 // spin-colour dilution, else 1) RHS; with t_period > 0 RHS group q keeps the
 // slices t = o_first + q (mod t_period) only (time dilution, coherent when

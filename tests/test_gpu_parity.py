@@ -235,11 +235,11 @@ def test_schur_low_precision(prec, links, bound, L):
     assert torch.equal(odd, outh[:3 * ctx.half_numel(prec, 1)])
 
 
-@pytest.mark.parametrize("prec,bound", [(P.TM_F16, 4e-3), (P.TM_BF16, 3e-2)])
+@pytest.mark.parametrize("prec,bound", [(P.TM_F16, 4e-3), (P.TM_BF16, 3e-2), (P.TM_F32, 2e-6)])
 @pytest.mark.parametrize("t_bc", [-1, 1])
 @pytest.mark.parametrize("L", [(4, 4, 4, 8), (6, 4, 2, 6)])
 def test_link_format_12_parameters(prec, bound, t_bc, L):
-    """12-parameter binary16 links (third row rebuilt in the kernel, boundary
+    """12-parameter binary16 (FP16/BF16 spinors) or FP32 links (third row rebuilt in the kernel, boundary
     factor restored on the links that cross t = Lt-1 <-> 0): every operator
     kind against the FP64 oracle at the storage rounding level, for both time
     boundary conditions; RHS tiles bit-identical; the rebuilt operator
@@ -259,11 +259,12 @@ def test_link_format_12_parameters(prec, bound, t_bc, L):
         (P.TM_SCHUR_DAG, e, 0, lambda r: O.schur(L, kappa, eps, t_bc, U, ve[r], adj=True)),
     ]
     outs = {}
+    lprec = P.TM_F32 if prec == P.TM_F32 else P.TM_F16
     for fmt in (12, 18):
         ctx.set_link_format(fmt)
         for kind, inp, par, ref in cases:
             outh = half_buf(ctx, prec, nrhs)
-            ctx.dslash(outh, inp, nrhs, kind, 1, prec, P.TM_F16)
+            ctx.dslash(outh, inp, nrhs, kind, 1, prec, lprec)
             full = torch.zeros((nrhs,) + v.shape[1:], dtype=torch.complex128, device=DEV)
             if par == 0:
                 ctx.unpack(full, outh, half_buf(ctx, prec, nrhs), nrhs, prec)
@@ -276,7 +277,7 @@ def test_link_format_12_parameters(prec, bound, t_bc, L):
             if fmt == 12:
                 nb = ctx.half_numel(prec, 1)
                 one = half_buf(ctx, prec, 1)
-                ctx.dslash(one, inp[nb:2 * nb], 1, kind, 1, prec, P.TM_F16)
+                ctx.dslash(one, inp[nb:2 * nb], 1, kind, 1, prec, lprec)
                 assert torch.equal(one, outh[nb:2 * nb]), kind
     for kind, _, _, _ in cases:
         assert 0 < rel(outs[(12, kind)], outs[(18, kind)]) < bound
