@@ -336,7 +336,8 @@ int tm_batch_solve(tm_batch *batch, double *const *x, const double *const *b, co
 /* Per-instance loops (sec. II, as tm_loops) with p[i].n_hp noise vectors of
  * high-precision solves each (n_lp must be 0), all instances' sources solved
  * in one batch; p[i].hp must agree across instances in solver, inner_prec and
- * check_every.  loops[i]: host [n_est_i][n_ins_i][Lt_i] complex double; stats:
+ * check_every; volume sources only (t_period = 0).  loops[i]: host
+ * [n_est_i][n_ins_i][Lt_i] complex double; stats:
  * host array of n entries or NULL. */
 int tm_batch_loops(tm_batch *batch, const tm_loop_params *p, double *const *loops,
                    tm_loop_stats *stats, tm_stream stream);
