@@ -82,7 +82,10 @@ typedef struct {
 } tm_lattice;
 
 /* Create a context on HIP device `device` for the given lattice.
- * Returns TM_ERR_ARG for odd or non-positive extents. */
+ * Returns TM_ERR_ARG for odd or non-positive extents, TM_ERR_UNSUPPORTED when
+ * one FP64 right-hand side of a half field (V/2 x 12 x 16 bytes) exceeds
+ * 2^31 - 1 bytes (the kernels' 32-bit offsets; V <= 22369620 sites, e.g.
+ * 48^3 x 96 fits, 64^3 x 128 does not). */
 int tm_create(tm_ctx **ctx, const tm_lattice *lat, int device);
 
 /* Destroy a context and free every buffer it owns.  NULL is ignored. */
@@ -95,19 +98,25 @@ const char *tm_last_error(const tm_ctx *ctx);
  * double.  Builds the internal even-odd link layout (forward links and
  * pre-conjugated backward links per site, boundary phase folded in) in FP64,
  * and the FP32 and IEEE binary16 copies on first use by a kernel that reads
- * them (each rounded once from FP64, to nearest even).  U is not retained. */
+ * them (each rounded once from FP64, to nearest even).  Measures how far the
+ * links are from SU(3) (max over links of |U U^dag - 1| and |det U - 1|,
+ * entrywise) and synchronises the stream for that.  U is not retained. */
 int tm_set_gauge(tm_ctx *ctx, const double *U, tm_stream stream);
 
 /* Link format of the Dslash kernels (FP64 links for FP64 spinors, FP32 for
  * FP32, binary16 for FP16/BF16 unless tm_dslash asks for FP32 links; every
  * solve):
  *   18  all nine complex entries per link;
- *   12  (default) the first two rows only (sec. IV, 12-parameter
+ *   12  (default) the first two rows only (appendix A.1, 12-parameter
  *       reconstruction): the third row of the special unitary link is
  *       rebuilt in the kernel as the complex conjugate of the cross product of
  *       the first two, times the time-boundary factor on links that cross
- *       t = Lt-1 <-> 0.  Needs links in SU(3) (the gauge field given to
- *       tm_set_gauge).
+ *       t = Lt-1 <-> 0.  Used by the kernels of a precision only while the
+ *       field's measured distance from SU(3) (tm_set_gauge) stays below that
+ *       precision's rounding scale (FP64 1e-12, FP32 1e-6, binary16 1e-3);
+ *       otherwise those kernels read all 18.  Reliable-update residuals and
+ *       the final true residual of every solve always use all 18 FP64
+ *       parameters.
  * FP16/BF16 spinors with FP32 links (tm_dslash, link_prec TM_F32) keep all
  * 18.  Returns TM_ERR_ARG for other values. */
 int tm_set_link_format(tm_ctx *ctx, int params);
@@ -154,8 +163,10 @@ typedef enum {
                         FP16/BF16 storage reads binary16 links, FP32 storage
                         FP32 links */
     TM_CG_LOW = 2,   /* truncated low-precision CGNR (TSM low-precision solve):
-                        inner_prec storage, FP32 arithmetic, no reliable update;
-                        stops on the iterated residual */
+                        inner_prec storage, FP32 arithmetic; when the iterated
+                        residual meets tol the FP64 true residual is formed and
+                        right-hand sides still above tol continue from it, so
+                        the exit criterion holds for |b - M x| / |b| */
     TM_FGMRES = 3,   /* restarted GMRES(m) on the full system M x = b in FP64
                         (no preconditioner); the reference for TM_FGMRES_PTC */
     TM_FGMRES_PTC = 4 /* flexible GMRES(m) (Saad 1993) in FP64, right-
@@ -184,6 +195,16 @@ typedef struct {
     double true_rel_res;  /* |b - M x| / |b| recomputed in FP64 at exit         */
     double iter_rel_res;  /* the solver's own (iterated) residual at exit       */
     double seconds;       /* wall time of the whole call                        */
+    double bytes;         /* algorithmic device-memory bytes of the call's
+                             kernels (every field and link read once and every
+                             output written once per launch), this RHS's share
+                             (the call's total / nrhs)                           */
+    double flops;         /* the call's floating-point work / nrhs: per site
+                             and RHS 1320 for the hopping term of a half-Dslash,
+                             72 for its spin-diagonal coefficient, 96 for an
+                             own-site term, 48 per fused norm or vector update;
+                             vector kernels by their arithmetic (a complex
+                             multiply 6, an add 2)                               */
 } tm_solve_stats;
 
 /* Solve M(mu_sign) x = b for nrhs right-hand sides at once.
@@ -218,7 +239,7 @@ enum {
 };
 
 /* Insertions per estimator.  derivative = 0: the 16 ultra-local Gamma_n.
- * derivative = 1: also the one-derivative insertions of sec. III (the
+ * derivative = 1: also the one-derivative insertions of appendix A.2 (the
  * covariant-derivative kernel), n_ins = 80, insertion 16 (1 + mu) + n for
  * direction mu = 0..3 (x, y, z, t): the bilinear w^dag Gamma_n D_mu v with
  * the symmetric left-right covariant derivative attributed to site x,
@@ -285,8 +306,8 @@ int tm_contract(tm_ctx *ctx, const double *eta, const double *s, int nrhs, int e
                 int mu_sign, double *out, tm_stream stream);
 
 /* ---------------------------------------------------------------- momenta
- * Momentum projection of the loops (sec. III, contraction kernels and the
- * Fourier step): L_n(t, p) = sum_{x in t} e^{+i p.x} [loop density at x],
+ * Momentum projection of the loops (appendix A.2, contraction kernels, and
+ * the Fourier step of appendix A.3): L_n(t, p) = sum_{x in t} e^{+i p.x} [loop density at x],
  * p = 2 pi (n_x / L_x, n_y / L_y, n_z / L_z), x = (x, y, z) in 0 .. L - 1,
  * for every integer vector n with |n|^2 <= p2max (the paper's cut-off in p^2,
  * in units of (2 pi / L)^2).  Momentum order: |n|^2 ascending, then n_x, n_y,

@@ -21,7 +21,7 @@ marshals arguments and writes out the estimator formulas of the paper:
     (eq. loopStD),
   * the Hopping Parameter Expansion (section II.E, eqs. HPE and loopHPE1),
   * one-derivative insertions (the covariant-derivative contraction of
-    section III) and the momentum projection (the Fourier step of section III).
+    appendix A.2) and the momentum projection (the Fourier step of appendix A.3).
 """
 import ctypes
 import os

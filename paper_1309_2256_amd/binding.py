@@ -49,7 +49,8 @@ class tm_solve_params(ctypes.Structure):
 class tm_solve_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("n_reliable", ctypes.c_int), ("converged", ctypes.c_int),
                 ("reserved", ctypes.c_int), ("true_rel_res", ctypes.c_double),
-                ("iter_rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("iter_rel_res", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class tm_loop_params(ctypes.Structure):

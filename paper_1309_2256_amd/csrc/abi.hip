@@ -128,6 +128,9 @@ extern "C" int tm_create(tm_ctx **out, const tm_lattice *lat, int device)
         V *= lat->L[mu];
     }
     if (V / 2 > (1L << 30)) return TM_ERR_ARG;
+    // the kernels address one right-hand side of a half field with 32-bit
+    // byte offsets (FP64: 12 complex of 16 bytes per half-site)
+    if ((V / 2) * 12L * 16L > 0x7fffffffL) return TM_ERR_UNSUPPORTED;
     if (!std::isfinite(lat->kappa) || !std::isfinite(lat->two_kappa_mu)) return TM_ERR_ARG;
     if (lat->t_bc != 1 && lat->t_bc != -1) return TM_ERR_ARG;
     int ndev = 0;
@@ -177,6 +180,7 @@ extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
                 c->links64[p] = q;
             }
         launch_gauge_ingest(c, U, hs(stream));
+        c->su3_dev = gauge_su3_deviation(c, U, hs(stream));
         c->have_gauge = true;
         c->have_links32 = false;
         c->have_links16 = false;
@@ -310,6 +314,7 @@ extern "C" int tm_solve(tm_ctx *c, double *x, const double *b, int nrhs, const t
         TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
         TM_REQUIRE(c->have_gauge, "no gauge field set");
         hipStream_t s = hs(stream);
+        const double b0 = c->acct_bytes, f0 = c->acct_flops;
         const size_t hb = half_bytes(c, TM_F64, nrhs);
         void *be = ws_get(c, "a_be", hb), *bo = ws_get(c, "a_bo", hb);
         void *xe = ws_get(c, "a_xe", hb), *xo = ws_get(c, "a_xo", hb);
@@ -322,6 +327,8 @@ extern "C" int tm_solve(tm_ctx *c, double *x, const double *b, int nrhs, const t
             for (int i = 0; i < nrhs; i++) {
                 stats[i] = r.st[i];
                 stats[i].seconds = secs;
+                stats[i].bytes = (c->acct_bytes - b0) / nrhs;
+                stats[i].flops = (c->acct_flops - f0) / nrhs;
             }
         if (r.status == TM_ERR_NOCONV) c->err = "a right-hand side missed the tolerance within maxiter";
         if (r.status == TM_ERR_NAN) c->err = "NaN/Inf in the solution";

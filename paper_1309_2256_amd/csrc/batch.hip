@@ -172,12 +172,26 @@ void run_batch(tm_batch *b, std::vector<Solver> &S)
             }
             continue;
         }
-        if (b->eager) {
-            if (!b->single_launches) prepare_stages(b, S, set, choose_R(b, S, set));
-            for (int k = 0; k < K; k++) launch_iteration(b, S, set);
-        } else {
-            if (b->graph_set != set || b->graph_iters != K) build_graph(b, S, set, K);
-            TM_HIP(hipGraphLaunch(b->exec, b->stream));
+        // the grouped iterations are accounted per instance below, not per
+        // recorded launch (a graph is recorded once and replayed)
+        for (int i : set) S[i].c->acct_pause++;
+        try {
+            if (b->eager) {
+                if (!b->single_launches) prepare_stages(b, S, set, choose_R(b, S, set));
+                for (int k = 0; k < K; k++) launch_iteration(b, S, set);
+            } else {
+                if (b->graph_set != set || b->graph_iters != K) build_graph(b, S, set, K);
+                TM_HIP(hipGraphLaunch(b->exec, b->stream));
+            }
+        } catch (...) {
+            for (int i : set) S[i].c->acct_pause--;
+            throw;
+        }
+        for (int i : set) {
+            S[i].c->acct_pause--;
+            double ib, ifl;
+            S[i].iter_cost(ib, ifl);
+            account(S[i].c, K * ib, K * ifl);
         }
         for (int i : set) {
             for (int k = 0; k < K; k++) S[i].count_iteration();
@@ -245,6 +259,11 @@ extern "C" int tm_batch_solve(tm_batch *b, double *const *x, const double *const
         const auto t0 = std::chrono::steady_clock::now();
         std::vector<Solver> S(n);
         std::vector<void *> xe(n), xo(n);
+        std::vector<double> b0(n), f0(n);
+        for (int i = 0; i < n; i++) {
+            b0[i] = b->ctx[i]->acct_bytes;
+            f0[i] = b->ctx[i]->acct_flops;
+        }
         for (int i = 0; i < n; i++) {
             tm_ctx *c = b->ctx[i];
             const size_t hb = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * nrhs[i];
@@ -265,6 +284,8 @@ extern "C" int tm_batch_solve(tm_batch *b, double *const *x, const double *const
                 for (int k = 0; k < nrhs[i]; k++) {
                     stats[i][k] = r.st[k];
                     stats[i][k].seconds = secs;
+                    stats[i][k].bytes = (b->ctx[i]->acct_bytes - b0[i]) / nrhs[i];
+                    stats[i][k].flops = (b->ctx[i]->acct_flops - f0[i]) / nrhs[i];
                 }
             if (r.status != TM_OK && status == TM_OK) status = r.status;
         }

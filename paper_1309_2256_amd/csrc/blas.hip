@@ -226,6 +226,7 @@ void launch_spin_diag(tm_ctx *c, void *out, const void *in, int prec, int nrhs, 
     size_t n = half_elems(c);
     dim3 grid(grid_for(n), nrhs);
     cx<float> fu{(float)d.u.r, (float)d.u.i}, fl{(float)d.l.r, (float)d.l.i};
+    account(c, 2.0 * n * nrhs * prec_bytes(prec), 6.0 * n * nrhs);
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(k_spin_diag<S>, grid, dim3(kBlock), 0, s, (S *)out, (const S *)in, c->geo.vh, fu,
@@ -239,6 +240,7 @@ void launch_copy_convert(tm_ctx *c, void *out, int out_prec, const void *in, int
 {
     size_t n = half_elems(c);
     dim3 grid(grid_for(n), nrhs);
+    account(c, (double)n * nrhs * (prec_bytes(in_prec) + prec_bytes(out_prec)), dscale ? 2.0 * n * nrhs : 0.0);
     dispatch_prec(out_prec, [&](auto *to) {
         using SO = std::remove_pointer_t<decltype(to)>;
         dispatch_prec(in_prec, [&](auto *ti) {
@@ -254,6 +256,7 @@ void launch_axpby_host(tm_ctx *c, void *y, const void *x, int prec, int nrhs, do
                        hipStream_t s)
 {
     size_t n = half_elems(c) * nrhs;
+    account(c, 3.0 * n * prec_bytes(prec), 6.0 * n);
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(k_axpby<S>, dim3(grid_for(n)), dim3(kBlock), 0, s, (S *)y, (const S *)x, n, a, b);
@@ -285,6 +288,7 @@ static void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *
 void launch_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *dev_out, hipStream_t s)
 {
     int nblk = reduce_blocks(c);
+    account(c, (double)half_elems(c) * nrhs * prec_bytes(prec), 4.0 * half_elems(c) * nrhs);
     double *part = (double *)ws_get(c, "norm_part", sizeof(double) * nblk * nrhs);
     partial_norm2(c, v, prec, nrhs, part, nblk, s);
     hipLaunchKernelGGL(k_finish_sum, dim3(nrhs), dim3(kBlock), 0, s, (const double *)part, nblk, dev_out);
@@ -307,6 +311,7 @@ void cg_finish_beta(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int 
 void launch_zero(tm_ctx *c, void *y, int prec, int nrhs, hipStream_t s)
 {
     size_t n = half_elems(c) * nrhs;
+    account(c, (double)n * prec_bytes(prec), 0.0);
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(k_zero<S>, dim3(grid_for(n)), dim3(kBlock), 0, s, (S *)y, n);
@@ -319,6 +324,7 @@ void launch_axpy_dev(tm_ctx *c, void *y, int yprec, const void *x, int xprec, in
 {
     size_t n = half_elems(c);
     dim3 grid(grid_for(n), nrhs);
+    account(c, (double)n * nrhs * (2 * prec_bytes(yprec) + prec_bytes(xprec)), 4.0 * n * nrhs);
     dispatch_prec(yprec, [&](auto *ty) {
         using SY = std::remove_pointer_t<decltype(ty)>;
         dispatch_prec(xprec, [&](auto *tx) {
@@ -334,6 +340,8 @@ void cg_update_px(tm_ctx *c, void *p, const void *r, void *x, int prec, int xpre
 {
     size_t n = half_elems(c);
     dim3 grid(grid_for(n), nrhs);
+    // reads p, r, x; writes p, x; x += alpha p and p = r + beta p
+    account(c, (double)n * nrhs * (3 * prec_bytes(prec) + 2 * prec_bytes(xprec)), 8.0 * n * nrhs);
     if (prec == TM_F64) {
         TM_REQUIRE(xprec == TM_F64, "FP64 CG needs an FP64 solution vector");
         hipLaunchKernelGGL((k_update_px<double2, double2>), grid, dim3(kBlock), 0, s, (double2 *)p,

@@ -350,7 +350,7 @@ __device__ __forceinline__ void load_spinor(rawc<typename RawT<SS>::L> psi[12], 
     for (int k = 0; k < 12; k++) psi[k] = BufIO<SS>::ldraw(sr, voff, k * vbytes);
 }
 
-// 12-parameter link (sec. IV, link reconstruction): the first two rows in
+// 12-parameter link (appendix A.1, link reconstruction): the first two rows in
 // binary16, [8 directions][6][vh]; the third row of a special unitary matrix
 // is the complex conjugate of the cross product of the first two.  The stored
 // rows carry the time-boundary factor f = +-1, which cancels in the cross
@@ -876,22 +876,23 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
                        dcs[k].epi == m.epi,
                    "multi-instance calls must share precision and operator form");
         TM_REQUIRE(cs[k]->have_gauge, "no gauge field set");
-        TM_REQUIRE(cs[k]->link_recon == cs[0]->link_recon, "multi-instance calls must share the link format");
+        TM_REQUIRE(recon12_ok(cs[k], m.prec) == recon12_ok(cs[0], m.prec),
+                   "multi-instance calls must share the link format");
         if (m.prec == TM_F32) {
-            if (cs[k]->link_recon == 12)
+            if (recon12_ok(cs[k], m.prec))
                 ensure_links12f(cs[k], s);
             else
                 ensure_links32(cs[k], s);
         }
-        if (m.prec == TM_F64 && cs[k]->link_recon == 12) ensure_links12d(cs[k], s);
+        if (m.prec == TM_F64 && recon12_ok(cs[k], m.prec)) ensure_links12d(cs[k], s);
         if (m.prec == TM_F16 || m.prec == TM_BF16) {
-            if (cs[k]->link_recon == 12)
+            if (recon12_ok(cs[k], m.prec))
                 ensure_links12(cs[k], s);
             else
                 ensure_links16(cs[k], s);
         }
     }
-    m.recon12 = cs[0]->link_recon == 12;
+    m.recon12 = recon12_ok(cs[0], m.prec);
     multi_dispatch(m.prec, m.recon12, R,
                    [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs); });
 }
@@ -904,14 +905,50 @@ void multi_dslash_launch(const MultiDslash &m, hipStream_t s)
 
 int dslash_site_blocks(tm_ctx *c) { return (c->geo.vh + kBlock - 1) / kBlock; }
 
+void dslash_cost(tm_ctx *c, const DslashCall &dc, double &bytes, double &flops)
+{
+    const double sites = (double)c->geo.vh, n = dc.nrhs;
+    const double sb = 12.0 * prec_bytes(dc.spinor_prec);  // one half-site spinor
+    // link entries per site (8 directions) and bytes per complex entry
+    double lb;
+    const int par = recon12_ok(c, dc.spinor_prec) && !dc.links18 ? 6 : 9;
+    switch (dc.spinor_prec) {
+    case TM_F64: lb = 16.0 * par; break;
+    case TM_F32: lb = 8.0 * par; break;
+    default: lb = c->half_links_f32 ? 8.0 * 9 : 4.0 * par; break;
+    }
+    double per = 2 * sb;  // input once, output once
+    double fl = 1320 + 72;
+    if (dc.has_own) {
+        per += sb;
+        fl += 96;
+    }
+    if (dc.epi == 1) fl += 48;
+    if (dc.epi == 2) {
+        per += sb;  // r read; the output is r itself (written once)
+        fl += 96;
+        if (dc.rho) {
+            per += 2 * sb;
+            fl += 96;
+        }
+    }
+    bytes = sites * (n * per + 8 * lb);
+    flops = sites * n * fl;
+}
+
 void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 {
     TM_REQUIRE(c->have_gauge, "no gauge field set");
+    {
+        double b, f;
+        dslash_cost(c, dc, b, f);
+        account(c, b, f);
+    }
     switch (dc.spinor_prec) {
     // FP64 (the plain solver and the reliable updates): 12-parameter FP64
     // links in the context's format, the third row rebuilt exactly up to rounding
     case TM_F64:
-        if (c->link_recon == 12) {
+        if (recon12_ok(c, TM_F64) && !dc.links18) {
             ensure_links12d(c, s);
             launch_rhs<double2, L12D, double>(c, dc, s);
         } else {
@@ -919,7 +956,7 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         }
         break;
     case TM_F32:
-        if (c->link_recon == 12) {
+        if (recon12_ok(c, TM_F32)) {
             ensure_links12f(c, s);
             launch_rhs<float2, L12F, float>(c, dc, s);
         } else {
@@ -934,7 +971,7 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         if (c->half_links_f32) {
             ensure_links32(c, s);
             launch_rhs<h2, float2, float>(c, dc, s);
-        } else if (c->link_recon == 12) {
+        } else if (recon12_ok(c, TM_F16)) {
             ensure_links12(c, s);
             launch_rhs<h2, L12, float>(c, dc, s);
         } else {
@@ -946,7 +983,7 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         if (c->half_links_f32) {
             ensure_links32(c, s);
             launch_rhs<b2, float2, float>(c, dc, s);
-        } else if (c->link_recon == 12) {
+        } else if (recon12_ok(c, TM_BF16)) {
             ensure_links12(c, s);
             launch_rhs<b2, L12, float>(c, dc, s);
         } else {

@@ -225,6 +225,8 @@ struct Fg {
 template <typename SV>
 void mdot(Fg &f, const SV *V, size_t vstride, int nb, const double2 *w, double2 *out, int ld, int i0)
 {
+    // both halves: nb basis vectors and w read once, 8 flops per complex product-add
+    account(f.c, 2.0 * f.n * f.nrhs * (nb * sizeof(SV) + sizeof(double2)), 16.0 * f.n * f.nrhs * nb);
     for (int c0 = 0; c0 < nb; c0 += kChunk) {
         const int k = std::min(kChunk, nb - c0);
         hipLaunchKernelGGL(k_mdot<SV>, dim3(kDotBlk, f.nrhs, 2), dim3(kBlock), 0, f.s, V + c0 * vstride, vstride, k,
@@ -240,6 +242,7 @@ template <typename SV>
 void maxpy(Fg &f, double2 *w, const SV *V, size_t vstride, int nb, const double2 *coef, int ld, double sign)
 {
     const int blocks = (int)std::min<size_t>((f.n + kBlock - 1) / kBlock, 2048);
+    account(f.c, 2.0 * f.n * f.nrhs * (nb * sizeof(SV) + 2 * sizeof(double2)), 16.0 * f.n * f.nrhs * nb);
     for (int c0 = 0; c0 < nb; c0 += kChunk) {
         const int k = std::min(kChunk, nb - c0);
         hipLaunchKernelGGL(k_maxpy<SV>, dim3(blocks, f.nrhs, 2), dim3(kBlock), 0, f.s, w, V + c0 * vstride, vstride,

@@ -91,6 +91,53 @@ __global__ __launch_bounds__(kBlock) void k_gauge_ingest(double2 *l0, double2 *l
     }
 }
 
+// Deviation of each link from SU(3): max over entries of |U U^dag - 1| and
+// |det U - 1|; per-block maxima, then one block takes the maximum of those.
+__global__ __launch_bounds__(kBlock) void k_su3_dev(const double2 *U, long nlinks, double *part)
+{
+    const long l = (long)blockIdx.x * kBlock + threadIdx.x;
+    double dev = 0;
+    if (l < nlinks) {
+        cx<double> u[9];
+        for (int k = 0; k < 9; k++) {
+            const double2 v = U[l * 9 + k];
+            u[k] = {v.x, v.y};
+        }
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                cx<double> acc{a == b ? -1.0 : 0.0, 0.0};
+                for (int k = 0; k < 3; k++) cmac(acc, u[3 * a + k], conjg(u[3 * b + k]));
+                dev = fmax(dev, fmax(fabs(acc.r), fabs(acc.i)));
+            }
+        const cx<double> det = u[0] * (u[4] * u[8] - u[5] * u[7]) - u[1] * (u[3] * u[8] - u[5] * u[6]) +
+                               u[2] * (u[3] * u[7] - u[4] * u[6]);
+        dev = fmax(dev, fmax(fabs(det.r - 1.0), fabs(det.i)));
+        if (dev != dev) dev = INFINITY;  // NaN entries count as far off
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = dev;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_finish(const double *part, long n, double *out)
+{
+    double m = 0;
+    for (long k = threadIdx.x; k < n; k += kBlock) m = fmax(m, part[k]);
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // out[d][k][i] = binary16(in[d][k][i]) for the first two rows (k < 6) of
 // every link, d < 8, i < vh
 __global__ __launch_bounds__(kBlock) void k_d2h_rows(h2 *out, const double2 *in, long vh)
@@ -280,6 +327,7 @@ void launch_pack(tm_ctx *c, void *even, void *odd, const double *full, int nrhs,
                  const double *dscale, hipStream_t s)
 {
     dim3 grid((unsigned)((c->V + kBlock - 1) / kBlock), nrhs);
+    account(c, (double)c->V * 12 * nrhs * (16 + prec_bytes(prec)), 0.0);
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(k_pack<S>, grid, dim3(kBlock), 0, s, (S *)even, (S *)odd, (const double2 *)full,
@@ -292,6 +340,7 @@ void launch_unpack(tm_ctx *c, double *full, const void *even, const void *odd, i
                    hipStream_t s)
 {
     dim3 grid((unsigned)((c->V + kBlock - 1) / kBlock), nrhs);
+    account(c, (double)c->V * 12 * nrhs * (16 + prec_bytes(prec)), 0.0);
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(k_unpack<S>, grid, dim3(kBlock), 0, s, (double2 *)full, (const S *)even,
@@ -306,6 +355,21 @@ void launch_gauge_ingest(tm_ctx *c, const double *U, hipStream_t s)
     hipLaunchKernelGGL(k_gauge_ingest, grid, dim3(kBlock), 0, s, (double2 *)c->links64[0],
                        (double2 *)c->links64[1], (const double2 *)U, c->geo, c->V, c->t_bc);
     TM_HIP(hipGetLastError());
+}
+
+double gauge_su3_deviation(tm_ctx *c, const double *U, hipStream_t s)
+{
+    const long nl = 4 * c->V;
+    const long nb = (nl + kBlock - 1) / kBlock;
+    double *part = (double *)ws_get(c, "su3_part", sizeof(double) * (nb + 1));
+    hipLaunchKernelGGL(k_su3_dev, dim3((unsigned)nb), dim3(kBlock), 0, s, (const double2 *)U, nl, part + 1);
+    TM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_max_finish, dim3(1), dim3(kBlock), 0, s, (const double *)(part + 1), nb, part);
+    TM_HIP(hipGetLastError());
+    double dev = 0;
+    TM_HIP(hipMemcpyAsync(&dev, part, sizeof(double), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    return dev;
 }
 
 void launch_links_to_f32(tm_ctx *c, hipStream_t s)

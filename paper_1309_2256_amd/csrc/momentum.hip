@@ -1,8 +1,8 @@
-// Momentum projection of the loops (sec. III, contraction kernels and the
-// Fourier step): the colour-traced Dirac outer products are formed per site,
+// Momentum projection of the loops (appendix A.2, contraction kernels, and
+// the Fourier step of appendix A.3): the colour-traced Dirac outer products are formed per site,
 // C(x)[b][a] = sum_r sum_c v_{r,bc}(x) w*_{r,ac}(x) for ultra-local
 // insertions, and for the one-derivative insertions (the covariant-derivative
-// kernel of sec. III) in each direction mu
+// kernel of appendix A.2) in each direction mu
 //   D_mu(x)[b][a] = 1/4 sum_r sum_c [(nabla_mu v)_{bc} w*_{ac} - v_{bc} (nabla_mu w)*_{ac}],
 //   nabla_mu f(x) = U_mu(x) f(x + mu) - U_mu(x - mu)^dag f(x - mu)
 // (the symmetric left-right derivative of the bilinear w^dag Gamma D_mu v

@@ -25,10 +25,12 @@ void ptc_apply_halves(tm_ctx *c, const void *in_e, const void *in_o, void *out_e
 
 // out = D_hop Hop[in] (+ D_own own) on output parity out_par (see DslashCall)
 void op_dslash(tm_ctx *c, void *out, const void *in, const void *own, int nrhs, int prec, int out_par,
-               int dag, SpinDiag dhop, SpinDiag down, hipStream_t s);
+               int dag, SpinDiag dhop, SpinDiag down, hipStream_t s, bool links18 = false);
 
 // half-layout operators; tmp is an odd-parity scratch field of nrhs in prec
-void op_schur(tm_ctx *c, void *out, const void *in, void *tmp, int nrhs, int prec, double epsp, hipStream_t s);
+// (links18: FP64 with all 18 link parameters, the exact operator)
+void op_schur(tm_ctx *c, void *out, const void *in, void *tmp, int nrhs, int prec, double epsp, hipStream_t s,
+              bool links18 = false);
 void op_schur_dag(tm_ctx *c, void *out, const void *in, void *tmp, int nrhs, int prec, double epsp,
                   hipStream_t s);
 // (B H)^k on a full field given as halves (ping-pong in place), FP64
@@ -73,13 +75,18 @@ struct Solver {
     void iteration(hipStream_t s);       // one iteration, single-instance launches
     DslashCall stage(int k) const;       // the k-th (1..4) half-Dslash of an iteration
     void iteration_tail(hipStream_t s);  // finish_beta + x/p update
+    // algorithmic bytes and flops of one iteration (the four half-Dslash
+    // stages and the x/p update), as accounted by single-instance launches
+    void iter_cost(double &bytes, double &flops) const;
     void count_iteration();
     bool due() const;
     void check(hipStream_t s);
     SolveOut finalize(hipStream_t s);
 
   private:
-    void restart(bool first, hipStream_t s);
+    // reactivate: right-hand sides whose true residual is above tol iterate
+    // again (truncated solves); otherwise activity is kept
+    void restart(bool first, hipStream_t s, bool reactivate = false);
     void accumulate(hipStream_t s);
 };
 

@@ -83,9 +83,10 @@ hipStream_t s_of(tm_ctx *c) { return c->stream; }
 double eps_of(tm_ctx *c, int mu_sign) { return mu_sign >= 0 ? c->eps : -c->eps; }
 
 void op_dslash(tm_ctx *c, void *out, const void *in, const void *own, int nrhs, int prec, int out_par, int dag,
-               SpinDiag dhop, SpinDiag down, hipStream_t s)
+               SpinDiag dhop, SpinDiag down, hipStream_t s, bool links18)
 {
     DslashCall dc{};
+    dc.links18 = links18;
     dc.out = out;
     dc.in = in;
     dc.own = own;
@@ -100,11 +101,13 @@ void op_dslash(tm_ctx *c, void *out, const void *in, const void *own, int nrhs, 
 }
 
 // Ahat x = R x - H_eo R^-1 H_oe x, with H = -kappa Hop
-void op_schur(tm_ctx *c, void *out, const void *in, void *tmp, int nrhs, int prec, double epsp, hipStream_t s)
+void op_schur(tm_ctx *c, void *out, const void *in, void *tmp, int nrhs, int prec, double epsp, hipStream_t s,
+              bool links18)
 {
     const double k = c->kappa;
-    op_dslash(c, tmp, in, nullptr, nrhs, prec, 1, 0, sd_mul(sd_scalar(-k), sd_twist_inv(epsp)), sd_scalar(0), s);
-    op_dslash(c, out, tmp, in, nrhs, prec, 0, 0, sd_scalar(k), sd_twist(epsp), s);
+    op_dslash(c, tmp, in, nullptr, nrhs, prec, 1, 0, sd_mul(sd_scalar(-k), sd_twist_inv(epsp)), sd_scalar(0), s,
+              links18);
+    op_dslash(c, out, tmp, in, nrhs, prec, 0, 0, sd_scalar(k), sd_twist(epsp), s, links18);
 }
 
 // Ahat^dag x = gamma5 Ahat(-eps) gamma5 x
@@ -235,7 +238,7 @@ void Solver::init(tm_ctx *ctx, void *xe_, void *xo_, const void *be_, const void
 
     // bhat_e = b_e - H_eo R_oo^-1 b_o
     launch_spin_diag(c, t64, bo, TM_F64, nrhs, sd_twist_inv(epsp), s);
-    op_dslash(c, bh, t64, be, nrhs, TM_F64, 0, 0, sd_scalar(c->kappa), sd_scalar(1.0), s);
+    op_dslash(c, bh, t64, be, nrhs, TM_F64, 0, 0, sd_scalar(c->kappa), sd_scalar(1.0), s, true);
 
     hsc.assign(nrhs, CGScalars{});
     n_rel.assign(nrhs, 0);
@@ -296,7 +299,7 @@ void Solver::init(tm_ctx *ctx, void *xe_, void *xo_, const void *be_, const void
 
 // (re)start the low-precision iteration from the FP64 residual rho64:
 // r = Ahat^dag rho, new per-RHS scales, p rescaled (kept otherwise)
-void Solver::restart(bool first, hipStream_t s)
+void Solver::restart(bool first, hipStream_t s, bool reactivate)
 {
     const double nel = 12.0 * c->geo.vh;
     const size_t fl = field_bytes(c, lp, nrhs);
@@ -353,6 +356,7 @@ void Solver::restart(bool first, hipStream_t s)
         q.target2 = p.tol * p.tol * bn2[r] * sig_new[r] * sig_new[r];
         q.sigma = sig_new[r];
         q.want_update = 0;
+        if (reactivate) q.active = 1;
         if (nrho[r] <= p.tol * p.tol * bn2[r]) q.active = 0;  // converged on the true FP64 residual
         iter_res[r] = std::sqrt(nrho[r] / bn2[r]);
     }
@@ -387,6 +391,20 @@ void Solver::iteration(hipStream_t s)
 
 DslashCall Solver::stage(int k) const { return stage_call(c, w, epsp, k); }
 
+void Solver::iter_cost(double &bytes, double &flops) const
+{
+    bytes = flops = 0;
+    for (int k = 1; k <= 4; k++) {
+        double b, f;
+        dslash_cost(c, stage(k), b, f);
+        bytes += b;
+        flops += f;
+    }
+    const double n = 12.0 * c->geo.vh * nrhs;
+    bytes += n * (3 * prec_bytes(w.prec) + 2 * prec_bytes(w.xprec));
+    flops += 8.0 * n;
+}
+
 void Solver::count_iteration()
 {
     total++;
@@ -415,16 +433,34 @@ void Solver::check(hipStream_t s)
     }
     if (p.solver == TM_CG_LOW) {
         if (!any_active || out_of_iters) {
-            accumulate(s);
             for (int r = 0; r < nrhs; r++) iter_res[r] = std::sqrt(hsc[r].rho2 / bn2[r]) / hsc[r].sigma;
+            accumulate(s);
             done = true;
+            if (out_of_iters) return;
+            // the truncation criterion holds for the true residual: the FP64
+            // Schur residual of the accumulated solution (equal to the
+            // full-system residual after odd reconstruction); right-hand
+            // sides still above tol continue from it, as after a reliable
+            // update
+            op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s, true);
+            copy_field(rho64, bh, field_bytes(c, TM_F64, nrhs), s);
+            launch_axpby_host(c, rho64, q64, TM_F64, nrhs, -1.0, 1.0, s);
+            std::vector<double> nrho = norms_host(c, rho64, TM_F64, nrhs, s);
+            bool again = false;
+            for (int r = 0; r < nrhs; r++) again |= nrho[r] > p.tol * p.tol * bn2[r];
+            if (again) {
+                restart(false, s, true);
+                bool any = false;
+                for (auto &q : hsc) any |= q.active != 0;
+                done = !any;
+            }
         }
         return;
     }
     if (!any_update && !out_of_iters) return;
     // reliable update: FP64 true residual of the accumulated solution
     accumulate(s);
-    op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s);
+    op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s, true);
     copy_field(rho64, bh, field_bytes(c, TM_F64, nrhs), s);
     launch_axpby_host(c, rho64, q64, TM_F64, nrhs, -1.0, 1.0, s);
     for (int r = 0; r < nrhs; r++)
@@ -439,11 +475,12 @@ SolveOut Solver::finalize(hipStream_t s)
 {
     const double kap = c->kappa;
     // odd reconstruction psi_o = R^-1 (b_o - H_oe psi_e)
-    op_dslash(c, xo, xe, bo, nrhs, TM_F64, 1, 0, sd_mul(sd_scalar(kap), sd_twist_inv(epsp)), sd_twist_inv(epsp), s);
-    // true residual b - M x, both parities
-    op_dslash(c, rho64, xo, xe, nrhs, TM_F64, 0, 0, sd_scalar(-kap), sd_twist(epsp), s);
+    op_dslash(c, xo, xe, bo, nrhs, TM_F64, 1, 0, sd_mul(sd_scalar(kap), sd_twist_inv(epsp)), sd_twist_inv(epsp), s,
+              true);
+    // true residual b - M x, both parities, with the exact (18-parameter) links
+    op_dslash(c, rho64, xo, xe, nrhs, TM_F64, 0, 0, sd_scalar(-kap), sd_twist(epsp), s, true);
     launch_axpby_host(c, rho64, be, TM_F64, nrhs, -1.0, 1.0, s);
-    op_dslash(c, t64, xe, xo, nrhs, TM_F64, 1, 0, sd_scalar(-kap), sd_twist(epsp), s);
+    op_dslash(c, t64, xe, xo, nrhs, TM_F64, 1, 0, sd_scalar(-kap), sd_twist(epsp), s, true);
     launch_axpby_host(c, t64, bo, TM_F64, nrhs, -1.0, 1.0, s);
     std::vector<double> re = norms_host(c, rho64, TM_F64, nrhs, s);
     std::vector<double> ro = norms_host(c, t64, TM_F64, nrhs, s);

@@ -273,6 +273,11 @@ struct tm_ctx {
     // parameters (12 reads a third fewer link bytes; measured no slower at 12
     // RHS and 9-24% faster at 1-4 RHS per call)
     int link_recon = 12;
+    // largest deviation of the gauge field from SU(3) measured at ingest,
+    // max over links of max(|U U^dag - 1|, |det U - 1|) entrywise; the
+    // 12-parameter format of a precision is used only while this stays
+    // below that precision's rounding scale (recon12_ok)
+    double su3_dev = 0;
     // FP16/BF16-spinor Dslash launches read the FP32 links instead of the
     // binary16 copy (set by tm_dslash for link_prec = TM_F32)
     bool half_links_f32 = false;
@@ -289,7 +294,30 @@ struct tm_ctx {
     int ptc_nc = 0;
     long ptc_step = 0;
     int ptc_cap = 0, ptc_n = 0, ptc_store = TM_F32;
+    // algorithmic work of the kernels launched on this context so far
+    // (compulsory device-memory bytes and flops by the conventions of tm.h);
+    // acct_pause > 0 while launches are recorded into a graph that is
+    // accounted per replay instead
+    double acct_bytes = 0, acct_flops = 0;
+    int acct_pause = 0;
 };
+
+// 12-parameter links for kernels of spinor precision prec: the format asks
+// for them and the links are special unitary to that precision's rounding
+// (the third row is rebuilt from the first two assuming U in SU(3))
+inline bool recon12_ok(const tm_ctx *c, int prec)
+{
+    if (c->link_recon != 12) return false;
+    const double lim = prec == TM_F64 ? 1e-12 : prec == TM_F32 ? 1e-6 : 1e-3;
+    return c->su3_dev <= lim;
+}
+
+inline void account(tm_ctx *c, double bytes, double flops)
+{
+    if (c->acct_pause) return;
+    c->acct_bytes += bytes;
+    c->acct_flops += flops;
+}
 
 void *ws_get(tm_ctx *c, const std::string &name, size_t bytes);
 void *host_stage(tm_ctx *c, size_t bytes);
@@ -340,10 +368,18 @@ struct DslashCall {
     void *r = nullptr, *rho = nullptr;
     const struct CGScalars *sc = nullptr;
     double *part = nullptr;  // [quantity][nrhs][dslash_site_blocks]
+    // FP64 only: read all 18 parameters of the FP64 links whatever the
+    // format (the exact operator for reliable updates and true residuals)
+    bool links18 = false;
 };
 
 void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s);
 int dslash_site_blocks(tm_ctx *c);
+// algorithmic bytes (each field and link read once, each output written
+// once) and flops (1320 per site and RHS for the hopping term, 72 for its
+// spin-diagonal coefficient, 96 for the own-site term, 48 per fused norm or
+// update) of one launch of dc on this context's link format
+void dslash_cost(tm_ctx *c, const DslashCall &dc, double &bytes, double &flops);
 
 // One launch over several contexts (lattices), one DslashCall each; all
 // share precision and operator form; R right-hand sides per thread divides
@@ -409,6 +445,9 @@ void launch_pack(tm_ctx *c, void *even, void *odd, const double *full, int nrhs,
 void launch_unpack(tm_ctx *c, double *full, const void *even, const void *odd, int nrhs, int prec,
                    hipStream_t s);
 void launch_gauge_ingest(tm_ctx *c, const double *U, hipStream_t s);
+// max over the 4V links of the canonical field U (device) of
+// max(|U U^dag - 1|, |det U - 1|) entrywise; synchronises s
+double gauge_su3_deviation(tm_ctx *c, const double *U, hipStream_t s);
 void launch_links_to_f32(tm_ctx *c, hipStream_t s);
 void launch_links_to_f16(tm_ctx *c, hipStream_t s);
 // first two rows of every link, rounded once to binary16: [8][6][vh] per parity

@@ -1,4 +1,4 @@
-"""Base-2 accumulation storage of per-source loop results (sec. IV, binary
+"""Base-2 accumulation storage of per-source loop results (appendix A.4, binary
 storage system, fig. St).
 
 Stochastic estimates are averages over sources, so the individual per-source

@@ -36,7 +36,7 @@ def test_binding_struct_sizes_match_header():
     import paper_1309_2256_amd as P
     assert ctypes.sizeof(P.tm_lattice) == 4 * 4 + 8 + 8 + 4 + 4  # padded to 8
     assert ctypes.sizeof(P.tm_solve_params) == 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4
-    assert ctypes.sizeof(P.tm_solve_stats) == 4 * 4 + 3 * 8
+    assert ctypes.sizeof(P.tm_solve_stats) == 4 * 4 + 5 * 8
     assert ctypes.sizeof(P.tm_loop_params) == 8 + 8 * 4 + 2 * ctypes.sizeof(P.tm_solve_params)
 
 
@@ -47,6 +47,23 @@ def test_create_rejects_bad_lattices(L):
     h = ctypes.c_void_p()
     assert P.tm_create(ctypes.byref(h), ctypes.byref(lat), 0) == P.TM_ERR_ARG
     assert not h.value
+
+
+@pytest.mark.parametrize("L,ok", [((64, 64, 64, 128), False), ((48, 48, 48, 96), True)])
+def test_create_guards_32bit_field_offsets(L, ok):
+    """A geometry whose FP64 half field of one right-hand side exceeds 2^31 - 1
+    bytes is refused before any device call (the kernels use 32-bit byte
+    offsets); one that fits passes the guard (and then needs a device)."""
+    import paper_1309_2256_amd as P
+    lat = P.tm_lattice((ctypes.c_int * 4)(*L), 0.124, 0.01, -1)
+    h = ctypes.c_void_p()
+    st = P.tm_create(ctypes.byref(h), ctypes.byref(lat), 0)
+    if ok:
+        assert st != P.TM_ERR_UNSUPPORTED
+        if st == P.TM_OK:
+            P.tm_destroy(h)
+    else:
+        assert st == P.TM_ERR_UNSUPPORTED and not h.value
 
 
 def test_create_rejects_bad_bc_and_nulls():

@@ -1,5 +1,5 @@
 """Generalised one-end estimator (eq. loopStD) and one-derivative insertions
-(the covariant-derivative contraction of sec. III) on the device against the
+(the covariant-derivative contraction of appendix A.2) on the device against the
 oracle, per time slice and momentum resolved."""
 import numpy as np
 import pytest

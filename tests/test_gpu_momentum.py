@@ -1,6 +1,6 @@
 """Momentum-projected loops on the device against the oracle: the Fourier
 sum over each time slice of the loop density, for every momentum with
-|n|^2 <= p2max (sec. III, the Fourier step after the contraction)."""
+|n|^2 <= p2max (appendix A.3, the Fourier step after the contraction of appendix A.2)."""
 import numpy as np
 import pytest
 

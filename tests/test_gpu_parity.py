@@ -392,6 +392,57 @@ def test_solve_truncated_low_precision(prec):
     assert res < 3e-2
 
 
+@pytest.mark.parametrize("solver", [P.TM_CG_F64, P.TM_CG_MIXED])
+def test_solve_links_off_su3(solver):
+    """Links perturbed off SU(3) by ~1e-7 (as a field stored in single
+    precision would be): the FP64 kernels fall back to all 18 parameters and
+    the reported true residual is the oracle's residual for that very field;
+    the solve converges to it."""
+    L, kappa, eps = (4, 4, 4, 8), 0.124, 0.01
+    U = S.gauge_links(L, 0.3, 34)
+    rng = np.random.default_rng(35)
+    U = U + 1e-7 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+    ctx = P.Context(L, kappa, eps)
+    ctx.set_gauge(cuda(U))
+    b = S.random_spinor(L, 36, 1)
+    x = torch.zeros_like(cuda(b))
+    st, stats = ctx.solve(x, cuda(b), 1, P.solve_params(tol=1e-10, solver=solver,
+                                                        inner_prec=P.TM_F16))
+    res = oracle_residual(L, kappa, eps, U, host(x)[0], b[0])
+    assert res <= 1e-10 and stats[0].converged == 1
+    assert abs(stats[0].true_rel_res - res) <= 1e-3 * res
+    # the FP64 Schur operator itself is the oracle's for the perturbed field
+    v = S.random_spinor(L, 37, 1)
+    e, o = half_buf(ctx, P.TM_F64, 1), half_buf(ctx, P.TM_F64, 1)
+    ctx.pack(e, o, cuda(v), 1, P.TM_F64)
+    out = half_buf(ctx, P.TM_F64, 1)
+    ctx.dslash(out, e, 1, P.TM_SCHUR, 1, P.TM_F64)
+    full = torch.zeros_like(cuda(v))
+    ctx.unpack(full, out, half_buf(ctx, P.TM_F64, 1), 1, P.TM_F64)
+    ref = O.schur(L, kappa, eps, -1, U, v[0])
+    par = O.site_parity(L)
+    assert rel(host(full)[0][par == 0], ref[par == 0]) < 1e-13
+
+
+def test_solve_stats_count_work():
+    """tm_solve_stats.bytes / flops: per right-hand side, at least the four
+    half-Dslash launches of every CG iteration (1392 flops per site and RHS
+    each, input + output + links) and within a small factor of that."""
+    cfg = S.CONFIGS["c1"]
+    L, kappa, eps = cfg["L"], cfg["kappa"], cfg["two_kappa_mu"]
+    ctx, U = make_ctx(L, kappa, eps, cfg["seed"], cfg["eps_links"])
+    vh = int(np.prod(L)) // 2
+    for nrhs in (1, 3):
+        b = S.random_spinor(L, 38, nrhs)
+        x = torch.zeros_like(cuda(b))
+        _, stats = ctx.solve(x, cuda(b), nrhs, P.solve_params(tol=1e-10))
+        it = stats[0].iters
+        lo_f = 4 * it * vh * 1392
+        lo_b = 4 * it * vh * (2 * 192 + 8 * 6 * 16 / nrhs)
+        assert lo_f <= stats[0].flops <= 2.0 * lo_f, (stats[0].flops, lo_f)
+        assert lo_b <= stats[0].bytes <= 3.0 * lo_b, (stats[0].bytes, lo_b)
+
+
 def test_solve_failure_paths():
     L = (4, 4, 4, 8)
     ctx, U = make_ctx(L, 0.124, 0.01, 33)
@@ -523,6 +574,28 @@ def c3():
     ctx.close()
 
 
+def boundary_sample(L, even, rng, n):
+    """n even sites: random ones plus sites on every face of the lattice
+    (t = 0 and t = Lt - 1, where the hops cross the time boundary, and x, y,
+    z = 0 and L - 1), so that every wrap-around of both hops is exercised."""
+    V = int(np.prod(L))
+    s = np.arange(V)
+    c = [s % L[0], (s // L[0]) % L[1], (s // (L[0] * L[1])) % L[2], s // (L[0] * L[1] * L[2])]
+    par_even = np.zeros(V, dtype=bool)
+    par_even[even] = True
+    faces = []
+    for mu in (3, 0, 1, 2):
+        for v in (0, L[mu] - 1):
+            cand = np.where(par_even & (c[mu] == v))[0]
+            faces.extend(rng.choice(cand, 4, replace=False))
+    rest = np.setdiff1d(even, faces)
+    pick = np.concatenate([faces, rng.choice(rest, n - len(faces), replace=False)])
+    pick = np.sort(pick)
+    t = pick // (L[0] * L[1] * L[2])
+    assert (t == 0).any() and (t == L[3] - 1).any()
+    return pick
+
+
 def test_c3_schur_sampled_sites(c3):
     """32^3 x 64: the FP64 1-RHS and the 12-RHS FP16-storage Schur operator
     (the benchmarked launch) at 96 sampled even sites against the oracle
@@ -532,8 +605,7 @@ def test_c3_schur_sampled_sites(c3):
     rng = np.random.default_rng(5)
     par = O.site_parity(L)
     even = np.where(par == 0)[0]
-    sites = np.sort(rng.choice(even, 96, replace=False))
-    sites[:2] = [0, even[-1]]  # corners
+    sites = boundary_sample(L, even, rng, 96)
     nrhs = 12
     v = (rng.standard_normal((nrhs, V, 4, 3)) + 1j * rng.standard_normal((nrhs, V, 4, 3)))
     dv = cuda(v)

@@ -1,4 +1,4 @@
-"""Base-2 accumulation storage (sec. IV, binary storage system, fig. St):
+"""Base-2 accumulation storage (appendix A.4, binary storage system, fig. St):
 rebuilt estimates are plain means over the source subsets the binary digits
 of n select."""
 import numpy as np
