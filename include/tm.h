@@ -146,6 +146,24 @@ typedef enum {
 int tm_dslash(tm_ctx *ctx, void *out, const void *in, int nrhs, int kind, int mu_sign,
               int spinor_prec, int link_prec, tm_stream stream);
 
+/* tm_dslash without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, operator and results as tm_dslash (the same
+ * kernels; the right-hand-side tile is the tuned one when tm_dslash already
+ * tuned this case, else the default, bit-identical either way).  The
+ * intermediate fields of TM_SCHUR, TM_SCHUR_DAG (one half field of nrhs in
+ * spinor_prec), TM_NORMAL (two) and TM_FULL/TM_FULL_DAG (four FP64 half
+ * fields), each rounded up to 256 bytes, come from one 64 MiB device array
+ * per device that the library holds until the process ends; larger requests
+ * return TM_ERR_UNSUPPORTED before anything is launched.  The link copy the
+ * call reads must already exist (built by an earlier allocating call with the
+ * same precisions, e.g. tm_dslash); otherwise TM_ERR_UNSUPPORTED.  Calls on
+ * one device share the array: calls that overlap in time on that device
+ * (other streams, other contexts, other host threads) race and must be
+ * serialised by the caller.  Enqueued on `stream`; does not synchronise. */
+int tm_dslash_noalloc(tm_ctx *ctx, void *out, const void *in, int nrhs, int kind, int mu_sign,
+                      int spinor_prec, int link_prec, tm_stream stream);
+
 /* Canonical full FP64 spinors [nrhs][V][4][3] -> two half-layout fields
  * (even, odd) in precision `prec`, each element multiplied by scale[r]
  * (scale may be NULL = 1).  Conversions round to nearest even. */

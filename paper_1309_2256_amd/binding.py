@@ -88,6 +88,8 @@ _SIGS = {
     "tm_set_gauge": (ctypes.c_int, [_vp, _vp, _vp]),
     "tm_dslash": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, _vp]),
+    "tm_dslash_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, _vp]),
     "tm_set_link_format": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tm_pack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _dp, _vp]),
     "tm_unpack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
@@ -200,6 +202,13 @@ class Context:
             link_prec = {TM_F64: TM_F64, TM_F32: TM_F32}.get(spinor_prec, TM_F16)
         self._check(tm_dslash(self.h, _ptr(out), _ptr(inp), nrhs, kind, mu_sign, spinor_prec,
                               link_prec, _stream(stream)))
+
+    def dslash_noalloc(self, out, inp, nrhs, kind, mu_sign=1, spinor_prec=TM_F64, link_prec=None,
+                       stream=None):
+        if link_prec is None:
+            link_prec = {TM_F64: TM_F64, TM_F32: TM_F32}.get(spinor_prec, TM_F16)
+        self._check(tm_dslash_noalloc(self.h, _ptr(out), _ptr(inp), nrhs, kind, mu_sign,
+                                      spinor_prec, link_prec, _stream(stream)))
 
     def pack(self, even, odd, full, nrhs, prec, scale=None, stream=None):
         sc = None

@@ -12,6 +12,13 @@
 
 void *ws_get(tm_ctx *c, const std::string &name, size_t bytes)
 {
+    if (c->no_alloc) {
+        auto it = c->ws.find(name);
+        if (it != c->ws.end() && it->second.p && it->second.bytes >= bytes) return it->second.p;
+        throw TmError{TM_ERR_UNSUPPORTED, "the allocation-free call would allocate " + std::to_string(bytes) +
+                                              " bytes of device memory (" + name +
+                                              "); one allocating call with the same precisions builds it"};
+    }
     DevBuf &b = c->ws[name];
     if (b.p && b.bytes >= bytes) return b.p;
     if (b.p) {
@@ -135,6 +142,8 @@ extern "C" int tm_create(tm_ctx **out, const tm_lattice *lat, int device)
     if (lat->t_bc != 1 && lat->t_bc != -1) return TM_ERR_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TM_ERR_HIP;
+    // device address of the allocation-free entry points' scratch (once per device)
+    if (noalloc_setup(device) != TM_OK) return TM_ERR_HIP;
     tm_ctx *c = new (std::nothrow) tm_ctx();
     if (!c) return TM_ERR_OOM;
     c->device = device;
@@ -202,71 +211,111 @@ extern "C" int tm_set_link_format(tm_ctx *c, int params)
     });
 }
 
+namespace {
+
+// Body of tm_dslash and tm_dslash_noalloc.  tmp(name, bytes) supplies the
+// intermediate half fields; every one is requested before the first launch,
+// so a request that cannot be met fails before anything is enqueued.
+template <typename Tmp>
+int dslash_body(tm_ctx *c, void *out, const void *in, int nrhs, int kind, int mu_sign, int spinor_prec,
+                int link_prec, tm_stream stream, Tmp &&tmp)
+{
+    TM_REQUIRE(out && in && out != in, "out and in must be distinct non-null pointers");
+    TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
+    TM_REQUIRE(valid_prec(spinor_prec), "bad spinor precision");
+    TM_REQUIRE(c->have_gauge, "no gauge field set");
+    if (spinor_prec == TM_F64)
+        TM_REQUIRE(link_prec == TM_F64, "FP64 spinors need FP64 links");
+    else if (spinor_prec == TM_F32)
+        TM_REQUIRE(link_prec == TM_F32, "FP32 spinors use FP32 links");
+    else
+        TM_REQUIRE(link_prec == TM_F32 || link_prec == TM_F16, "FP16/BF16 spinors use FP16 or FP32 links");
+    // the link copy for this call only (solvers use the binary16 copy)
+    struct LinkChoice {
+        tm_ctx *c;
+        ~LinkChoice() { c->half_links_f32 = false; }
+    } restore{c};
+    c->half_links_f32 = link_prec == TM_F32;
+    hipStream_t s = hs(stream);
+    const double epsp = eps_of(c, mu_sign), k = c->kappa;
+    switch (kind) {
+    case TM_HOP_EO:
+    case TM_HOP_OE:
+        op_dslash(c, out, in, nullptr, nrhs, spinor_prec, kind == TM_HOP_OE, 0, sd_scalar(-k), sd_scalar(0), s);
+        break;
+    case TM_RINV_HOP_OE:
+    case TM_RINV_HOP_EO:
+        op_dslash(c, out, in, nullptr, nrhs, spinor_prec, kind == TM_RINV_HOP_OE, 0,
+                  sd_mul(sd_scalar(-k), sd_twist_inv(epsp)), sd_scalar(0), s);
+        break;
+    case TM_SCHUR:
+        op_schur(c, out, in, tmp("d_tmp", half_bytes(c, spinor_prec, nrhs)), nrhs, spinor_prec, epsp, s);
+        break;
+    case TM_SCHUR_DAG:
+        op_schur_dag(c, out, in, tmp("d_tmp", half_bytes(c, spinor_prec, nrhs)), nrhs, spinor_prec, epsp, s);
+        break;
+    case TM_NORMAL: {
+        void *t = tmp("d_tmp", half_bytes(c, spinor_prec, nrhs));
+        void *mid = tmp("d_mid", half_bytes(c, spinor_prec, nrhs));
+        op_schur(c, mid, in, t, nrhs, spinor_prec, epsp, s);
+        op_schur_dag(c, out, mid, t, nrhs, spinor_prec, epsp, s);
+        break;
+    }
+    case TM_FULL:
+    case TM_FULL_DAG: {
+        TM_REQUIRE(spinor_prec == TM_F64, "full-lattice kinds take canonical FP64 spinors");
+        const size_t b = half_bytes(c, TM_F64, nrhs);
+        void *ie = tmp("d_ie", b), *io = tmp("d_io", b);
+        void *oe = tmp("d_oe", b), *oo = tmp("d_oo", b);
+        launch_pack(c, ie, io, (const double *)in, nrhs, TM_F64, nullptr, s);
+        const int dag = kind == TM_FULL_DAG;
+        // M = R(eps) + H;  M^dag = R(-eps) + H^dag
+        const SpinDiag tw = sd_twist(dag ? -epsp : epsp);
+        op_dslash(c, oe, io, ie, nrhs, TM_F64, 0, dag, sd_scalar(-k), tw, s);
+        op_dslash(c, oo, ie, io, nrhs, TM_F64, 1, dag, sd_scalar(-k), tw, s);
+        launch_unpack(c, (double *)out, oe, oo, nrhs, TM_F64, s);
+        break;
+    }
+    default: throw TmError{TM_ERR_ARG, "unknown dslash kind"};
+    }
+    return TM_OK;
+}
+
+}  // namespace
+
 extern "C" int tm_dslash(tm_ctx *c, void *out, const void *in, int nrhs, int kind, int mu_sign, int spinor_prec,
                          int link_prec, tm_stream stream)
 {
     return guarded(c, [&]() {
-        TM_REQUIRE(out && in && out != in, "out and in must be distinct non-null pointers");
-        TM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
-        TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
-        TM_REQUIRE(valid_prec(spinor_prec), "bad spinor precision");
-        TM_REQUIRE(c->have_gauge, "no gauge field set");
-        if (spinor_prec == TM_F64)
-            TM_REQUIRE(link_prec == TM_F64, "FP64 spinors need FP64 links");
-        else if (spinor_prec == TM_F32)
-            TM_REQUIRE(link_prec == TM_F32, "FP32 spinors use FP32 links");
-        else
-            TM_REQUIRE(link_prec == TM_F32 || link_prec == TM_F16, "FP16/BF16 spinors use FP16 or FP32 links");
-        // the link copy for this call only (solvers use the binary16 copy)
-        struct LinkChoice {
+        return dslash_body(c, out, in, nrhs, kind, mu_sign, spinor_prec, link_prec, stream,
+                           [&](const char *name, size_t bytes) { return ws_get(c, name, bytes); });
+    });
+}
+
+extern "C" int tm_dslash_noalloc(tm_ctx *c, void *out, const void *in, int nrhs, int kind, int mu_sign,
+                                 int spinor_prec, int link_prec, tm_stream stream)
+{
+    return guarded(c, [&]() {
+        char *base = (char *)noalloc_scratch(c->device);
+        if (!base) throw TmError{TM_ERR_HIP, "device scratch not set up for this device"};
+        struct NoAlloc {
             tm_ctx *c;
-            ~LinkChoice() { c->half_links_f32 = false; }
-        } restore{c};
-        c->half_links_f32 = link_prec == TM_F32;
-        hipStream_t s = hs(stream);
-        const double epsp = eps_of(c, mu_sign), k = c->kappa;
-        switch (kind) {
-        case TM_HOP_EO:
-        case TM_HOP_OE:
-            op_dslash(c, out, in, nullptr, nrhs, spinor_prec, kind == TM_HOP_OE, 0, sd_scalar(-k), sd_scalar(0), s);
-            break;
-        case TM_RINV_HOP_OE:
-        case TM_RINV_HOP_EO:
-            op_dslash(c, out, in, nullptr, nrhs, spinor_prec, kind == TM_RINV_HOP_OE, 0,
-                      sd_mul(sd_scalar(-k), sd_twist_inv(epsp)), sd_scalar(0), s);
-            break;
-        case TM_SCHUR:
-            op_schur(c, out, in, ws_get(c, "d_tmp", half_bytes(c, spinor_prec, nrhs)), nrhs, spinor_prec, epsp, s);
-            break;
-        case TM_SCHUR_DAG:
-            op_schur_dag(c, out, in, ws_get(c, "d_tmp", half_bytes(c, spinor_prec, nrhs)), nrhs, spinor_prec, epsp,
-                         s);
-            break;
-        case TM_NORMAL: {
-            void *tmp = ws_get(c, "d_tmp", half_bytes(c, spinor_prec, nrhs));
-            void *mid = ws_get(c, "d_mid", half_bytes(c, spinor_prec, nrhs));
-            op_schur(c, mid, in, tmp, nrhs, spinor_prec, epsp, s);
-            op_schur_dag(c, out, mid, tmp, nrhs, spinor_prec, epsp, s);
-            break;
-        }
-        case TM_FULL:
-        case TM_FULL_DAG: {
-            TM_REQUIRE(spinor_prec == TM_F64, "full-lattice kinds take canonical FP64 spinors");
-            const size_t b = half_bytes(c, TM_F64, nrhs);
-            void *ie = ws_get(c, "d_ie", b), *io = ws_get(c, "d_io", b);
-            void *oe = ws_get(c, "d_oe", b), *oo = ws_get(c, "d_oo", b);
-            launch_pack(c, ie, io, (const double *)in, nrhs, TM_F64, nullptr, s);
-            const int dag = kind == TM_FULL_DAG;
-            // M = R(eps) + H;  M^dag = R(-eps) + H^dag
-            const SpinDiag tw = sd_twist(dag ? -epsp : epsp);
-            op_dslash(c, oe, io, ie, nrhs, TM_F64, 0, dag, sd_scalar(-k), tw, s);
-            op_dslash(c, oo, ie, io, nrhs, TM_F64, 1, dag, sd_scalar(-k), tw, s);
-            launch_unpack(c, (double *)out, oe, oo, nrhs, TM_F64, s);
-            break;
-        }
-        default: throw TmError{TM_ERR_ARG, "unknown dslash kind"};
-        }
-        return TM_OK;
+            ~NoAlloc() { c->no_alloc = false; }
+        } guard{c};
+        c->no_alloc = true;
+        size_t used = 0;
+        // consecutive 256-byte aligned pieces of the scratch array
+        auto take = [&](const char *name, size_t bytes) -> void * {
+            const size_t at = used;
+            used += (bytes + 255) / 256 * 256;
+            if (used > kNoallocScratchBytes)
+                throw TmError{TM_ERR_UNSUPPORTED,
+                              std::string("tm_dslash_noalloc: the intermediate fields of this kind need more than the ") +
+                                  std::to_string(kNoallocScratchBytes) + " bytes of device scratch (" + name + ")"};
+            return base + at;
+        };
+        return dslash_body(c, out, in, nrhs, kind, mu_sign, spinor_prec, link_prec, stream, take);
     });
 }
 

@@ -730,11 +730,15 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         launch_r<SS, LS, T>(c, dc, it->second, s);
         return;
     }
+    const int def = sizeof(T) == 8 ? 1 : (n % 2 == 0 ? 2 : 1);
+    if (c->no_alloc) {  // allocation-free call: no timing launches, no events
+        launch_r<SS, LS, T>(c, dc, def, s);
+        return;
+    }
     int fixed = 0;
     if (const char *e = getenv("TM_DSLASH_RHS_TILE")) fixed = atoi(e);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     TM_HIP(hipStreamIsCapturing(s, &cs));
-    const int def = sizeof(T) == 8 ? 1 : (n % 2 == 0 ? 2 : 1);
     // timing launches must leave the caller's fields as they were: the output
     // distinct from both inputs, and the in-place CG update of the fused form
     // redirected to scratch fields (its block partials are rewritten by the

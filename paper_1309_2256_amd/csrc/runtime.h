@@ -7,6 +7,13 @@
 // eps' = mu_sign * eps
 double eps_of(tm_ctx *c, int mu_sign);
 
+// device scratch of the allocation-free entry points (noalloc.hip): bytes
+// per device; setup looks the array's address up on `device` (once per
+// device, TM_OK or TM_ERR_HIP); scratch returns it (null before setup)
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+int noalloc_setup(int device);
+void *noalloc_scratch(int device);
+
 // host helpers: wall clock; synchronous upload; download through the pinned
 // stage (synchronises s); per-RHS |v|^2 on the host; bytes of a half field;
 // asynchronous device copy

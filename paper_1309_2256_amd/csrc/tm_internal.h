@@ -300,6 +300,9 @@ struct tm_ctx {
     // accounted per replay instead
     double acct_bytes = 0, acct_flops = 0;
     int acct_pause = 0;
+    // set for the duration of an allocation-free call: ws_get refuses to
+    // allocate and the Dslash tile tuner is not run
+    bool no_alloc = false;
 };
 
 // 12-parameter links for kernels of spinor precision prec: the format asks
