@@ -26,7 +26,7 @@ constexpr int kBlock = 256;
 // per lane to 512 / waves): one FP64 right-hand side fits in ~150 registers,
 // two in 256; one or two FP32-arithmetic right-hand sides fit in 128
 template <typename T, int R>
-constexpr int waves_for() { return sizeof(T) == 8 ? (R == 1 ? 3 : 2) : (R <= 2 ? 4 : 3); }
+constexpr int waves_for() { return sizeof(T) == 8 ? (R == 1 ? 3 : 2) : (R <= 2 ? 4 : R == 3 ? 3 : 2); }
 
 // 16-byte aligned so that an array of records keeps every complex field
 // naturally aligned
@@ -389,10 +389,176 @@ __device__ __forceinline__ void load_link12(cx<T> W[9], rsrc_t lr, int vbytes, i
     }
 }
 
+// ------------------------------------------------ FP16 spinors, binary16 links
+// Packed form of the hop for IEEE binary16 spinors and links: the spin
+// projection h = u + a l (a = +-1, +-i) is one packed binary16 add per
+// complex value, producing h in the two arrangements the colour product
+// needs, conj(h) = (h.r, -h.i) and swap(h) = (h.i, h.r); each complex
+// multiply-add of the 3x3 link product is then two v_dot2_f32_f16
+//   Re(w h) += w.r h.r - w.i h.i = dot2(w, conj h),
+//   Im(w h) += w.r h.i + w.i h.r = dot2(w, swap h),
+// whose binary16 products are exact and whose sums are FP32.  Relative to
+// the FP32 projection this rounds h once to binary16 (the storage precision
+// of its inputs); all accumulation stays FP32.
+typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
+
+// h = u + SG l (I = false) or u + SG i l (I = true), as (conj h, swap h):
+// each one v_pk_add_f16 whose operand selection (op_sel: which half of each
+// source feeds the low result, op_sel_hi: the high result) and negation
+// modifiers (neg_lo, neg_hi: negate that source's value in the low / high
+// result) form the arrangement, written out so that no separate swap or
+// sign instruction is generated.  With u = (ur, ui), l = (lr, li):
+//   real, SG > 0:  conj = (ur + lr, -ui - li)   swap = (ui + li, ur + lr)
+//   real, SG < 0:  conj = (ur - lr, -ui + li)   swap = (ui - li, ur - lr)
+//   i,    SG > 0:  conj = (ur - li, -ui - lr)   swap = (ui + lr, ur - li)
+//   i,    SG < 0:  conj = (ur + li, -ui + lr)   swap = (ui - lr, ur + li)
+template <bool I, int SG>
+__device__ __forceinline__ void proj2(hv2 u, hv2 l, hv2 &hc, hv2 &hs)
+{
+    if constexpr (!I && SG > 0) {
+        asm("v_pk_add_f16 %0, %1, %2 neg_hi:[1,1]" : "=v"(hc) : "v"(u), "v"(l));
+        asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,1] op_sel_hi:[0,0]" : "=v"(hs) : "v"(u), "v"(l));
+    } else if constexpr (!I) {
+        asm("v_pk_add_f16 %0, %1, %2 neg_lo:[0,1] neg_hi:[1,0]" : "=v"(hc) : "v"(u), "v"(l));
+        asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[0,1]"
+            : "=v"(hs) : "v"(u), "v"(l));
+    } else if constexpr (SG > 0) {
+        asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[1,1]"
+            : "=v"(hc) : "v"(u), "v"(l));
+        asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1] neg_hi:[0,1]" : "=v"(hs) : "v"(u), "v"(l));
+    } else {
+        asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_hi:[1,0]" : "=v"(hc) : "v"(u), "v"(l));
+        asm("v_pk_add_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1]" : "=v"(hs) : "v"(u), "v"(l));
+    }
+}
+
+// a.lo b.lo + a.hi b.hi (binary16 products, FP32 sum) with no accumulator
+// input: the first term of a chain, without a register cleared to zero
+__device__ __forceinline__ float dot2_first(hv2 a, hv2 b)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+
+template <int MU, int S>
+__device__ __forceinline__ void hop_dir_h(cx<float> acc[12], const hv2 W[9], const hv2 psi[12])
+{
+    hv2 c0[3], s0[3], c1[3], s1[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const hv2 u0 = psi[c], u1 = psi[3 + c], l0 = psi[6 + c], l1 = psi[9 + c];
+        if (MU == 0) {          // h0 = u0 + S i l1, h1 = u1 + S i l0
+            proj2<true, S>(u0, l1, c0[c], s0[c]);
+            proj2<true, S>(u1, l0, c1[c], s1[c]);
+        } else if (MU == 1) {   // h0 = u0 + S l1,   h1 = u1 - S l0
+            proj2<false, S>(u0, l1, c0[c], s0[c]);
+            proj2<false, -S>(u1, l0, c1[c], s1[c]);
+        } else if (MU == 2) {   // h0 = u0 + S i l0, h1 = u1 - S i l1
+            proj2<true, S>(u0, l0, c0[c], s0[c]);
+            proj2<true, -S>(u1, l1, c1[c], s1[c]);
+        } else {                // h0 = u0 - S l0,   h1 = u1 - S l1
+            proj2<false, -S>(u0, l0, c0[c], s0[c]);
+            proj2<false, -S>(u1, l1, c1[c], s1[c]);
+        }
+    }
+    cx<float> w0[3], w1[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        float ar = dot2_first(W[3 * r], c0[0]), ai = dot2_first(W[3 * r], s0[0]);
+        float br = dot2_first(W[3 * r], c1[0]), bi = dot2_first(W[3 * r], s1[0]);
+#pragma unroll
+        for (int c = 1; c < 3; c++) {
+            ar = __builtin_amdgcn_fdot2(W[3 * r + c], c0[c], ar, false);
+            ai = __builtin_amdgcn_fdot2(W[3 * r + c], s0[c], ai, false);
+            br = __builtin_amdgcn_fdot2(W[3 * r + c], c1[c], br, false);
+            bi = __builtin_amdgcn_fdot2(W[3 * r + c], s1[c], bi, false);
+        }
+        w0[r] = {ar, ai};
+        w1[r] = {br, bi};
+    }
+    constexpr float s = (float)S;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc[c].r += w0[c].r;
+        acc[c].i += w0[c].i;
+        acc[3 + c].r += w1[c].r;
+        acc[3 + c].i += w1[c].i;
+        cx<float> &l0 = acc[6 + c], &l1 = acc[9 + c];
+        if (MU == 0) {          // lower = -S (i w1, i w0)
+            l0.r += s * w1[c].i; l0.i -= s * w1[c].r;
+            l1.r += s * w0[c].i; l1.i -= s * w0[c].r;
+        } else if (MU == 1) {   // lower = -S (w1, -w0)
+            l0.r -= s * w1[c].r; l0.i -= s * w1[c].i;
+            l1.r += s * w0[c].r; l1.i += s * w0[c].i;
+        } else if (MU == 2) {   // lower = -S (i w0, -i w1)
+            l0.r += s * w0[c].i; l0.i -= s * w0[c].r;
+            l1.r -= s * w1[c].i; l1.i += s * w1[c].r;
+        } else {                // lower = -S (w0, w1)
+            l0.r -= s * w0[c].r; l0.i -= s * w0[c].i;
+            l1.r -= s * w1[c].r; l1.i -= s * w1[c].i;
+        }
+    }
+}
+
+__device__ __forceinline__ hv2 ld_hv2(rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(hv2, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// binary16 link as nine packed entries; the 12-parameter form rebuilds the
+// third row conj(row0 x row1) with dot2 products (exact binary16 products,
+// FP32 sums) rounded once to binary16, times the time-boundary factor on
+// links that cross the boundary
+template <bool REC>
+__device__ __forceinline__ void load_link_h(hv2 W[9], rsrc_t lr, int vbytes, int voff, bool cross, float tbc)
+{
+    if constexpr (!REC) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) W[k] = ld_hv2(lr, voff, k * vbytes);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; k++) W[k] = ld_hv2(lr, voff, k * vbytes);
+        // conj(a b - c d): Re(a b) = dot2(a, conj b), Im(a b) = dot2(a, swap b)
+        auto cr = [](hv2 a, hv2 b, hv2 c, hv2 d) {
+            const hv2 nc = -c;
+            const float re = __builtin_amdgcn_fdot2(nc, hv2{d.x, -d.y}, dot2_first(a, hv2{b.x, -b.y}), false);
+            const float im = __builtin_amdgcn_fdot2(nc, hv2{d.y, d.x}, dot2_first(a, hv2{b.y, b.x}), false);
+            return hv2{(_Float16)re, (_Float16)(-im)};
+        };
+        W[6] = cr(W[1], W[5], W[2], W[4]);
+        W[7] = cr(W[2], W[3], W[0], W[5]);
+        W[8] = cr(W[0], W[4], W[1], W[3]);
+        if (cross) {
+            const _Float16 f = (_Float16)tbc;
+#pragma unroll
+            for (int k = 6; k < 9; k++) W[k] = W[k] * f;
+        }
+    }
+}
+
 template <int MU, int S, typename SS, typename LS, typename T, int R>
 __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, const rsrc_t *sr, int dir, int j,
                                        int i, int t)
 {
+    if constexpr (std::is_same<SS, h2>::value && (std::is_same<LS, L12>::value || std::is_same<LS, h2>::value)) {
+        constexpr bool REC = std::is_same<LS, L12>::value;
+        constexpr int NP = REC ? 6 : 9;
+        const h2 *lbase = (const h2 *)a.links + (size_t)dir * NP * a.g.vh;
+        const rsrc_t lr = make_rsrc(lbase, (size_t)NP * a.g.vh * sizeof(h2));
+        const bool bnd = MU == 3 && (dir < 4 ? t == a.g.L[3] - 1 : t == 0);
+        hv2 W[9];
+        load_link_h<REC>(W, lr, a.g.vh * (int)sizeof(h2), i * (int)sizeof(h2), bnd, (float)a.t_bc);
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            hv2 psi[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) psi[k] = ld_hv2(sr[rr], j * (int)sizeof(h2), k * a.g.vh * (int)sizeof(h2));
+            hop_dir_h<MU, S>(reinterpret_cast<cx<float> *>(acc[rr]), W, psi);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        return;
+    }
     typename LinkEl<LS, T>::type W[9];
     if constexpr (std::is_same<LS, L12>::value || std::is_same<LS, L12D>::value || std::is_same<LS, L12F>::value) {
         using RS = std::conditional_t<std::is_same<LS, L12>::value, h2,
@@ -690,15 +856,29 @@ void launch_t(tm_ctx *c, const DslashCall &dc, hipStream_t s)
 }
 
 // Right-hand sides per thread that fit the register budget: FP32 arithmetic
-// 1..3 (4 or more exceed 3 resident waves and spill), FP64 1..2
-template <typename T>
-constexpr int max_tile() { return sizeof(T) == 8 ? 2 : 3; }
+// 1..3 (4 or more exceed 3 resident waves and spill), FP64 1..2; the packed
+// binary16 form (FP16 spinors, binary16 links) keeps its spinors in half the
+// registers and also tries 4 (at 2 waves per SIMD)
+template <typename SS, typename LS, typename T>
+constexpr int max_tile()
+{
+    if constexpr (sizeof(T) == 8) return 2;
+    if constexpr (std::is_same<SS, h2>::value && (std::is_same<LS, L12>::value || std::is_same<LS, h2>::value))
+        return 4;
+    return 3;
+}
 
 template <typename SS, typename LS, typename T>
 void launch_r(tm_ctx *c, const DslashCall &dc, int R, hipStream_t s)
 {
+    if constexpr (max_tile<SS, LS, T>() >= 4) {
+        if (R == 4) {
+            launch_t<SS, LS, T, 4>(c, dc, s);
+            return;
+        }
+    }
     if (R == 3) {
-        if constexpr (max_tile<T>() >= 3) {
+        if constexpr (max_tile<SS, LS, T>() >= 3) {
             launch_t<SS, LS, T, 3>(c, dc, s);
             return;
         }
@@ -745,7 +925,7 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     // real launch that follows)
     DslashCall tc = dc;
     const bool repeatable = dc.epi == EPI_CG || (dc.out != dc.in && dc.out != dc.own);
-    if (fixed > 0 && fixed <= max_tile<T>() && n % fixed == 0) {
+    if (fixed > 0 && fixed <= max_tile<SS, LS, T>() && n % fixed == 0) {
         c->rhs_tile[key] = fixed;
     } else if (!repeatable || cs != hipStreamCaptureStatusNone || n == 1) {
         launch_r<SS, LS, T>(c, dc, def, s);  // tune on a later plain launch
@@ -761,7 +941,7 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         TM_HIP(hipEventCreate(&e1));
         float best = 1e30f;
         int bestR = def;
-        for (int R = 1; R <= max_tile<T>(); R++) {
+        for (int R = 1; R <= max_tile<SS, LS, T>(); R++) {
             if (n % R) continue;
             launch_r<SS, LS, T>(c, tc, R, s);  // warm
             TM_HIP(hipEventRecord(e0, s));
