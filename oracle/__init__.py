@@ -43,6 +43,8 @@ def lib():
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.or_gamma.argtypes = [ctypes.c_int, dp]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_get_threads.restype = ctypes.c_int
         L.or_twist.argtypes = [_c_int4, ctypes.c_double, ctypes.c_int, dp, dp]
         L.or_hop.argtypes = [_c_int4, ctypes.c_double, ctypes.c_int, dp, dp, dp, ctypes.c_int]
         L.or_apply_M.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -78,6 +80,9 @@ def lib():
         L.or_ptc_loss_grad.argtypes = [_c_int4, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, dp,
                                        dp]
         L.or_ptc_loss_grad.restype = ctypes.c_double
+        L.or_ptc_res_loss_grad.argtypes = [_c_int4, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp,
+                                           ctypes.c_int, dp, dp, dp, dp, dp]
+        L.or_ptc_res_loss_grad.restype = ctypes.c_double
         L.or_site_parity.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_int)]
         L.or_neighbours.argtypes = [_c_int4, ctypes.POINTER(ctypes.c_long)]
         _lib = L
@@ -631,3 +636,28 @@ def ptc_loss_grad(L, t_bc, U, W1, W2, rs, es):
                                        _p(_spinor(L, r)), _p(_spinor(L, e)), _p(G1), _p(G2))
     n = len(rs)
     return loss / n, G1 / n, G2 / n
+
+
+def ptc_res_loss_grad(L, kappa, eps, t_bc, U, W1, W2, rs):
+    """Mean over residuals of |M N(r) - r|^2 / |r|^2 and its gradient (complex
+    dl/dRe w + i dl/dIm w) for W1 and W2."""
+    nc = W1.shape[1]
+    W1, W2 = _weights(W1, nc), _weights(W2, nc)
+    U = _links(L, U)
+    G1 = np.zeros_like(W1)
+    G2 = np.zeros_like(W2)
+    loss = 0.0
+    for r in rs:
+        loss += lib().or_ptc_res_loss_grad(_L(L), float(kappa), float(eps), int(t_bc), _p(U), nc, _p(W1),
+                                           _p(W2), _p(_spinor(L, r)), _p(G1), _p(G2))
+    n = len(rs)
+    return loss / n, G1 / n, G2 / n
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle (timing of the CPU baseline)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads():
+    return lib().or_get_threads()

@@ -35,6 +35,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -954,41 +955,28 @@ void or_ptc_at(const int L[4], int t_bc, const double *Ud, int nc, const double 
 }
 
 /*
- * Loss of one pair, l = |N(in) - e|^2 / |e|^2, and its gradient with respect
- * to the real and imaginary parts of every weight, accumulated into G1, G2 as
- * complex numbers dl/dRe(w) + i dl/dIm(w), by reverse-mode differentiation of
- * the forward pass above: with delta = 2 (out - e) / |e|^2,
+ * Gradient of a loss l(out), out = N(in), with respect to the real and
+ * imaginary parts of every weight, accumulated into G1, G2 as complex numbers
+ * dl/dRe(w) + i dl/dIm(w), given delta = 2 dl/d(conj out) (for l = |out - e|^2 / |e|^2
+ * that is 2 (out - e) / |e|^2), by reverse-mode differentiation of the forward
+ * pass above:
  *   G2[k][c] = sum_x delta(x) (T_k phi_c)(x)^dag      (spin outer product,
  *                                                      colour traced)
  *   g_c      = sum_k T_k^dag (W2[k][c]^dag delta)
  *   G1[k][c] = sum_x g_c(x) (T_k in)(x)^dag.
- * Returns l.
  */
-double or_ptc_loss_grad(const int L[4], int t_bc, const double *U, int nc, const double *W1d,
-                        const double *W2d, const double *ind, const double *ed, double *G1d,
-                        double *G2d)
+static void ptc_grad_from_delta(const int L[4], int t_bc, const double *U, int nc, const cplx *W1,
+                                const cplx *W2, const double *ind, const cplx *delta, cplx *G1, cplx *G2)
 {
-    const cplx *W1 = (const cplx *)W1d, *W2 = (const cplx *)W2d, *e = (const cplx *)ed;
-    cplx *G1 = (cplx *)G1d, *G2 = (cplx *)G2d;
     long V = vol(L);
     size_t n = sizeof(cplx) * 12 * V;
-    cplx *T = malloc(n), *phi = malloc(n * nc), *out = malloc(n), *delta = malloc(n);
-    cplx *g = malloc(n), *tmp = malloc(n), *Tin = malloc(n * 9);
-    or_ptc_forward(L, t_bc, U, nc, W1d, W2d, ind, (double *)out);
+    cplx *T = malloc(n), *phi = malloc(n * nc), *g = malloc(n), *tmp = malloc(n), *Tin = malloc(n * 9);
     /* hidden layer again (kept for the gradients) */
     memset(phi, 0, n * nc);
     for (int k = 0; k < 9; k++) {
         or_transport(L, t_bc, U, k, ind, (double *)(Tin + 12 * V * k), 0);
         for (int c = 0; c < nc; c++) spin_mac(V, W1 + 16 * (k * nc + c), Tin + 12 * V * k, phi + 12 * V * c);
     }
-    double en = 0, l = 0;
-    for (long i = 0; i < 12 * V; i++) en += creal(e[i] * conj(e[i]));
-    for (long i = 0; i < 12 * V; i++) {
-        cplx d = out[i] - e[i];
-        l += creal(d * conj(d));
-        delta[i] = 2.0 * d / en;
-    }
-    l /= en;
     for (int c = 0; c < nc; c++) {
         memset(g, 0, n);
         for (int k = 0; k < 9; k++) {
@@ -1023,6 +1011,67 @@ double or_ptc_loss_grad(const int L[4], int t_bc, const double *U, int nc, const
                 }
         }
     }
-    free(T); free(phi); free(out); free(delta); free(g); free(tmp); free(Tin);
+    free(T); free(phi); free(g); free(tmp); free(Tin);
+}
+
+/*
+ * Error loss of one pair, l = |N(in) - e|^2 / |e|^2, and its gradient
+ * (accumulated into G1, G2); delta = 2 (out - e) / |e|^2.  Returns l.
+ */
+double or_ptc_loss_grad(const int L[4], int t_bc, const double *U, int nc, const double *W1d,
+                        const double *W2d, const double *ind, const double *ed, double *G1d,
+                        double *G2d)
+{
+    const cplx *e = (const cplx *)ed;
+    long V = vol(L);
+    size_t n = sizeof(cplx) * 12 * V;
+    cplx *out = malloc(n), *delta = malloc(n);
+    or_ptc_forward(L, t_bc, U, nc, W1d, W2d, ind, (double *)out);
+    double en = 0, l = 0;
+    for (long i = 0; i < 12 * V; i++) en += creal(e[i] * conj(e[i]));
+    for (long i = 0; i < 12 * V; i++) {
+        cplx d = out[i] - e[i];
+        l += creal(d * conj(d));
+        delta[i] = 2.0 * d / en;
+    }
+    l /= en;
+    ptc_grad_from_delta(L, t_bc, U, nc, (const cplx *)W1d, (const cplx *)W2d, ind, delta, (cplx *)G1d,
+                        (cplx *)G2d);
+    free(out); free(delta);
     return l;
 }
+
+/*
+ * Residual loss of one residual r = in: with w = M N(r) - r,
+ * l = |w|^2 / |r|^2 (how far M N is from the identity on r, the quantity a
+ * right preconditioner N of M is judged by), and its gradient: l depends on
+ * out = N(r) through w, so delta = 2 dl/d(conj out) = 2 M^dag w / |r|^2.
+ * Returns l.
+ */
+double or_ptc_res_loss_grad(const int L[4], double kappa, double eps, int t_bc, const double *U, int nc,
+                            const double *W1d, const double *W2d, const double *ind, double *G1d, double *G2d)
+{
+    const cplx *r = (const cplx *)ind;
+    long V = vol(L);
+    size_t n = sizeof(cplx) * 12 * V;
+    cplx *out = malloc(n), *w = malloc(n), *delta = malloc(n);
+    or_ptc_forward(L, t_bc, U, nc, W1d, W2d, ind, (double *)out);
+    or_apply_M(L, kappa, eps, t_bc, U, (const double *)out, (double *)w, 0);
+    double rn = 0, l = 0;
+    for (long i = 0; i < 12 * V; i++) {
+        rn += creal(r[i] * conj(r[i]));
+        w[i] -= r[i];
+        l += creal(w[i] * conj(w[i]));
+    }
+    or_apply_M(L, kappa, eps, t_bc, U, (const double *)w, (double *)delta, 1);
+    for (long i = 0; i < 12 * V; i++) delta[i] *= 2.0 / rn;
+    ptc_grad_from_delta(L, t_bc, U, nc, (const cplx *)W1d, (const cplx *)W2d, ind, delta, (cplx *)G1d,
+                        (cplx *)G2d);
+    free(out); free(w); free(delta);
+    return l / rn;
+}
+
+/* OpenMP threads of the oracle's parallel loops (timing only; results do not
+ * depend on it beyond reduction order) */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }

@@ -45,4 +45,8 @@ void or_ptc_at(const int L[4], int t_bc, const double *U, int nc, const double *
 double or_ptc_loss_grad(const int L[4], int t_bc, const double *U, int nc, const double *W1,
                         const double *W2, const double *in, const double *e, double *G1,
                         double *G2);
+double or_ptc_res_loss_grad(const int L[4], double kappa, double eps, int t_bc, const double *U, int nc,
+                            const double *W1, const double *W2, const double *in, double *G1, double *G2);
+void or_set_threads(int n);
+int or_get_threads(void);
 #endif

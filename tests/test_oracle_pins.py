@@ -435,6 +435,62 @@ def test_ptc_gradient_finite_differences():
                 assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (idx, part, fd, an)
 
 
+def test_ptc_residual_loss_gradient_finite_differences():
+    """Residual loss |M N(r) - r|^2 / |r|^2: the analytic gradient (delta =
+    2 M^dag w / |r|^2 propagated back through the network) against central
+    differences of the loss, both signs of the twist."""
+    L = (2, 2, 2, 4)
+    U = S.gauge_links(L, 0.5, 61)
+    rng = np.random.default_rng(62)
+    nc = 3
+    W1, W2 = _rand_weights(rng, nc), _rand_weights(rng, nc)
+    rs = [S.random_spinor(L, 63 + i) for i in range(2)]
+    h = 1e-6
+    for eps in (0.05, -0.05):
+        loss, G1, G2 = O.ptc_res_loss_grad(L, 0.13, eps, -1, U, W1, W2, rs)
+        for W, G in ((W1, G1), (W2, G2)):
+            for idx in [(0, 0, 0, 0), (3, 1, 2, 1), (8, 2, 3, 3), (6, 0, 1, 2)]:
+                for part in (1, 1j):
+                    Wp, Wm = W.copy(), W.copy()
+                    Wp[idx] += h * part
+                    Wm[idx] -= h * part
+                    lp = O.ptc_res_loss_grad(L, 0.13, eps, -1, U, Wp if W is W1 else W1,
+                                             Wp if W is W2 else W2, rs)[0]
+                    lm = O.ptc_res_loss_grad(L, 0.13, eps, -1, U, Wm if W is W1 else W1,
+                                             Wm if W is W2 else W2, rs)[0]
+                    fd = (lp - lm) / (2 * h)
+                    an = G[idx].real if part == 1 else G[idx].imag
+                    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (eps, idx, part, fd, an)
+
+
+def test_ptc_residual_loss_special_cases():
+    """N = 0 gives loss 1 (w = -r); N = R^-1 on a field with H = 0 (kappa = 0)
+    is the exact inverse, loss 0 and zero gradient; the residual loss of a
+    pair equals |M (N r - e)|^2 / |r|^2 for e = M^-1 r, tying it to the error
+    loss's quantity N r - e."""
+    L = (2, 2, 2, 4)
+    U = S.gauge_links(L, 0.5, 64)
+    r = S.random_spinor(L, 65)
+    nc = 2
+    W1 = np.zeros((9, nc, 4, 4), dtype=complex)
+    W2 = np.zeros((9, nc, 4, 4), dtype=complex)
+    loss, G1, G2 = O.ptc_res_loss_grad(L, 0.13, 0.05, -1, U, W1, W2, [r])
+    assert abs(loss - 1.0) < 1e-14
+    eps = 0.05
+    Rinv = np.diag([1 / (1 + 1j * eps)] * 2 + [1 / (1 - 1j * eps)] * 2)
+    W1[0, 0] = np.eye(4)
+    W2[0, 0] = Rinv
+    loss, G1, G2 = O.ptc_res_loss_grad(L, 0.0, eps, -1, U, W1, W2, [r])
+    assert loss < 1e-28 and np.abs(G1).max() < 1e-14 and np.abs(G2).max() < 1e-14
+    rng = np.random.default_rng(66)
+    W1, W2 = _rand_weights(rng, 3), _rand_weights(rng, 3)
+    e, _, _ = O.cgnr(L, 0.13, eps, -1, U, r, 1e-13)
+    d = O.ptc_forward(L, -1, U, W1, W2, r) - e
+    ref = np.linalg.norm(O.apply_M(L, 0.13, eps, -1, U, d)) ** 2 / np.linalg.norm(r) ** 2
+    loss, _, _ = O.ptc_res_loss_grad(L, 0.13, eps, -1, U, W1, W2, [r])
+    assert abs(loss - ref) <= 1e-10 * ref
+
+
 def test_ptc_at_equals_whole_lattice_forward():
     """The site-by-site evaluation (used at 32^3x64) agrees with the
     layer-by-layer whole-lattice evaluation, both boundary conditions."""
