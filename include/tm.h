@@ -117,9 +117,29 @@ int tm_set_gauge(tm_ctx *ctx, const double *U, tm_stream stream);
  *       otherwise those kernels read all 18.  Reliable-update residuals and
  *       the final true residual of every solve always use all 18 FP64
  *       parameters.
+ *   8   the FP64 kernels (plain solves, HPE, D_W, odd reconstruction) read
+ *       8 real parameters per link (appendix A.1, 8-parameter
+ *       reconstruction): a2, a3, b1 of U = [[a1,a2,a3],[b1,b2,b3],
+ *       [c1,c2,c3]] and the phases of a1 and c1; |a1|, |c1| follow from
+ *       the unit first row and column and the 2x2 block from the cofactor
+ *       relations of a special unitary matrix (links with |c1| < |b1| are
+ *       stored with their lower rows exchanged and negated, flagged in the
+ *       stored phase).  The FP32/FP16/BF16 kernels read the 12-parameter
+ *       form.  Used only while the field is special unitary to 1e-12 and
+ *       every link has |a2|^2 + |a3|^2 >= 1e-10 (the reconstruction divides
+ *       by it; exactly diagonal links such as a unit field keep 12).  The
+ *       reconstructed links agree with the stored ones to ~1e-13.
  * FP16/BF16 spinors with FP32 links (tm_dslash, link_prec TM_F32) keep all
  * 18.  Returns TM_ERR_ARG for other values. */
 int tm_set_link_format(tm_ctx *ctx, int params);
+
+/* Links read by the FP16/BF16-spinor kernels of the solvers (TM_CG_MIXED and
+ * TM_CG_LOW with FP16/BF16 storage) and of tm_dslash calls that do not ask
+ * otherwise: TM_F16 (default) the binary16 copy in the tm_set_link_format
+ * format, TM_F32 the FP32 copy with all 18 parameters (the FP32-link /
+ * FP16-spinor operator).  Batches (tm_batch_*) take TM_F16 only
+ * (TM_ERR_UNSUPPORTED otherwise).  TM_ERR_ARG for other values. */
+int tm_set_half_spinor_links(tm_ctx *ctx, int link_prec);
 
 /* Operator kinds of tm_dslash. */
 typedef enum {
@@ -209,7 +229,10 @@ typedef struct {
     int iters;            /* CG iterations (FGMRES: Arnoldi steps)              */
     int n_reliable;       /* reliable updates performed (FGMRES: restarts)      */
     int converged;        /* 1 when |b - M x| <= tol |b| at exit                 */
-    int reserved;
+    int fallback;         /* TM_FGMRES_PTC: 1 when a restart cycle failed to halve
+                             the residual and the plain mixed CG (FP16 storage,
+                             FP64 reliable updates) finished the solve from the
+                             current x; iters then adds its CG iterations        */
     double true_rel_res;  /* |b - M x| / |b| recomputed in FP64 at exit         */
     double iter_rel_res;  /* the solver's own (iterated) residual at exit       */
     double seconds;       /* wall time of the whole call                        */
@@ -399,6 +422,15 @@ int tm_batch_loops(tm_batch *batch, const tm_loop_params *p, double *const *loop
  * with A[k][k'] = sum_c W2[k][c] W1[k'][c] (exact: both layers are linear and
  * T_k commutes with spin matrices), transports in FP32, gradient sums in FP64. */
 
+/* Arithmetic of the network's forward pass (tm_ptc_apply, the FGMRES
+ * preconditioner, the training forward): TM_F32 (default; FP32 weights and
+ * fields on the vector units) or TM_BF16 (the spin mixing u_k = sum_k'
+ * A[k][k'] T_k' psi on the matrix cores, v_mfma_f32_16x16x32_bf16: A and the
+ * transported fields rounded to bfloat16, FP32 accumulation; transports and
+ * the gather stay FP32).  Gradients are FP32/FP64 either way.  TM_ERR_ARG for
+ * other values. */
+int tm_ptc_set_arith(tm_ctx *ctx, int prec);
+
 /* Set / read the weights (1 <= nc <= 64). */
 int tm_ptc_set_weights(tm_ctx *ctx, int nc, const double *W1, const double *W2);
 int tm_ptc_get_weights(tm_ctx *ctx, int nc, double *W1, double *W2);
@@ -409,16 +441,38 @@ int tm_ptc_get_weights(tm_ctx *ctx, int nc, double *W1, double *W2);
 int tm_ptc_init_hopping(tm_ctx *ctx, int nc, int mu_sign, uint64_t seed, double noise);
 /* out = N(in): device canonical full FP64 [nrhs][V][4][3], computed in FP32. */
 int tm_ptc_apply(tm_ctx *ctx, double *out, const double *in, int nrhs, tm_stream stream);
-/* Mean loss over npairs pairs (r[i], e[i]) (device canonical full FP64) and
- * its gradient; G1, G2: host [9][nc][4][4] complex double (may be NULL). */
-int tm_ptc_loss_grad(tm_ctx *ctx, const double *r, const double *e, int npairs, double *loss, double *G1,
-                     double *G2, tm_stream stream);
+/* Training losses of a pair (r, e), r a residual and e = M^-1 r its error:
+ *   TM_PTC_LOSS_ERROR     |N(r) - e|^2 / |e|^2
+ *   TM_PTC_LOSS_RESIDUAL  |M N(r) - r|^2 / |r|^2 with M = M(mu_sign) (e unused): how far
+ *                         M N is from the identity on r, what a right
+ *                         preconditioner is judged by.  On the device M is the
+ *                         FP32 even-odd operator and the gradient is carried
+ *                         back through M^dag. */
+enum { TM_PTC_LOSS_ERROR = 0, TM_PTC_LOSS_RESIDUAL = 1 };
+
+/* Mean loss of kind `loss_kind` over npairs pairs (r[i], e[i]) (device
+ * canonical full FP64; e may be NULL for TM_PTC_LOSS_RESIDUAL) and its
+ * gradient; G1, G2: host [9][nc][4][4] complex double (may be NULL). */
+int tm_ptc_loss_grad(tm_ctx *ctx, int loss_kind, int mu_sign, const double *r, const double *e, int npairs,
+                     double *loss, double *G1, double *G2, tm_stream stream);
 /* Training-pair store owned by the context: reserve room for `capacity`
  * pairs held in store_prec (TM_F32 or TM_BF16, round to nearest even); this
  * drops stored pairs.  tm_ptc_pairs_add appends n pairs (device canonical
  * full FP64 r, e; TM_ERR_ARG beyond capacity or for e = 0). */
 int tm_ptc_pairs_reserve(tm_ctx *ctx, int capacity, int store_prec);
 int tm_ptc_pairs_add(tm_ctx *ctx, const double *r, const double *e, int n, tm_stream stream);
+/* Pairs from the solver's own iterates: solves M(p->mu_sign) x = b for the
+ * nrhs right-hand sides b (device canonical full FP64) with p (TM_CG_F64 or
+ * TM_CG_MIXED) to its tolerance for x*, then again from x = 0 with maxiter =
+ * iters[j] for the iterates x_j (the solver is deterministic, so x_j is its
+ * own iterate after iters[j] iterations), and appends the pairs
+ * (r_j, e_j) = (b - M x_j, x* - x_j), r_j with all 18 FP64 link parameters,
+ * to the pair store (at most nrhs * n_iters; pairs whose r or e rounds to
+ * zero in the store precision are dropped).  *added (may be NULL) receives the
+ * number appended.  TM_ERR_ARG beyond capacity or if the reference solve
+ * does not converge. */
+int tm_ptc_pairs_from_solve(tm_ctx *ctx, const double *b, int nrhs, const tm_solve_params *p, const int *iters,
+                            int n_iters, int *added, tm_stream stream);
 
 typedef struct {
     int epochs;        /* passes over the stored pairs (>= 1)                      */
@@ -426,6 +480,8 @@ typedef struct {
     double lr;         /* Adam step size (Kingma and Ba 2015)                      */
     double beta1, beta2, adam_eps; /* Adam moments and denominator guard            */
     uint64_t seed;     /* order of the batches within each epoch                   */
+    int loss;          /* TM_PTC_LOSS_ERROR or TM_PTC_LOSS_RESIDUAL                */
+    int mu_sign;       /* flavour of M in the residual loss (+1 u, -1 d)           */
 } tm_ptc_train_params;
 
 typedef struct {
@@ -438,7 +494,7 @@ typedef struct {
 
 /* Train the weights by Adam on the stored pairs: each epoch visits the
  * floor(n / batch) consecutive batches in an order drawn from `seed`; a step
- * minimises the batch mean of the loss.  loss_per_step: host array of
+ * minimises the batch mean of the loss of kind p->loss.  loss_per_step: host array of
  * epochs * floor(n / batch) doubles (loss of each batch before its step) or
  * NULL.  The weights start from the current ones (set or initialised). */
 int tm_ptc_train(tm_ctx *ctx, const tm_ptc_train_params *p, tm_ptc_train_stats *stats, double *loss_per_step,

@@ -29,6 +29,7 @@ TM_F64, TM_F32, TM_F16, TM_BF16 = 0, 1, 2, 3
 TM_CG_F64, TM_CG_MIXED, TM_CG_LOW, TM_FGMRES, TM_FGMRES_PTC = 0, 1, 2, 3, 4
 TM_EST_STD, TM_EST_ONE_END, TM_EST_HPE, TM_EST_GEN_ONE_END = 1, 2, 4, 8
 TM_DIL_NONE, TM_DIL_SPIN_COLOUR = 0, 1
+TM_PTC_LOSS_ERROR, TM_PTC_LOSS_RESIDUAL = 0, 1
 
 STATUS_NAMES = {0: "TM_OK", -1: "TM_ERR_ARG", -2: "TM_ERR_HIP", -3: "TM_ERR_OOM",
                 -4: "TM_ERR_NOCONV", -5: "TM_ERR_NAN", -6: "TM_ERR_UNSUPPORTED"}
@@ -48,7 +49,7 @@ class tm_solve_params(ctypes.Structure):
 
 class tm_solve_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("n_reliable", ctypes.c_int), ("converged", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("true_rel_res", ctypes.c_double),
+                ("fallback", ctypes.c_int), ("true_rel_res", ctypes.c_double),
                 ("iter_rel_res", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
@@ -71,7 +72,7 @@ class tm_loop_stats(ctypes.Structure):
 class tm_ptc_train_params(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("adam_eps", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("loss", ctypes.c_int), ("mu_sign", ctypes.c_int)]
 
 
 class tm_ptc_train_stats(ctypes.Structure):
@@ -91,6 +92,7 @@ _SIGS = {
     "tm_dslash_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, _vp]),
     "tm_set_link_format": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "tm_set_half_spinor_links": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tm_pack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _dp, _vp]),
     "tm_unpack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "tm_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(tm_solve_params),
@@ -116,12 +118,17 @@ _SIGS = {
                                       ctypes.POINTER(tm_loop_stats), _vp]),
     "tm_ptc_set_weights": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
     "tm_ptc_get_weights": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
+    "tm_ptc_set_arith": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tm_ptc_init_hopping": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                            ctypes.c_double]),
     "tm_ptc_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
-    "tm_ptc_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _dp, _dp, _dp, _vp]),
+    "tm_ptc_loss_grad": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _dp, _dp,
+                                        _dp, _vp]),
     "tm_ptc_pairs_reserve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "tm_ptc_pairs_add": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "tm_ptc_pairs_from_solve": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(tm_solve_params),
+                                               ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_int), _vp]),
     "tm_ptc_train": (ctypes.c_int, [_vp, ctypes.POINTER(tm_ptc_train_params),
                                     ctypes.POINTER(tm_ptc_train_stats), _dp, _vp]),
 }
@@ -192,6 +199,10 @@ class Context:
     def set_gauge(self, U, stream=None):
         self._check(tm_set_gauge(self.h, _ptr(U), _stream(stream)))
 
+    def set_half_spinor_links(self, link_prec):
+        """Links of the FP16/BF16-spinor solver kernels: TM_F16 (binary16) or TM_F32."""
+        self._check(tm_set_half_spinor_links(self.h, link_prec))
+
     def set_link_format(self, params):
         """Binary16 links of the FP16/BF16-spinor kernels: 18 or 12 parameters."""
         self._check(tm_set_link_format(self.h, params))
@@ -255,6 +266,10 @@ class Context:
         self._check(tm_ptc_set_weights(self.h, W1.shape[1], W1.ctypes.data_as(_dp),
                                        W2.ctypes.data_as(_dp)))
 
+    def ptc_set_arith(self, prec):
+        """Network forward arithmetic: TM_F32 (vector units) or TM_BF16 (matrix cores)."""
+        self._check(tm_ptc_set_arith(self.h, prec))
+
     def ptc_get_weights(self, nc):
         W1 = np.zeros((9, nc, 4, 4), dtype=np.complex128)
         W2 = np.zeros_like(W1)
@@ -267,11 +282,12 @@ class Context:
     def ptc_apply(self, out, inp, nrhs, stream=None):
         self._check(tm_ptc_apply(self.h, _ptr(out), _ptr(inp), nrhs, _stream(stream)))
 
-    def ptc_loss_grad(self, r, e, npairs, nc, stream=None):
+    def ptc_loss_grad(self, r, e, npairs, nc, loss_kind=TM_PTC_LOSS_ERROR, mu_sign=1, stream=None):
         loss = ctypes.c_double()
         G1 = np.zeros((9, nc, 4, 4), dtype=np.complex128)
         G2 = np.zeros_like(G1)
-        self._check(tm_ptc_loss_grad(self.h, _ptr(r), _ptr(e), npairs, ctypes.byref(loss),
+        self._check(tm_ptc_loss_grad(self.h, loss_kind, mu_sign, _ptr(r),
+                                     _ptr(e) if e is not None else None, npairs, ctypes.byref(loss),
                                      G1.ctypes.data_as(_dp), G2.ctypes.data_as(_dp), _stream(stream)))
         return loss.value, G1, G2
 
@@ -281,9 +297,17 @@ class Context:
     def ptc_pairs_add(self, r, e, n, stream=None):
         self._check(tm_ptc_pairs_add(self.h, _ptr(r), _ptr(e), n, _stream(stream)))
 
+    def ptc_pairs_from_solve(self, b, nrhs, params, iters, stream=None):
+        it = (ctypes.c_int * len(iters))(*iters)
+        added = ctypes.c_int(0)
+        self._check(tm_ptc_pairs_from_solve(self.h, _ptr(b), nrhs, ctypes.byref(params), it, len(iters),
+                                            ctypes.byref(added), _stream(stream)))
+        return added.value
+
     def ptc_train(self, epochs, batch, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-12, seed=0,
-                  n_pairs=None, stream=None):
-        p = tm_ptc_train_params(epochs, batch, lr, beta1, beta2, adam_eps, ctypes.c_uint64(seed))
+                  n_pairs=None, loss=TM_PTC_LOSS_ERROR, mu_sign=1, stream=None):
+        p = tm_ptc_train_params(epochs, batch, lr, beta1, beta2, adam_eps, ctypes.c_uint64(seed), loss,
+                                mu_sign)
         st = tm_ptc_train_stats()
         hist = None
         if n_pairs is not None:

@@ -84,6 +84,17 @@ void ensure_links12d(tm_ctx *c, hipStream_t s)
     c->have_links12d = true;
 }
 
+bool ensure_links8d(tm_ctx *c, hipStream_t s)
+{
+    if (!recon8_wanted(c)) return false;
+    if (c->have_links8d) return c->links8_usable;
+    for (int p = 0; p < 2; p++)
+        if (!c->links8d[p]) c->links8d[p] = ws_get(c, p ? "links8d_1" : "links8d_0", (size_t)32 * c->geo.vh * 16);
+    c->links8_usable = launch_links_to_r8d(c, s) >= kRecon8MinN;
+    c->have_links8d = true;
+    return c->links8_usable;
+}
+
 void ensure_links12f(tm_ctx *c, hipStream_t s)
 {
     if (c->have_links12f) return;
@@ -195,6 +206,8 @@ extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
         c->have_links16 = false;
         c->have_links12 = false;
         c->have_links12d = false;
+        c->have_links8d = false;
+        c->links8_usable = false;
         c->have_links12f = false;
         return TM_OK;
     });
@@ -202,10 +215,20 @@ extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
 
 // ---------------------------------------------------------------- dslash
 
+extern "C" int tm_set_half_spinor_links(tm_ctx *c, int link_prec)
+{
+    return guarded(c, [&]() {
+        TM_REQUIRE(link_prec == TM_F16 || link_prec == TM_F32, "link precision must be TM_F16 or TM_F32");
+        c->half_links_f32_default = link_prec == TM_F32;
+        c->half_links_f32 = c->half_links_f32_default;
+        return TM_OK;
+    });
+}
+
 extern "C" int tm_set_link_format(tm_ctx *c, int params)
 {
     return guarded(c, [&]() {
-        TM_REQUIRE(params == 18 || params == 12, "link format must be 18 or 12 parameters");
+        TM_REQUIRE(params == 18 || params == 12 || params == 8, "link format must be 18, 12 or 8 parameters");
         c->link_recon = params;
         return TM_OK;
     });
@@ -234,7 +257,7 @@ int dslash_body(tm_ctx *c, void *out, const void *in, int nrhs, int kind, int mu
     // the link copy for this call only (solvers use the binary16 copy)
     struct LinkChoice {
         tm_ctx *c;
-        ~LinkChoice() { c->half_links_f32 = false; }
+        ~LinkChoice() { c->half_links_f32 = c->half_links_f32_default; }
     } restore{c};
     c->half_links_f32 = link_prec == TM_F32;
     hipStream_t s = hs(stream);

@@ -389,6 +389,46 @@ __device__ __forceinline__ void load_link12(cx<T> W[9], rsrc_t lr, int vbytes, i
     }
 }
 
+// 8-parameter FP64 link (appendix A.1; stored form in misc.hip): |a1| and
+// |c1| from the unit first row and column, their phases from the stored
+// angles, the 2x2 block from the cofactor relations conj(U) = cof(U):
+//   b2 = -(conj(a1) a2 b1 + conj(c1) conj(a3)) / n,  b3 = (conj(a2) conj(c1) - conj(a1) a3 b1) / n,
+//   c2 = (conj(a3) conj(b1) - conj(a1) a2 c1) / n,   c3 = -(conj(a2) conj(b1) + conj(a1) a3 c1) / n,
+// n = |a2|^2 + |a3|^2; rows swapped and negated back for links stored that
+// way (phase flag), then the time-boundary factor on crossing links
+template <typename T>
+__device__ __forceinline__ void load_link8(cx<T> W[9], rsrc_t lr, int vbytes, int voff, bool cross, T tbc)
+{
+    const cx<T> a2 = BufIO<double2>::template ldlink<T>(lr, voff, 0);
+    const cx<T> a3 = BufIO<double2>::template ldlink<T>(lr, voff, vbytes);
+    const cx<T> b1 = BufIO<double2>::template ldlink<T>(lr, voff, 2 * vbytes);
+    const cx<T> ph = BufIO<double2>::template ldlink<T>(lr, voff, 3 * vbytes);
+    const bool swap = ph.i > (T)4;
+    const T tc = swap ? ph.i - (T)8 : ph.i;
+    const T n = a2.r * a2.r + a2.i * a2.i + a3.r * a3.r + a3.i * a3.i;
+    const T ra = sqrt((T)1 - n), rc = sqrt(fmax(n - (b1.r * b1.r + b1.i * b1.i), (T)0));
+    T sa, ca, sc, cc;
+    sincos(ph.r, &sa, &ca);
+    sincos(tc, &sc, &cc);
+    const cx<T> a1 = {ra * ca, ra * sa}, c1 = {rc * cc, rc * sc};
+    const T inv = (T)1 / n;
+    const cx<T> ab = conjg(a1) * b1, ac = conjg(a1) * c1;
+    const cx<T> a2c = conjg(a2), a3c = conjg(a3), b1c = conjg(b1), c1c = conjg(c1);
+    const cx<T> b2 = (ab * a2 + c1c * a3c) * cx<T>{-inv, 0};
+    const cx<T> b3 = (a2c * c1c - ab * a3) * cx<T>{inv, 0};
+    const cx<T> c2 = (a3c * b1c - ac * a2) * cx<T>{inv, 0};
+    const cx<T> c3 = (a2c * b1c + ac * a3) * cx<T>{-inv, 0};
+    const cx<T> m[9] = {a1, a2, a3, b1, b2, b3, c1, c2, c3};
+    const T g = (swap ? (T)-1 : (T)1) * (cross ? tbc : (T)1);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        W[k] = {g * m[k].r, g * m[k].i};
+        const cx<T> r1 = swap ? m[6 + k] : m[3 + k], r2 = swap ? m[3 + k] : m[6 + k];
+        W[3 + k] = {g * r1.r, g * r1.i};
+        W[6 + k] = {g * r2.r, g * r2.i};
+    }
+}
+
 // ------------------------------------------------ FP16 spinors, binary16 links
 // Packed form of the hop for IEEE binary16 spinors and links: the spin
 // projection h = u + a l (a = +-1, +-i) is one packed binary16 add per
@@ -560,7 +600,13 @@ __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, co
         return;
     }
     typename LinkEl<LS, T>::type W[9];
-    if constexpr (std::is_same<LS, L12>::value || std::is_same<LS, L12D>::value || std::is_same<LS, L12F>::value) {
+    if constexpr (std::is_same<LS, L8D>::value) {
+        const double2 *lbase = (const double2 *)a.links + (size_t)dir * 4 * a.g.vh;
+        const rsrc_t lr = make_rsrc(lbase, (size_t)4 * a.g.vh * sizeof(double2));
+        const bool bnd = MU == 3 && (dir < 4 ? t == a.g.L[3] - 1 : t == 0);
+        load_link8<T>(W, lr, a.g.vh * (int)sizeof(double2), i * (int)sizeof(double2), bnd, (T)a.t_bc);
+    } else if constexpr (std::is_same<LS, L12>::value || std::is_same<LS, L12D>::value ||
+                         std::is_same<LS, L12F>::value) {
         using RS = std::conditional_t<std::is_same<LS, L12>::value, h2,
                                       std::conditional_t<std::is_same<LS, L12D>::value, double2, float2>>;
         const RS *lbase = (const RS *)a.links + (size_t)dir * 6 * a.g.vh;
@@ -814,6 +860,7 @@ DParams<T> fill_params(tm_ctx *c, const DslashCall &dc)
                : std::is_same<LS, L12>::value    ? c->links12
                : std::is_same<LS, L12D>::value   ? c->links12d
                : std::is_same<LS, L12F>::value   ? c->links12f
+               : std::is_same<LS, L8D>::value    ? c->links8d
                                                  : c->links32)[dc.out_parity];
     a.g = c->geo;
     a.p = dc.out_parity;
@@ -902,6 +949,7 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
                       : std::is_same<LS, L12>::value ? 2
                       : std::is_same<LS, L12D>::value ? 3
                       : std::is_same<LS, L12F>::value ? 4
+                      : std::is_same<LS, L8D>::value  ? 5
                                                       : 0;
     const int form = dc.dag + 2 * (dc.has_own ? 1 : 0) + 4 * dc.epi;
     const auto key = std::make_pair(dc.spinor_prec + 8 * lcode + 32 * form, n);
@@ -1010,7 +1058,7 @@ void multi_go(const MultiDslash &m, hipStream_t s)
 }
 
 template <typename F>
-void multi_dispatch(int prec, bool recon12, int R, F &&f)
+void multi_dispatch(int prec, bool recon12, bool recon8, int R, F &&f)
 {
     auto byR = [&](auto *tag) {
         using P3 = std::remove_pointer_t<decltype(tag)>;
@@ -1028,6 +1076,7 @@ void multi_dispatch(int prec, bool recon12, int R, F &&f)
     };
     struct PD { using SS = double2; using LS = double2; using T = double; };
     struct PD12 { using SS = double2; using LS = L12D; using T = double; };
+    struct PD8 { using SS = double2; using LS = L8D; using T = double; };
     struct PF { using SS = float2; using LS = float2; using T = float; };
     struct PF12 { using SS = float2; using LS = L12F; using T = float; };
     struct PH { using SS = h2; using LS = h2; using T = float; };
@@ -1035,7 +1084,12 @@ void multi_dispatch(int prec, bool recon12, int R, F &&f)
     struct PH12 { using SS = h2; using LS = L12; using T = float; };
     struct PB12 { using SS = b2; using LS = L12; using T = float; };
     switch (prec) {
-    case TM_F64: recon12 ? byR((PD12 *)nullptr) : byR((PD *)nullptr); break;
+    case TM_F64:
+        if (recon8)
+            byR((PD8 *)nullptr);
+        else
+            recon12 ? byR((PD12 *)nullptr) : byR((PD *)nullptr);
+        break;
     case TM_F32: recon12 ? byR((PF12 *)nullptr) : byR((PF *)nullptr); break;
     case TM_F16: recon12 ? byR((PH12 *)nullptr) : byR((PH *)nullptr); break;
     case TM_BF16: recon12 ? byR((PB12 *)nullptr) : byR((PB *)nullptr); break;
@@ -1049,12 +1103,17 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
                           hipStream_t s)
 {
     TM_REQUIRE(!cs.empty() && cs.size() == dcs.size(), "bad multi-instance call");
+    for (tm_ctx *c : cs)
+        if (dcs[0].spinor_prec == TM_F16 || dcs[0].spinor_prec == TM_BF16)
+            if (c->half_links_f32)
+                throw TmError{TM_ERR_UNSUPPORTED, "batches read binary16 links for FP16/BF16 spinors"};
     m.prec = dcs[0].spinor_prec;
     m.dag = dcs[0].dag;
     m.own = dcs[0].has_own ? 1 : 0;
     m.epi = dcs[0].epi;
     m.R = R;
     m.n = (int)cs.size();
+    m.recon8 = false;
     for (size_t k = 0; k < cs.size(); k++) {
         TM_REQUIRE(dcs[k].spinor_prec == m.prec && dcs[k].dag == m.dag && (dcs[k].has_own ? 1 : 0) == m.own &&
                        dcs[k].epi == m.epi,
@@ -1068,7 +1127,12 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
             else
                 ensure_links32(cs[k], s);
         }
-        if (m.prec == TM_F64 && recon12_ok(cs[k], m.prec)) ensure_links12d(cs[k], s);
+        if (m.prec == TM_F64) {
+            const bool r8 = recon8_wanted(cs[k]) && ensure_links8d(cs[k], s);
+            TM_REQUIRE(k == 0 || r8 == m.recon8, "multi-instance calls must share the link format");
+            m.recon8 = r8;
+            if (!r8 && recon12_ok(cs[k], m.prec)) ensure_links12d(cs[k], s);
+        }
         if (m.prec == TM_F16 || m.prec == TM_BF16) {
             if (recon12_ok(cs[k], m.prec))
                 ensure_links12(cs[k], s);
@@ -1077,13 +1141,13 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
         }
     }
     m.recon12 = recon12_ok(cs[0], m.prec);
-    multi_dispatch(m.prec, m.recon12, R,
+    multi_dispatch(m.prec, m.recon12, m.recon8, R,
                    [&]<typename SS, typename LS, typename T, int RR>() { multi_fill<SS, LS, T, RR>(m, cs, dcs); });
 }
 
 void multi_dslash_launch(const MultiDslash &m, hipStream_t s)
 {
-    multi_dispatch(m.prec, m.recon12, m.R,
+    multi_dispatch(m.prec, m.recon12, m.recon8, m.R,
                    [&]<typename SS, typename LS, typename T, int RR>() { multi_go<SS, LS, T, RR>(m, s); });
 }
 
@@ -1097,7 +1161,7 @@ void dslash_cost(tm_ctx *c, const DslashCall &dc, double &bytes, double &flops)
     double lb;
     const int par = recon12_ok(c, dc.spinor_prec) && !dc.links18 ? 6 : 9;
     switch (dc.spinor_prec) {
-    case TM_F64: lb = 16.0 * par; break;
+    case TM_F64: lb = !dc.links18 && recon8_wanted(c) && c->links8_usable ? 64.0 : 16.0 * par; break;
     case TM_F32: lb = 8.0 * par; break;
     default: lb = c->half_links_f32 ? 8.0 * 9 : 4.0 * par; break;
     }
@@ -1132,7 +1196,9 @@ void launch_dslash(tm_ctx *c, const DslashCall &dc, hipStream_t s)
     // FP64 (the plain solver and the reliable updates): 12-parameter FP64
     // links in the context's format, the third row rebuilt exactly up to rounding
     case TM_F64:
-        if (recon12_ok(c, TM_F64) && !dc.links18) {
+        if (!dc.links18 && recon8_wanted(c) && ensure_links8d(c, s)) {
+            launch_rhs<double2, L8D, double>(c, dc, s);
+        } else if (recon12_ok(c, TM_F64) && !dc.links18) {
             ensure_links12d(c, s);
             launch_rhs<double2, L12D, double>(c, dc, s);
         } else {

@@ -316,7 +316,8 @@ SolveOut fgmres_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void
         upload(target2, t2.data(), sizeof(double) * nrhs, s);
     }
     int restarts = 0, total = 0;
-    bool nan = false;
+    bool nan = false, fallback = false;
+    std::vector<double> prev2(nrhs, 0.0);
     while (true) {
         // V_0 = b - M x, beta = |V_0|
         apply_M(f, w, x, epsp);
@@ -324,15 +325,22 @@ SolveOut fgmres_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void
         launch_axpby_host(c, V, w, TM_F64, 2 * nrhs, -1.0, 1.0, s);
         mdot(f, V, vs, 1, V, st.dots, m + 1, 0);
         download(c, h_d.data(), st.dots, sizeof(double2) * nrhs * (m + 1), s);
-        bool any = false;
+        bool any = false, stalled = false;
         for (int r = 0; r < nrhs; r++) {
             beta2[r] = h_d[(size_t)r * (m + 1)].x;
             if (!std::isfinite(beta2[r])) nan = true;
             act[r] = beta2[r] > t2[r] ? 1 : 0;
             any |= act[r] != 0;
             res2[r] = beta2[r];
+            // a full restart cycle that did not halve the residual
+            if (ptc && restarts > 0 && act[r] && beta2[r] > 0.25 * prev2[r]) stalled = true;
+            prev2[r] = beta2[r];
         }
         if (nan || !any || total >= p.maxiter) break;
+        if (stalled) {
+            fallback = true;
+            break;
+        }
         std::vector<double2> g0((size_t)nrhs * (m + 1), make_double2(0, 0));
         for (int r = 0; r < nrhs; r++) {
             const double be_ = std::sqrt(beta2[r]);
@@ -384,6 +392,39 @@ SolveOut fgmres_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void
             maxpy(f, x, V, vs, j, y, m, 1.0);
         restarts++;
     }
+    // Fallback when the preconditioned iteration stalls: the remaining
+    // correction M d = b - M x (in V_0, unscaled) by the plain mixed-precision
+    // CG (FP16 storage, FP64 reliable updates) to the tolerance that brings
+    // every right-hand side to tol, then x += d and the true residual again.
+    std::vector<tm_solve_stats> cg_st;
+    if (fallback && !nan) {
+        double tol_d = 1.0;
+        for (int r = 0; r < nrhs; r++)
+            if (beta2[r] > t2[r]) tol_d = std::min(tol_d, p.tol * std::sqrt(bn2[r] / beta2[r]));
+        tm_solve_params pc = p;
+        pc.solver = TM_CG_MIXED;
+        pc.inner_prec = TM_F16;
+        pc.tol = tol_d;
+        pc.maxiter = std::max(1, p.maxiter - total) * 8;
+        pc.check_every = 0;
+        pc.delta = 0;
+        double2 *d = (double2 *)ws_get(c, "fg_d", sizeof(double2) * vs);
+        double2 *rr = (double2 *)ws_get(c, "fg_r", sizeof(double2) * vs);
+        copy_field(rr, V, 2 * hb, s);
+        SolveOut cg = solve_halves(c, d, d + f.hs, rr, rr + f.hs, nrhs, pc, s);
+        if (cg.status == TM_ERR_NAN) nan = true;
+        cg_st = cg.st;
+        launch_axpby_host(c, x, d, TM_F64, 2 * nrhs, 1.0, 1.0, s);
+        apply_M(f, w, x, epsp);
+        copy_field(V, b, 2 * hb, s);
+        launch_axpby_host(c, V, w, TM_F64, 2 * nrhs, -1.0, 1.0, s);
+        mdot(f, V, vs, 1, V, st.dots, m + 1, 0);
+        download(c, h_d.data(), st.dots, sizeof(double2) * nrhs * (m + 1), s);
+        for (int r = 0; r < nrhs; r++) {
+            beta2[r] = h_d[(size_t)r * (m + 1)].x;
+            if (!std::isfinite(beta2[r])) nan = true;
+        }
+    }
     // solution out; true residual already in beta2 (b - M x of the last x)
     copy_field(xe, x, hb, s);
     copy_field(xo, x + f.hs, hb, s);
@@ -393,8 +434,9 @@ SolveOut fgmres_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void
     for (int r = 0; r < nrhs; r++) {
         tm_solve_stats &q = out.st[r];
         q = tm_solve_stats{};
-        q.iters = iters[r];
+        q.iters = iters[r] + (cg_st.empty() ? 0 : cg_st[r].iters);
         q.n_reliable = restarts;
+        q.fallback = fallback ? 1 : 0;
         q.true_rel_res = std::sqrt(beta2[r] / bn2[r]);
         q.iter_rel_res = q.true_rel_res;
         q.converged = q.true_rel_res <= p.tol ? 1 : 0;

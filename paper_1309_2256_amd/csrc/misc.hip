@@ -160,6 +160,78 @@ __global__ __launch_bounds__(kBlock) void k_d2d_rows(double2 *out, const double2
     out[idx] = in[(d * 9 + k) * vh + i];
 }
 
+// 8-parameter FP64 links (appendix A.1; the paper stores 8 real numbers per
+// link and recomputes the full matrix in the kernel).  Of U = [[a1 a2 a3],
+// [b1 b2 b3], [c1 c2 c3]] in SU(3) the form keeps the complex a2, a3, b1 and
+// the phases of a1 and c1: |a1| and |c1| follow from the unit first row and
+// first column, and the 2x2 block from conj(U) = cofactor matrix (U^-1 = U^dag,
+// det U = 1), a linear system in (b2, b3) and in (c2, c3) with determinant
+// n = |a2|^2 + |a3|^2.  |c1|^2 = n - |b1|^2 loses accuracy when |c1| << |b1|;
+// such links are stored as W = -(rows 1, 3, 2 of U) (again special unitary,
+// its first-column entries below a1 being -c1, -b1), flagged by adding 8 to
+// the stored phase of W's c1, and the kernel swaps and negates the rows back.
+// The boundary factor folded into the stored links (f = -1 makes det = -1) is
+// removed here and restored by the kernel on the links that cross the
+// boundary.  Layout [8 directions][4][vh] double2: a2, a3, b1, (arg a1, arg c1
+// [+ 8]).  part[block] = smallest n of the block.
+__global__ __launch_bounds__(kBlock) void k_d2r8(double2 *out, const double2 *in, Geo g, int p, int t_bc,
+                                                 double *part)
+{
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long vh = g.vh;
+    double nmin = INFINITY;
+    if (idx < 8 * vh) {
+        const long i = idx % vh, d = idx / vh;
+        int x, y, z, t;
+        eo_coords(g, p, (int)i, x, y, z, t);
+        const bool cross = (d == 3 && t == g.L[3] - 1) || (d == 7 && t == 0);
+        const double f = cross ? (double)t_bc : 1.0;
+        cx<double> u[9];
+        for (int k = 0; k < 9; k++) {
+            const double2 v = in[(d * 9 + k) * vh + i];
+            u[k] = {f * v.x, f * v.y};
+        }
+        const bool swap = u[6].r * u[6].r + u[6].i * u[6].i < u[3].r * u[3].r + u[3].i * u[3].i;
+        if (swap) {
+            for (int k = 0; k < 3; k++) {
+                const cx<double> r1 = u[3 + k], r2 = u[6 + k];
+                u[k] = {-u[k].r, -u[k].i};
+                u[3 + k] = {-r2.r, -r2.i};
+                u[6 + k] = {-r1.r, -r1.i};
+            }
+        }
+        double2 *o = out + d * 4 * vh + i;
+        o[0] = make_double2(u[1].r, u[1].i);
+        o[vh] = make_double2(u[2].r, u[2].i);
+        o[2 * vh] = make_double2(u[3].r, u[3].i);
+        o[3 * vh] = make_double2(atan2(u[0].i, u[0].r), atan2(u[6].i, u[6].r) + (swap ? 8.0 : 0.0));
+        nmin = u[1].r * u[1].r + u[1].i * u[1].i + u[2].r * u[2].r + u[2].i * u[2].i;
+        if (nmin != nmin) nmin = 0;  // NaN entries: the form is not used
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = nmin;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_min_finish(const double *part, long n, double *out)
+{
+    double m = INFINITY;
+    for (long k = threadIdx.x; k < n; k += kBlock) m = fmin(m, part[k]);
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // and rounded once to FP32
 __global__ __launch_bounds__(kBlock) void k_d2f_rows(float2 *out, const double2 *in, long vh)
 {
@@ -388,6 +460,27 @@ void launch_links_to_r12(tm_ctx *c, hipStream_t s)
         hipLaunchKernelGGL(k_d2h_rows, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                            (h2 *)c->links12[p], (const double2 *)c->links64[p], (long)c->geo.vh);
     TM_HIP(hipGetLastError());
+}
+
+double launch_links_to_r8d(tm_ctx *c, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TM_HIP(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        throw TmError{TM_ERR_UNSUPPORTED, "8-parameter links are built on first use outside graph capture"};
+    const long n = 8L * c->geo.vh;
+    const long nb = (n + kBlock - 1) / kBlock;
+    double *part = (double *)ws_get(c, "r8_part", sizeof(double) * (2 * nb + 1));
+    for (int p = 0; p < 2; p++)
+        hipLaunchKernelGGL(k_d2r8, dim3((unsigned)nb), dim3(kBlock), 0, s, (double2 *)c->links8d[p],
+                           (const double2 *)c->links64[p], c->geo, p, c->t_bc, part + 1 + p * nb);
+    TM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(kBlock), 0, s, (const double *)(part + 1), 2 * nb, part);
+    TM_HIP(hipGetLastError());
+    double nmin = 0;
+    TM_HIP(hipMemcpyAsync(&nmin, part, sizeof(double), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    return nmin;
 }
 
 void launch_links_to_r12d(tm_ctx *c, hipStream_t s)

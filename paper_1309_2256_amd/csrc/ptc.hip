@@ -140,6 +140,110 @@ __global__ __launch_bounds__(kBlock) void k_ptc_mix(const S *in_same, const S *i
     }
 }
 
+// ---------------------------------------------------------------- matrix cores
+// The spin mixing u = A G at one site, A the 36x36 complex block matrix
+// A[(k,a)][(k',b)] = A[k][k'][a][b] and G[(k',b)][c] = (T_k' psi)_{b c}, as a
+// real product on v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation)
+// with real and imaginary parts interleaved: row 2i+ri, column 2j+rj of the
+// real A is Re A_ij (ri = rj), -Im A_ij (ri = 0, rj = 1), Im A_ij (ri = 1,
+// rj = 0); row 2j+rj of the real G holds Re / Im G_j.  72 x 72 padded to 5
+// row tiles of 16 and 3 K steps of 32.  One wave takes 16 sites (the MFMA
+// columns) and one colour c at a time.  Operand lanes: A[i][k] in lane
+// (i = l % 16, g = l / 16) at k = 8g + j; B[k][n] in lane (n = l % 16, g) at
+// k = 8g + j; D[i][n] in lane (n, g) at i = 4g + v (v = 0..3).  So lane
+// (n, g) at K step q holds path k' = 4q + g of site n (8 values: 4 spins,
+// re/im), and its D of row tile t holds complex rows 8t + 2g, 8t + 2g + 1.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMT = 5, kKS = 3;  // row tiles, K steps
+
+// frag[(t * kKS + q) * 64 + lane] = the A operand of row tile t, K step q
+__global__ void k_ptc_afrag(const float2 *A, bf16x8 *frag)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kMT * kKS * 64) return;
+    const int lane = idx % 64, tq = idx / 64, t = tq / kKS, q = tq % kKS;
+    const int R = 16 * t + lane % 16, i = R / 2, ri = R % 2;
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int K = 32 * q + 8 * (lane / 16) + j, jj = K / 2, rj = K % 2;
+        float a = 0.f;
+        if (i < 36 && jj < 36) {
+            const float2 w = A[((i / 4) * 9 + jj / 4) * 16 + 4 * (i % 4) + jj % 4];
+            a = ri == rj ? w.x : (ri == 0 ? -w.y : w.y);
+        }
+        v[j] = (__bf16)a;
+    }
+    frag[idx] = v;
+}
+
+// u_k (parity p) for all nine k on the matrix cores; block of 4 waves = 64
+// sites, grid (site blocks of 64, nrhs).  u layout [9][nrhs][12][vh].
+template <typename S>
+__global__ __launch_bounds__(kBlock, 2) void k_ptc_mix_mfma(const S *in_same, const S *in_other,
+                                                            const float2 *links, const bf16x8 *frag, float2 *u,
+                                                            Geo g, int p, int nrhs)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane % 16, grp = lane / 16;
+    const int i_raw = blockIdx.x * 64 + w * 16 + n;
+    const bool valid = i_raw < g.vh;
+    const int i = valid ? i_raw : g.vh - 1;
+    const int r = blockIdx.y;
+    const size_t fs = (size_t)12 * g.vh, vh = (size_t)g.vh;
+    const S *same = in_same + r * fs, *other = in_other + r * fs;
+    int x, y, z, t;
+    eo_coords(g, p, i, x, y, z, t);
+    // B operands: the transports of this lane's paths, per colour
+    bf16x8 bq[3][kKS];
+#pragma unroll
+    for (int q = 0; q < kKS; q++) {
+        const int kp = 4 * q + grp;
+        cx<float> gv[12];
+        if (kp <= 8) {
+            transport_at<S>(gv, kp, same, other, links, g, i, x, y, z, t);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 12; e++) gv[e] = {0.f, 0.f};
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                bq[c][q][2 * b] = (__bf16)gv[3 * b + c].r;
+                bq[c][q][2 * b + 1] = (__bf16)gv[3 * b + c].i;
+            }
+    }
+    bf16x8 af[kMT][kKS];
+#pragma unroll
+    for (int tt = 0; tt < kMT; tt++)
+#pragma unroll
+        for (int q = 0; q < kKS; q++) af[tt][q] = frag[(tt * kKS + q) * 64 + lane];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        f32x4 acc[kMT];
+#pragma unroll
+        for (int tt = 0; tt < kMT; tt++) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < kKS; q++)
+#pragma unroll
+            for (int tt = 0; tt < kMT; tt++)
+                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[tt][q], bq[c][q], acc[tt], 0, 0, 0);
+        if (valid) {
+#pragma unroll
+            for (int tt = 0; tt < kMT; tt++)
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    const int cr = 8 * tt + 2 * grp + e, k = cr / 4, a = cr % 4;
+                    if (k < 9)
+                        u[(((size_t)k * nrhs + r) * 12 + 3 * a + c) * vh + i] =
+                            make_float2(acc[tt][2 * e], acc[tt][2 * e + 1]);
+                }
+        }
+    }
+}
+
 // out (parity p) = u_0 + sum_{k >= 1} T_k u_k; u_same / u_other: the u
 // fields of parity p / 1 - p.  grid (site blocks, nrhs).
 template <typename SO>
@@ -213,6 +317,42 @@ __global__ void k_ptc_loss_finish(const double *part0, const double *part1, cons
         l += s / en2[r];
     }
     *loss = l / nrhs;
+}
+
+// Residual loss: w -= r (r in the pair-store precision), partial |w|^2 per
+// block.  grid (blocks, nrhs); part [nrhs][nblk].
+template <typename SR>
+__global__ __launch_bounds__(kBlock) void k_ptc_resid(float2 *w, const SR *r, double *part, size_t n, int nblk)
+{
+    const size_t base = (size_t)blockIdx.y * n;
+    double acc = 0;
+    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (size_t)gridDim.x * kBlock) {
+        const float2 o = w[base + k];
+        const cx<float> rv = ldT<float>(r, base + k);
+        const float dr = o.x - rv.r, di = o.y - rv.i;
+        acc += (double)dr * dr + (double)di * di;
+        w[base + k] = make_float2(dr, di);
+    }
+    __shared__ double red[kBlock / 64];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int ww = 0; ww < kBlock / 64; ww++) s += red[ww];
+        part[(size_t)blockIdx.y * nblk + blockIdx.x] = s;
+    }
+}
+
+// v *= 2 / (nrhs |r_b|^2) for sample b = blockIdx.y
+__global__ __launch_bounds__(kBlock) void k_ptc_scale(float2 *v, const double *rn2, size_t n)
+{
+    const size_t base = (size_t)blockIdx.y * n;
+    const float sc = (float)(2.0 / (gridDim.y * rn2[blockIdx.y]));
+    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (size_t)gridDim.x * kBlock) {
+        const float2 o = v[base + k];
+        v[base + k] = make_float2(sc * o.x, sc * o.y);
+    }
 }
 
 // Partial dl/dA[k][k'] on parity p: sum over the block's sites (grid-stride)
@@ -375,6 +515,11 @@ void run_update(tm_ctx *c, int mode, const AdamArgs &ad, hipStream_t s)
                        wbuf(c, "ptc_W2"), wbuf(c, "ptc_G1"), wbuf(c, "ptc_G2"), wbuf(c, "ptc_M1"), wbuf(c, "ptc_V1"),
                        wbuf(c, "ptc_M2"), wbuf(c, "ptc_V2"), ad, (float2 *)ws_get(c, "ptc_A", sizeof(float2) * 81 * 16));
     TM_HIP(hipGetLastError());
+    // BF16 operand fragments of A for the matrix-core spin mixing
+    hipLaunchKernelGGL(k_ptc_afrag, dim3((kMT * kKS * 64 + 255) / 256), dim3(256), 0, s,
+                       (const float2 *)ws_get(c, "ptc_A", sizeof(float2) * 81 * 16),
+                       (bf16x8 *)ws_get(c, "ptc_Afrag", sizeof(bf16x8) * kMT * kKS * 64));
+    TM_HIP(hipGetLastError());
 }
 
 // N(in) for nrhs fields given as FP32-or-BF16 halves (S) -> FP32 halves
@@ -387,11 +532,21 @@ void forward_t(tm_ctx *c, const void *in_e, const void *in_o, float2 *out_e, flo
                     (float2 *)ws_get(c, "ptc_u1", sizeof(float2) * 9 * fl)};
     const float2 *A = (const float2 *)ws_get(c, "ptc_A", sizeof(float2) * 81 * 16);
     const S *in[2] = {(const S *)in_e, (const S *)in_o};
-    dim3 gm(site_blocks(c), nrhs, 9 / kKG);
-    for (int p = 0; p < 2; p++) {
-        hipLaunchKernelGGL(k_ptc_mix<S>, gm, dim3(kBlock), 0, s, in[p], in[1 - p], (const float2 *)c->links32[p], A,
-                           u[p], c->geo, p, nrhs);
-        TM_HIP(hipGetLastError());
+    if (c->ptc_arith == TM_BF16) {
+        const bf16x8 *frag = (const bf16x8 *)ws_get(c, "ptc_Afrag", sizeof(bf16x8) * kMT * kKS * 64);
+        dim3 gm((c->geo.vh + 63) / 64, nrhs);
+        for (int p = 0; p < 2; p++) {
+            hipLaunchKernelGGL(k_ptc_mix_mfma<S>, gm, dim3(kBlock), 0, s, in[p], in[1 - p],
+                               (const float2 *)c->links32[p], frag, u[p], c->geo, p, nrhs);
+            TM_HIP(hipGetLastError());
+        }
+    } else {
+        dim3 gm(site_blocks(c), nrhs, 9 / kKG);
+        for (int p = 0; p < 2; p++) {
+            hipLaunchKernelGGL(k_ptc_mix<S>, gm, dim3(kBlock), 0, s, in[p], in[1 - p], (const float2 *)c->links32[p],
+                               A, u[p], c->geo, p, nrhs);
+            TM_HIP(hipGetLastError());
+        }
     }
     float2 *out[2] = {out_e, out_o};
     dim3 gg(site_blocks(c), nrhs);
@@ -413,9 +568,15 @@ void forward(tm_ctx *c, int in_prec, const void *in_e, const void *in_o, float2 
 
 // loss (device scalar) and dl/dA of the batch mean for nrhs pairs (r, e)
 // given as halves in precision prec; en2: device |e_b|^2
+// LossKind::error: l = |N(r) - e|^2 / |e|^2, en2 = |e|^2;
+// LossKind::residual: l = |M N(r) - r|^2 / |r|^2 with M = M(epsp) in FP32
+// (the Dslash of the FP32 solver), en2 = |r|^2, e unused:
+//   w = M out - r,  dl/d(conj out) = M^dag w / |r|^2
+enum class LossKind { error = 0, residual = 1 };
+
 template <typename S>
-void loss_grad_t(tm_ctx *c, const void *r_e, const void *r_o, const void *e_e, const void *e_o, const double *en2,
-                 int nrhs, double *loss, hipStream_t s)
+void loss_grad_t(tm_ctx *c, LossKind kind, double epsp, const void *r_e, const void *r_o, const void *e_e,
+                 const void *e_o, const double *en2, int nrhs, double *loss, hipStream_t s)
 {
     const size_t fl = (size_t)12 * c->geo.vh * nrhs;
     float2 *out[2] = {(float2 *)ws_get(c, "ptc_out0", sizeof(float2) * fl),
@@ -426,11 +587,33 @@ void loss_grad_t(tm_ctx *c, const void *r_e, const void *r_o, const void *e_e, c
                        (double *)ws_get(c, "ptc_lpart1", sizeof(double) * nbd * nrhs)};
     float2 *dl[2] = {(float2 *)ws_get(c, "ptc_dl0", sizeof(float2) * fl),
                      (float2 *)ws_get(c, "ptc_dl1", sizeof(float2) * fl)};
-    const S *ee[2] = {(const S *)e_e, (const S *)e_o};
-    for (int p = 0; p < 2; p++) {
-        hipLaunchKernelGGL(k_ptc_delta<S>, dim3(nbd, nrhs), dim3(kBlock), 0, s, (const float2 *)out[p], ee[p],
-                           en2, dl[p], part[p], (size_t)12 * c->geo.vh, nbd);
-        TM_HIP(hipGetLastError());
+    if (kind == LossKind::error) {
+        const S *ee[2] = {(const S *)e_e, (const S *)e_o};
+        for (int p = 0; p < 2; p++) {
+            hipLaunchKernelGGL(k_ptc_delta<S>, dim3(nbd, nrhs), dim3(kBlock), 0, s, (const float2 *)out[p], ee[p],
+                               en2, dl[p], part[p], (size_t)12 * c->geo.vh, nbd);
+            TM_HIP(hipGetLastError());
+        }
+    } else {
+        float2 *w[2] = {(float2 *)ws_get(c, "ptc_w0", sizeof(float2) * fl),
+                        (float2 *)ws_get(c, "ptc_w1", sizeof(float2) * fl)};
+        const double k = c->kappa;
+        // w = M out (per parity: R(eps) out_p - kappa Hop out_{1-p}), then w -= r
+        for (int p = 0; p < 2; p++)
+            op_dslash(c, w[p], out[1 - p], out[p], nrhs, TM_F32, p, 0, sd_scalar(-k), sd_twist(epsp), s);
+        const S *rr[2] = {(const S *)r_e, (const S *)r_o};
+        for (int p = 0; p < 2; p++) {
+            hipLaunchKernelGGL(k_ptc_resid<S>, dim3(nbd, nrhs), dim3(kBlock), 0, s, w[p], rr[p], part[p],
+                               (size_t)12 * c->geo.vh, nbd);
+            TM_HIP(hipGetLastError());
+        }
+        // dl = M^dag w = R(-eps) w_p - kappa Hop^dag w_{1-p}, scaled by 2 / (n |r|^2)
+        for (int p = 0; p < 2; p++)
+            op_dslash(c, dl[p], w[1 - p], w[p], nrhs, TM_F32, p, 1, sd_scalar(-k), sd_twist(-epsp), s);
+        for (int p = 0; p < 2; p++) {
+            hipLaunchKernelGGL(k_ptc_scale, dim3(nbd, nrhs), dim3(kBlock), 0, s, dl[p], en2, (size_t)12 * c->geo.vh);
+            TM_HIP(hipGetLastError());
+        }
     }
     hipLaunchKernelGGL(k_ptc_loss_finish, dim3(1), dim3(64), 0, s, (const double *)part[0], (const double *)part[1],
                        en2, nbd, nrhs, loss);
@@ -449,13 +632,20 @@ void loss_grad_t(tm_ctx *c, const void *r_e, const void *r_o, const void *e_e, c
     TM_HIP(hipGetLastError());
 }
 
-void loss_grad(tm_ctx *c, int prec, const void *r_e, const void *r_o, const void *e_e, const void *e_o,
-               const double *en2, int nrhs, double *loss, hipStream_t s)
+void loss_grad(tm_ctx *c, LossKind kind, double epsp, int prec, const void *r_e, const void *r_o, const void *e_e,
+               const void *e_o, const double *en2, int nrhs, double *loss, hipStream_t s)
 {
     if (prec == TM_BF16)
-        loss_grad_t<b2>(c, r_e, r_o, e_e, e_o, en2, nrhs, loss, s);
+        loss_grad_t<b2>(c, kind, epsp, r_e, r_o, e_e, e_o, en2, nrhs, loss, s);
     else
-        loss_grad_t<float2>(c, r_e, r_o, e_e, e_o, en2, nrhs, loss, s);
+        loss_grad_t<float2>(c, kind, epsp, r_e, r_o, e_e, e_o, en2, nrhs, loss, s);
+}
+
+LossKind loss_kind(int loss)
+{
+    TM_REQUIRE(loss == TM_PTC_LOSS_ERROR || loss == TM_PTC_LOSS_RESIDUAL,
+               "loss must be TM_PTC_LOSS_ERROR or TM_PTC_LOSS_RESIDUAL");
+    return loss == TM_PTC_LOSS_ERROR ? LossKind::error : LossKind::residual;
 }
 
 template <typename F>
@@ -522,6 +712,15 @@ extern "C" int tm_ptc_set_weights(tm_ctx *c, int nc, const double *W1, const dou
         reset_adam(c, s);
         run_update(c, 2, AdamArgs{}, s);
         TM_HIP(hipStreamSynchronize(s));
+        return TM_OK;
+    });
+}
+
+extern "C" int tm_ptc_set_arith(tm_ctx *c, int prec)
+{
+    return guard(c, [&]() {
+        TM_REQUIRE(prec == TM_F32 || prec == TM_BF16, "network arithmetic must be TM_F32 or TM_BF16");
+        c->ptc_arith = prec;
         return TM_OK;
     });
 }
@@ -625,30 +824,37 @@ extern "C" int tm_ptc_apply(tm_ctx *c, double *out, const double *in, int nrhs, 
     });
 }
 
-extern "C" int tm_ptc_loss_grad(tm_ctx *c, const double *r, const double *e, int npairs, double *loss, double *G1,
-                                double *G2, tm_stream stream)
+extern "C" int tm_ptc_loss_grad(tm_ctx *c, int loss_kind_, int mu_sign, const double *r, const double *e,
+                                int npairs, double *loss, double *G1, double *G2, tm_stream stream)
 {
     return guard(c, [&]() {
-        TM_REQUIRE(r && e && loss, "null pointer");
+        const LossKind kind = loss_kind(loss_kind_);
+        TM_REQUIRE(r && loss && (e || kind == LossKind::residual), "null pointer");
         TM_REQUIRE(npairs >= 1, "npairs must be >= 1");
+        TM_REQUIRE(mu_sign == 1 || mu_sign == -1, "mu_sign must be +1 or -1");
         TM_REQUIRE(c->have_gauge, "no gauge field set");
         TM_REQUIRE(c->ptc_nc > 0, "no network weights set");
         hipStream_t s = hs(stream);
         const size_t hb = field_bytes(c, TM_F32, npairs);
         void *re = ws_get(c, "pl_re", hb), *ro = ws_get(c, "pl_ro", hb);
-        void *ee = ws_get(c, "pl_ee", hb), *eo = ws_get(c, "pl_eo", hb);
+        void *ee = nullptr, *eo = nullptr;
         launch_pack(c, re, ro, r, npairs, TM_F32, nullptr, s);
-        launch_pack(c, ee, eo, e, npairs, TM_F32, nullptr, s);
-        // |e|^2 of the FP32 fields the loss uses
+        if (kind == LossKind::error) {
+            ee = ws_get(c, "pl_ee", hb);
+            eo = ws_get(c, "pl_eo", hb);
+            launch_pack(c, ee, eo, e, npairs, TM_F32, nullptr, s);
+        }
+        // |e|^2 (error loss) or |r|^2 (residual loss) of the FP32 fields the loss uses
+        const void *ne = kind == LossKind::error ? ee : re, *no = kind == LossKind::error ? eo : ro;
         double *en2 = (double *)ws_get(c, "pl_en2", sizeof(double) * npairs);
-        std::vector<double> a = norms_host(c, ee, TM_F32, npairs, s), b = norms_host(c, eo, TM_F32, npairs, s);
+        std::vector<double> a = norms_host(c, ne, TM_F32, npairs, s), b = norms_host(c, no, TM_F32, npairs, s);
         for (int k = 0; k < npairs; k++) {
             a[k] += b[k];
-            TM_REQUIRE(a[k] > 0, "e = 0 in a pair");
+            TM_REQUIRE(a[k] > 0, "zero field in a pair");
         }
         upload(en2, a.data(), sizeof(double) * npairs, s);
         double *dl = (double *)ws_get(c, "pl_loss", sizeof(double));
-        loss_grad(c, TM_F32, re, ro, ee, eo, en2, npairs, dl, s);
+        loss_grad(c, kind, eps_of(c, mu_sign), TM_F32, re, ro, ee, eo, en2, npairs, dl, s);
         run_update(c, 0, AdamArgs{}, s);
         download(c, loss, dl, sizeof(double), s);
         const int nc = c->ptc_nc;
@@ -670,9 +876,51 @@ extern "C" int tm_ptc_pairs_reserve(tm_ctx *c, int capacity, int store_prec)
         ws_get(c, "ptc_pairs_r", 2 * one * capacity);
         ws_get(c, "ptc_pairs_e", 2 * one * capacity);
         ws_get(c, "ptc_pairs_en2", sizeof(double) * capacity);
+        ws_get(c, "ptc_pairs_rn2", sizeof(double) * capacity);
         return TM_OK;
     });
 }
+
+namespace {
+
+// append n pairs given as FP64 half fields (r_e, r_o, e_e, e_o; [n][12][vh]
+// each) to the store, converted to its precision; pairs with r = 0 or
+// e = 0 in the stored precision are dropped when skip_zero, else an error.
+// Returns the number appended.
+int store_pairs(tm_ctx *c, const void *r_e, const void *r_o, const void *e_e, const void *e_o, int n, bool skip_zero,
+                hipStream_t s)
+{
+    const size_t one = store_half_bytes(c), cap = (size_t)c->ptc_cap;
+    const size_t in1 = field_bytes(c, TM_F64, 1);
+    char *R = (char *)ws_get(c, "ptc_pairs_r", 2 * one * cap), *E = (char *)ws_get(c, "ptc_pairs_e", 2 * one * cap);
+    double *en2 = (double *)ws_get(c, "ptc_pairs_en2", sizeof(double) * cap);
+    double *rn2 = (double *)ws_get(c, "ptc_pairs_rn2", sizeof(double) * cap);
+    int added = 0;
+    for (int k = 0; k < n; k++) {
+        TM_REQUIRE(c->ptc_n + 1 <= c->ptc_cap, "pair store capacity exceeded");
+        const size_t at = one * c->ptc_n;
+        launch_copy_convert(c, R + at, c->ptc_store, (const char *)r_e + k * in1, TM_F64, 1, nullptr, s);
+        launch_copy_convert(c, R + one * cap + at, c->ptc_store, (const char *)r_o + k * in1, TM_F64, 1, nullptr, s);
+        launch_copy_convert(c, E + at, c->ptc_store, (const char *)e_e + k * in1, TM_F64, 1, nullptr, s);
+        launch_copy_convert(c, E + one * cap + at, c->ptc_store, (const char *)e_o + k * in1, TM_F64, 1, nullptr, s);
+        const double ne = norms_host(c, E + at, c->ptc_store, 1, s)[0] +
+                          norms_host(c, E + one * cap + at, c->ptc_store, 1, s)[0];
+        const double nr = norms_host(c, R + at, c->ptc_store, 1, s)[0] +
+                          norms_host(c, R + one * cap + at, c->ptc_store, 1, s)[0];
+        const bool ok = ne > 0 && nr > 0 && std::isfinite(ne) && std::isfinite(nr);
+        if (!ok) {
+            TM_REQUIRE(skip_zero, "r = 0, e = 0 or non-finite in a pair");
+            continue;
+        }
+        upload(en2 + c->ptc_n, &ne, sizeof(double), s);
+        upload(rn2 + c->ptc_n, &nr, sizeof(double), s);
+        c->ptc_n++;
+        added++;
+    }
+    return added;
+}
+
+}  // namespace
 
 extern "C" int tm_ptc_pairs_add(tm_ctx *c, const double *r, const double *e, int n, tm_stream stream)
 {
@@ -682,19 +930,54 @@ extern "C" int tm_ptc_pairs_add(tm_ctx *c, const double *r, const double *e, int
         TM_REQUIRE(c->ptc_cap > 0, "no pair store reserved");
         TM_REQUIRE(c->ptc_n + n <= c->ptc_cap, "pair store capacity exceeded");
         hipStream_t s = hs(stream);
-        const size_t one = store_half_bytes(c), cap = (size_t)c->ptc_cap;
-        char *R = (char *)ws_get(c, "ptc_pairs_r", 2 * one * cap), *E = (char *)ws_get(c, "ptc_pairs_e", 2 * one * cap);
-        const size_t at = one * c->ptc_n;
-        launch_pack(c, R + at, R + one * cap + at, r, n, c->ptc_store, nullptr, s);
-        launch_pack(c, E + at, E + one * cap + at, e, n, c->ptc_store, nullptr, s);
-        std::vector<double> a = norms_host(c, E + at, c->ptc_store, n, s);
-        std::vector<double> b = norms_host(c, E + one * cap + at, c->ptc_store, n, s);
-        for (int k = 0; k < n; k++) {
-            a[k] += b[k];
-            TM_REQUIRE(a[k] > 0 && std::isfinite(a[k]), "e = 0 or non-finite in a pair");
+        const size_t hb = field_bytes(c, TM_F64, n);
+        void *re = ws_get(c, "pp_re", hb), *ro = ws_get(c, "pp_ro", hb);
+        void *ee = ws_get(c, "pp_ee", hb), *eo = ws_get(c, "pp_eo", hb);
+        launch_pack(c, re, ro, r, n, TM_F64, nullptr, s);
+        launch_pack(c, ee, eo, e, n, TM_F64, nullptr, s);
+        store_pairs(c, re, ro, ee, eo, n, false, s);
+        return TM_OK;
+    });
+}
+
+extern "C" int tm_ptc_pairs_from_solve(tm_ctx *c, const double *b, int nrhs, const tm_solve_params *p,
+                                       const int *iters, int n_iters, int *added, tm_stream stream)
+{
+    return guard(c, [&]() {
+        TM_REQUIRE(b && p && iters, "null pointer");
+        TM_REQUIRE(nrhs >= 1 && n_iters >= 1, "nrhs and n_iters must be >= 1");
+        TM_REQUIRE(c->have_gauge, "no gauge field set");
+        TM_REQUIRE(c->ptc_cap > 0, "no pair store reserved");
+        for (int j = 0; j < n_iters; j++) TM_REQUIRE(iters[j] >= 1, "iteration counts must be >= 1");
+        TM_REQUIRE(p->solver == TM_CG_F64 || p->solver == TM_CG_MIXED, "pairs come from TM_CG_F64 or TM_CG_MIXED");
+        hipStream_t s = hs(stream);
+        const size_t hb = field_bytes(c, TM_F64, nrhs);
+        void *be = ws_get(c, "pp_be", hb), *bo = ws_get(c, "pp_bo", hb);
+        void *se = ws_get(c, "pp_se", hb), *so = ws_get(c, "pp_so", hb);
+        void *xe = ws_get(c, "pp_xe", hb), *xo = ws_get(c, "pp_xo", hb);
+        void *re = ws_get(c, "pp_re", hb), *ro = ws_get(c, "pp_ro", hb);
+        launch_pack(c, be, bo, b, nrhs, TM_F64, nullptr, s);
+        // x* to the solver's tolerance
+        SolveOut full = solve_halves(c, se, so, be, bo, nrhs, *p, s);
+        TM_REQUIRE(full.status == TM_OK, "the reference solve did not converge");
+        const double epsp = eps_of(c, p->mu_sign), k = c->kappa;
+        int n_add = 0;
+        for (int j = 0; j < n_iters; j++) {
+            tm_solve_params pk = *p;
+            pk.maxiter = iters[j];
+            SolveOut it = solve_halves(c, xe, xo, be, bo, nrhs, pk, s);
+            TM_REQUIRE(it.status == TM_OK || it.status == TM_ERR_NOCONV, "NaN/Inf in an iterate");
+            // r = b - M x with all 18 link parameters; e = x* - x (in place in x)
+            for (int par = 0; par < 2; par++)
+                op_dslash(c, par ? ro : re, par ? xe : xo, par ? xo : xe, nrhs, TM_F64, par, 0, sd_scalar(-k),
+                          sd_twist(epsp), s, true);
+            launch_axpby_host(c, re, be, TM_F64, nrhs, 1.0, -1.0, s);
+            launch_axpby_host(c, ro, bo, TM_F64, nrhs, 1.0, -1.0, s);
+            launch_axpby_host(c, xe, se, TM_F64, nrhs, 1.0, -1.0, s);
+            launch_axpby_host(c, xo, so, TM_F64, nrhs, 1.0, -1.0, s);
+            n_add += store_pairs(c, re, ro, xe, xo, nrhs, true, s);
         }
-        upload((double *)ws_get(c, "ptc_pairs_en2", sizeof(double) * cap) + c->ptc_n, a.data(), sizeof(double) * n, s);
-        c->ptc_n += n;
+        if (added) *added = n_add;
         return TM_OK;
     });
 }
@@ -710,13 +993,16 @@ extern "C" int tm_ptc_train(tm_ctx *c, const tm_ptc_train_params *p, tm_ptc_trai
         TM_REQUIRE(p->batch >= 1 && p->batch <= c->ptc_n, "batch must be in [1, stored pairs]");
         TM_REQUIRE(p->lr > 0 && p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1 && p->adam_eps > 0,
                    "bad Adam parameters");
+        const LossKind kind = loss_kind(p->loss);
+        TM_REQUIRE(p->mu_sign == 1 || p->mu_sign == -1, "mu_sign must be +1 or -1");
         hipStream_t s = hs(stream);
         const double t0 = now_s();
         const int nb = c->ptc_n / p->batch, steps = nb * p->epochs;
         const size_t one = store_half_bytes(c), cap = (size_t)c->ptc_cap;
         const char *R = (const char *)ws_get(c, "ptc_pairs_r", 2 * one * cap);
         const char *E = (const char *)ws_get(c, "ptc_pairs_e", 2 * one * cap);
-        const double *en2 = (const double *)ws_get(c, "ptc_pairs_en2", sizeof(double) * cap);
+        const double *en2 = (const double *)ws_get(
+            c, kind == LossKind::error ? "ptc_pairs_en2" : "ptc_pairs_rn2", sizeof(double) * cap);
         double *hist = (double *)ws_get(c, "ptc_hist", sizeof(double) * steps);
         std::vector<int> order(nb);
         uint64_t st = p->seed;
@@ -726,8 +1012,8 @@ extern "C" int tm_ptc_train(tm_ctx *c, const tm_ptc_train_params *p, tm_ptc_trai
             for (int k = nb - 1; k > 0; k--) std::swap(order[k], order[splitmix(st) % (uint64_t)(k + 1)]);
             for (int k = 0; k < nb; k++, step++) {
                 const size_t b0 = (size_t)order[k] * p->batch;
-                loss_grad(c, c->ptc_store, R + one * b0, R + one * (cap + b0), E + one * b0, E + one * (cap + b0),
-                          en2 + b0, p->batch, hist + step, s);
+                loss_grad(c, kind, eps_of(c, p->mu_sign), c->ptc_store, R + one * b0, R + one * (cap + b0),
+                          E + one * b0, E + one * (cap + b0), en2 + b0, p->batch, hist + step, s);
                 AdamArgs ad{p->lr, p->beta1, p->beta2, p->adam_eps, ++c->ptc_step};
                 run_update(c, 1, ad, s);
             }

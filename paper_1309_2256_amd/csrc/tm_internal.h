@@ -84,6 +84,8 @@ __host__ __device__ __forceinline__ void cmac_conj(cx<T> &acc, cx<T> a, cx<T> b)
 struct L12 {};
 struct L12D {};
 struct L12F {};
+// 8-parameter FP64 links (appendix A.1): [8 directions][4][vh] double2
+struct L8D {};
 
 struct alignas(4) h2 {
     _Float16 x, y;
@@ -263,12 +265,18 @@ struct tm_ctx {
     // FP64 and FP32 12-parameter copies, same layout
     void *links12d[2] = {nullptr, nullptr};
     void *links12f[2] = {nullptr, nullptr};
+    // FP64 8-parameter copy (a2, a3, b1 or -c1, phases; see misc.hip), [8][4][vh]
+    void *links8d[2] = {nullptr, nullptr};
     bool have_gauge = false;
     bool have_links32 = false;
     bool have_links16 = false;
     bool have_links12 = false;
     bool have_links12d = false;
     bool have_links12f = false;
+    bool have_links8d = false;
+    // the 8-parameter copy was built and every link's first row has
+    // |a2|^2 + |a3|^2 >= kRecon8MinN (the reconstruction divides by it)
+    bool links8_usable = false;
     // binary16 link format of the FP16/BF16-spinor kernels: 18 or 12
     // parameters (12 reads a third fewer link bytes; measured no slower at 12
     // RHS and 9-24% faster at 1-4 RHS per call)
@@ -281,6 +289,9 @@ struct tm_ctx {
     // FP16/BF16-spinor Dslash launches read the FP32 links instead of the
     // binary16 copy (set by tm_dslash for link_prec = TM_F32)
     bool half_links_f32 = false;
+    // links of the FP16/BF16-spinor kernels when no call overrides them
+    // (tm_set_half_spinor_links): false = binary16 copy, true = FP32 (18)
+    bool half_links_f32_default = false;
     std::map<std::string, DevBuf> ws;
     // autotuned right-hand sides per Dslash thread, keyed by (precision, nrhs)
     std::map<std::pair<int, int>, int> rhs_tile;
@@ -292,6 +303,9 @@ struct tm_ctx {
     // learned preconditioner (ptc.hip): channel count (0 = no weights),
     // Adam step counter, training-pair store (capacity, count, precision)
     int ptc_nc = 0;
+    // network arithmetic: TM_F32 (VALU, FP32 weights) or TM_BF16 (spin mixing
+    // on the matrix cores, BF16 weights and activations, FP32 accumulation)
+    int ptc_arith = TM_F32;
     long ptc_step = 0;
     int ptc_cap = 0, ptc_n = 0, ptc_store = TM_F32;
     // algorithmic work of the kernels launched on this context so far
@@ -306,14 +320,23 @@ struct tm_ctx {
 };
 
 // 12-parameter links for kernels of spinor precision prec: the format asks
-// for them and the links are special unitary to that precision's rounding
-// (the third row is rebuilt from the first two assuming U in SU(3))
+// for 12 (or 8, which the FP64 kernels alone read, the others taking 12)
+// and the links are special unitary to that precision's rounding (the third
+// row is rebuilt from the first two assuming U in SU(3))
 inline bool recon12_ok(const tm_ctx *c, int prec)
 {
-    if (c->link_recon != 12) return false;
+    if (c->link_recon != 12 && c->link_recon != 8) return false;
     const double lim = prec == TM_F64 ? 1e-12 : prec == TM_F32 ? 1e-6 : 1e-3;
     return c->su3_dev <= lim;
 }
+
+// smallest |a2|^2 + |a3|^2 (over the links) with which the 8-parameter form
+// is used; fields with a link closer to diagonal (unit links) keep 12
+constexpr double kRecon8MinN = 1e-10;
+
+// the FP64 kernels read 8-parameter links: asked for, special unitary to
+// FP64 rounding; links8_usable is settled when the copy is built
+inline bool recon8_wanted(const tm_ctx *c) { return c->link_recon == 8 && c->su3_dev <= 1e-12; }
 
 inline void account(tm_ctx *c, double bytes, double flops)
 {
@@ -328,6 +351,8 @@ void ensure_links32(tm_ctx *c, hipStream_t s);
 void ensure_links16(tm_ctx *c, hipStream_t s);
 void ensure_links12(tm_ctx *c, hipStream_t s);
 void ensure_links12d(tm_ctx *c, hipStream_t s);
+// builds the 8-parameter copy if needed; true when the FP64 kernels use it
+bool ensure_links8d(tm_ctx *c, hipStream_t s);
 void ensure_links12f(tm_ctx *c, hipStream_t s);
 
 // ---------------------------------------------------------------- dslash
@@ -394,7 +419,8 @@ struct MultiDslash {
     std::vector<std::vector<unsigned char>> args;
     std::vector<int> grid;
     int prec = 0, dag = 0, own = 0, epi = 0, R = 1, n = 0;
-    bool recon12 = false;  // binary16 links in the 12-parameter format
+    bool recon12 = false;  // links in the 12-parameter format
+    bool recon8 = false;   // FP64 links in the 8-parameter format
 };
 constexpr int kMultiInst = 16;  // instances per launch (kernel-argument space)
 void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, int R,
@@ -457,6 +483,8 @@ void launch_links_to_f16(tm_ctx *c, hipStream_t s);
 void launch_links_to_r12(tm_ctx *c, hipStream_t s);
 // first two rows of every link in FP64: [8][6][vh] per parity
 void launch_links_to_r12d(tm_ctx *c, hipStream_t s);
+// builds links8d for both parities; returns the smallest |a2|^2 + |a3|^2
+double launch_links_to_r8d(tm_ctx *c, hipStream_t s);
 // first two rows of every link rounded once to FP32: [8][6][vh] per parity
 void launch_links_to_r12f(tm_ctx *c, hipStream_t s);
 // Z4 noise for noise index r into FP64 half fields: n_off x (12 with

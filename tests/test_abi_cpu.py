@@ -81,7 +81,7 @@ def test_create_rejects_bad_bc_and_nulls():
 
 def test_ptc_structs_and_null_context():
     import paper_1309_2256_amd as P
-    assert ctypes.sizeof(P.tm_ptc_train_params) == 4 + 4 + 4 * 8 + 8
+    assert ctypes.sizeof(P.tm_ptc_train_params) == 4 + 4 + 4 * 8 + 8 + 4 + 4
     assert ctypes.sizeof(P.tm_ptc_train_stats) == 4 + 4 + 3 * 8
     assert P.tm_ptc_set_weights(None, 12, None, None) == P.TM_ERR_ARG
     assert P.tm_ptc_init_hopping(None, 12, 1, 0, 0.0) == P.TM_ERR_ARG
