@@ -35,11 +35,11 @@ def main():
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-full-solve", action="store_true",
+                    help="also run one 32^3x64 oracle solve to 1e-9 to completion (minutes of CPU time)")
     ap.add_argument("--no-ptc", action="store_true",
                     help="skip the learned-preconditioner comparison on 32^3x64")
     ap.add_argument("--ptc-pairs", type=int, default=4096)
-    ap.add_argument("--ptc-rhs", type=int, default=4,
-                    help="right-hand sides of the FGMRES runs (memory: ~12 GB each)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the momentum, TSM/HPE, time-dilution and uneven-batch legs")
     args = ap.parse_args()
@@ -104,48 +104,81 @@ def main():
     value = n_solves / elapsed
     chosen_iters = sum(s.iters_hp for s in stats) / n_solves
 
-    # plain: FP64 CG, one right-hand side at a time (the first dilution of noise 0)
+    # the same chosen solve with the configuration's stated link precision:
+    # FP32 links (all 18 parameters) with FP16 spinors
+    ctx.set_half_spinor_links(P.TM_F32)
+    step(args.warmup + args.steps)  # warm (tuning of the FP32-link kernels)
+    torch.cuda.synchronize()
+    tf = time.perf_counter()
+    fst = [step(args.warmup + args.steps + 1 + k)[1] for k in range(args.steps)]
+    torch.cuda.synchronize()
+    f32_elapsed = time.perf_counter() - tf
+    ctx.set_half_spinor_links(P.TM_F16)
+    f32_links = {"solves_per_s": sum(q.n_solves_hp for q in fst) / f32_elapsed,
+                 "iters_per_solve": sum(q.iters_hp for q in fst) / sum(q.n_solves_hp for q in fst),
+                 "max_res": max(q.max_res_hp for q in fst),
+                 "what": "the chosen solve with FP32 links (18 parameters) and FP16 spinors, "
+                         "the configuration's stated precision; same steps as value"}
+    print("[bench] chosen solve with FP32 links: %.2f solves/s" % f32_links["solves_per_s"],
+          file=sys.stderr, flush=True)
+
+    # plain: FP64 CG, one right-hand side at a time (the first dilution of
+    # noise 0), median of three timed solves
     b = torch.zeros((1, V, 4, 3), dtype=torch.complex128, device=dev)
     eta12 = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
     ctx.noise(eta12, seed_noise, 0, P.TM_DIL_SPIN_COLOUR)
     b.copy_(eta12[:1])
     del eta12
     x = torch.zeros_like(b)
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    _, pst = ctx.solve(x, b, 1, P.solve_params(tol=1e-9, solver=P.TM_CG_F64))
-    torch.cuda.synchronize()
-    plain_time = time.perf_counter() - tp
+    ctx.solve(x, b, 1, P.solve_params(tol=1e-9, solver=P.TM_CG_F64))  # warm
+    plain_times = []
+    for _ in range(3):
+        x.zero_()
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        _, pst = ctx.solve(x, b, 1, P.solve_params(tol=1e-9, solver=P.TM_CG_F64))
+        torch.cuda.synchronize()
+        plain_times.append(time.perf_counter() - tp)
+    plain_time = float(np.median(plain_times))
     plain_value = 1.0 / plain_time
     plain_iters = pst[0].iters
-    print("[bench] plain FP64 solve: %d iterations, residual %.2e, %.2fs"
-          % (plain_iters, pst[0].true_rel_res, plain_time), file=sys.stderr, flush=True)
+    print("[bench] plain FP64 solve: %d iterations, residual %.2e, %s s"
+          % (plain_iters, pst[0].true_rel_res, ["%.3f" % v for v in plain_times]), file=sys.stderr, flush=True)
     del x, b
 
     # dominant kernel: 12-RHS half-lattice Dslash R^-1 H (FP16 spinors and
-    # links, FP32 arithmetic), the form the chosen solver launches
+    # links, FP32 arithmetic), the form the chosen solver launches, timed with
+    # HIP events on the stream it is launched on (torch's current stream)
     vh = V // 2
     nb = ctx.half_numel(P.TM_F16, nrhs)
     bufs = [torch.randn(nb // 2, dtype=torch.float16, device=dev) * 0.1 for _ in range(2)]
     outb = torch.empty(nb, dtype=torch.uint8, device=dev)
     ctx.set_link_format(LINK_PARAMS)  # the library default, stated for the byte count
-    for _ in range(10):
-        ctx.dslash(outb, bufs[0], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16, P.TM_F16)
-    torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for r in range(args.dslash_reps):
-        ctx.dslash(outb, bufs[r % 2], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16, P.TM_F16)
-    ev1.record()
-    torch.cuda.synchronize()
-    dslash_s = ev0.elapsed_time(ev1) / 1e3 / args.dslash_reps
-    # compulsory bytes per output site and RHS: 8 neighbour spinors are one
-    # read of the input field (12 complex FP16 = 48 B), one output write
-    # (48 B), 8 binary16 links per site in the 12-parameter format (two rows,
-    # 192 B) shared by 12 RHS (16 B)
-    bytes_per_site_rhs = 48 + 48 + 8 * (LINK_PARAMS // 2) * 4 / nrhs
-    alg_bytes = vh * nrhs * bytes_per_site_rhs
-    achieved = alg_bytes / dslash_s / 1e9
+
+    def time_half(link_prec, reps):
+        for _ in range(10):
+            ctx.dslash(outb, bufs[0], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16, link_prec)
+        torch.cuda.synchronize()
+        ev0.record()
+        for r in range(reps):
+            ctx.dslash(outb, bufs[r % 2], nrhs, P.TM_RINV_HOP_OE, 1, P.TM_F16, link_prec)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    dslash_s = time_half(P.TM_F16, args.dslash_reps)
+    dslash_f32_s = time_half(P.TM_F32, args.dslash_reps)
+    # algorithmic bytes per output site and RHS (one read of the input field,
+    # one write of the output, the 8 links of a site shared by the 12 RHS):
+    #   reference model, FP32 links (18 parameters) / FP16 spinors:
+    #     48 + 48 + 8 * 72 / 12 = 144 B
+    #   this kernel's format, binary16 links with 12 parameters:
+    #     48 + 48 + 8 * (LINK_PARAMS / 2) * 4 / 12 = 112 B
+    ref_bytes = vh * nrhs * (48 + 48 + 8 * 72 / nrhs)
+    own_bytes = vh * nrhs * (48 + 48 + 8 * (LINK_PARAMS // 2) * 4 / nrhs)
+    achieved = ref_bytes / dslash_s / 1e9
+    alg_bytes = own_bytes
     del bufs, outb
 
     # the other Dslash forms the solvers run: FP64 1 RHS (plain solve and
@@ -166,16 +199,44 @@ def main():
         return ev0.elapsed_time(ev1) / 1e3 / reps
 
     dslash_cases = {}
-    for name, prec, n, site_rhs_bytes in (
-            ("fp64_1rhs_12param_links", P.TM_F64, 1, 192 + 192 + 8 * (LINK_PARAMS // 2) * 16),
-            ("fp16_1rhs_12param_links", P.TM_F16, 1, 48 + 48 + 8 * 6 * 4)):
+    for name, prec, n, site_rhs_bytes, fmt in (
+            ("fp64_1rhs_12param_links", P.TM_F64, 1, 192 + 192 + 8 * 6 * 16, 12),
+            ("fp64_1rhs_8param_links", P.TM_F64, 1, 192 + 192 + 8 * 4 * 16, 8),
+            ("fp16_1rhs_12param_links", P.TM_F16, 1, 48 + 48 + 8 * 6 * 4, 12)):
+        ctx.set_link_format(fmt)
         t_s = time_dslash(prec, n)
         b_ = vh * n * site_rhs_bytes
         dslash_cases[name] = {"us": t_s * 1e6, "algorithmic_bytes": b_,
                               "algorithmic_tb_s": b_ / t_s / 1e12, "frac_of_8tb_s": b_ / t_s / 8e12}
+    ctx.set_link_format(LINK_PARAMS)
     dslash_cases["fp16_12rhs_12param_links"] = {
-        "us": dslash_s * 1e6, "algorithmic_bytes": alg_bytes, "algorithmic_tb_s": achieved / 1e3,
-        "frac_of_8tb_s": achieved / HBM_PEAK_GBS}
+        "us": dslash_s * 1e6, "algorithmic_bytes": own_bytes, "algorithmic_tb_s": own_bytes / dslash_s / 1e12,
+        "frac_of_8tb_s": own_bytes / dslash_s / 8e12}
+    dslash_cases["fp16_12rhs_fp32_18param_links"] = {
+        "us": dslash_f32_s * 1e6, "algorithmic_bytes": ref_bytes, "algorithmic_tb_s": ref_bytes / dslash_f32_s / 1e12,
+        "frac_of_8tb_s": ref_bytes / dslash_f32_s / 8e12}
+
+    # plain FP64 solve with 8-parameter links (same source, same process)
+    ctx.set_link_format(8)
+    b8 = torch.zeros((1, V, 4, 3), dtype=torch.complex128, device=dev)
+    e12 = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+    ctx.noise(e12, seed_noise, 0, P.TM_DIL_SPIN_COLOUR)
+    b8.copy_(e12[:1])
+    del e12
+    x8 = torch.zeros_like(b8)
+    ctx.solve(x8, b8, 1, P.solve_params(tol=1e-9, solver=P.TM_CG_F64))  # warm
+    t8 = []
+    for _ in range(3):
+        x8.zero_()
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        _, p8 = ctx.solve(x8, b8, 1, P.solve_params(tol=1e-9, solver=P.TM_CG_F64))
+        torch.cuda.synchronize()
+        t8.append(time.perf_counter() - tp)
+    ctx.set_link_format(LINK_PARAMS)
+    plain_8param = {"solves_per_s": 1.0 / float(np.median(t8)), "iters": p8[0].iters,
+                    "true_rel_res": p8[0].true_rel_res}
+    del x8, b8
 
     # practical streaming ceiling (and the calibration kernel for the HBM
     # byte counters): a device-to-device copy of 1 GiB each way
@@ -193,49 +254,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-        eta = O.noise_z4(L, seed_noise, 0)
-        src = np.zeros_like(eta)
-        src[:, 0, 0] = eta[:, 0, 0]  # first spin-colour dilution, as the plain GPU solve
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        tc = time.perf_counter()
-        O.cgnr_iterations(L, kappa, eps, -1, U, src, 1)
-        t1 = time.perf_counter() - tc
-        tc = time.perf_counter()
-        O.cgnr_iterations(L, kappa, eps, -1, U, src, 1 + args.cpu_iters)
-        t2 = time.perf_counter() - tc
-        per_iter = (t2 - t1) / args.cpu_iters
-        setup = max(t1 - per_iter, 0.0)
-        cpu_solve_s = setup + plain_iters * per_iter
-        tc = time.perf_counter()
-        O.hop(L, kappa, -1, U, src)
-        hop_s = time.perf_counter() - tc
-        # the small lattices: a full oracle solve on 4^3x8, CG iterations on 16^3x32
-        small = {}
-        cf = S.CONFIGS["c1"]
-        Uc = S.gauge_links(cf["L"], cf["eps_links"], cf["seed"])
-        ec = O.noise_z4(cf["L"], S.NOISE_SEEDS["c1"], 0)
-        tc = time.perf_counter()
-        _, its, res = O.cgnr(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 1e-9)
-        dt_c = time.perf_counter() - tc
-        small["c1"] = {"lattice": list(cf["L"]), "iterations": int(its), "seconds": dt_c,
-                       "solves_per_s": 1.0 / dt_c, "residual": float(res)}
-        cf = S.CONFIGS["c2"]
-        Uc = S.gauge_links(cf["L"], cf["eps_links"], cf["seed"])
-        ec = O.noise_z4(cf["L"], S.NOISE_SEEDS["c2"], 0)
-        tc = time.perf_counter()
-        O.cgnr_iterations(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 1)
-        ta = time.perf_counter() - tc
-        tc = time.perf_counter()
-        O.cgnr_iterations(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 6)
-        tb = time.perf_counter() - tc
-        small["c2"] = {"lattice": list(cf["L"]), "per_iteration_s": (tb - ta) / 5}
-        cpu = {"value": 1.0 / cpu_solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "per_iteration_s": per_iter, "full_lattice_hop_s": hop_s, "small_lattices": small,
-               "sample": "FP64 oracle CGNR on the even-odd system, same source and lattice; "
-                         "%d + %d CG iterations timed (%.1fs), %.2fs per iteration, scaled "
-                         "to the %d iterations the plain FP64 GPU solve needed for 1e-9"
-                         % (1, 1 + args.cpu_iters, t1 + t2, per_iter, plain_iters)}
+        cpu = cpu_baseline(args, S, L, kappa, eps, U, seed_noise, plain_iters)
 
     out = {
         "metric": "solves/s to 1e-9 rel. residual, 32^3x64 (plain vs chosen); Dslash HBM TB/s",
@@ -258,7 +277,10 @@ def main():
             "lattice": list(L), "rhs_per_step": nrhs, "parallelism": "single GPU",
         },
         "plain_solves_per_s": plain_value,
+        "plain_seconds": plain_times,
         "plain_iters": plain_iters,
+        "plain_8param_links": plain_8param,
+        "chosen_fp32_links": f32_links,
         "chosen_iters_per_solve": chosen_iters,
         "speedup_vs_plain": value / plain_value,
         "dslash_tb_s": achieved / 1e3,
@@ -268,7 +290,16 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "k_dslash (R_oo^-1 H_oe, 12 RHS, FP16 spinors, 12-parameter binary16 links, "
                       "autotuned RHS tile)",
-            "avg_launch_us": dslash_s * 1e6, "algorithmic_bytes_per_launch": alg_bytes,
+            "avg_launch_us": dslash_s * 1e6,
+            "bytes_model": "achieved and frac: reference bytes, 144 B per site-RHS (FP32 links with 18 "
+                           "parameters, FP16 spinors) x 12 RHS x V/2 = %.3f GB per launch; own_*: the "
+                           "bytes this kernel's format needs, 112 B per site-RHS (binary16 links, 12 "
+                           "parameters) = %.3f GB" % (ref_bytes / 1e9, own_bytes / 1e9),
+            "algorithmic_bytes_per_launch": ref_bytes,
+            "own_bytes_per_launch": own_bytes, "own_achieved": own_bytes / dslash_s / 1e9,
+            "own_frac": own_bytes / dslash_s / 1e9 / HBM_PEAK_GBS,
+            "fp32_links_kernel_us": dslash_f32_s * 1e6,
+            "fp32_links_kernel_frac": ref_bytes / dslash_f32_s / 1e9 / HBM_PEAK_GBS,
             "copy_gb_s": copy_gbs, "frac_of_copy": achieved / copy_gbs,
         },
         "cpu_baseline": cpu,
@@ -326,6 +357,88 @@ def momentum_leg(P, torch, dev, ctx, L, nrhs, p2max=9, reps=3):
     del eta, sol
     torch.cuda.empty_cache()
     return res
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(args, S, L, kappa, eps, U, seed_noise, plain_iters):
+    """The FP64 oracle on the host cores (a reported baseline, not the
+    target), on a bounded sample: per-CG-iteration time of the 32^3x64 solve
+    at all threads and at one thread, scaled to the iteration count of the
+    plain GPU solve; a full oracle solve of the 4^3x8 lattice; CG iterations
+    of the 16^3x32 lattice."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(threads)
+    eta = O.noise_z4(L, seed_noise, 0)
+    src = np.zeros_like(eta)
+    src[:, 0, 0] = eta[:, 0, 0]  # first spin-colour dilution, as the plain GPU solve
+
+    def per_iter(n_threads, k):
+        O.set_threads(n_threads)
+        tc = time.perf_counter()
+        O.cgnr_iterations(L, kappa, eps, -1, U, src, 1)
+        t1 = time.perf_counter() - tc
+        tc = time.perf_counter()
+        O.cgnr_iterations(L, kappa, eps, -1, U, src, 1 + k)
+        t2 = time.perf_counter() - tc
+        return (t2 - t1) / k, max(t1 - (t2 - t1) / k, 0.0), t1 + t2
+
+    it_all, setup, t_all = per_iter(threads, args.cpu_iters)
+    it_one, _, t_one = per_iter(1, 1)
+    O.set_threads(threads)
+    cpu_solve_s = setup + plain_iters * it_all
+    tc = time.perf_counter()
+    O.hop(L, kappa, -1, U, src)
+    hop_s = time.perf_counter() - tc
+    small = {}
+    cf = S.CONFIGS["c1"]
+    Uc = S.gauge_links(cf["L"], cf["eps_links"], cf["seed"])
+    ec = O.noise_z4(cf["L"], S.NOISE_SEEDS["c1"], 0)
+    tc = time.perf_counter()
+    _, its, res = O.cgnr(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 1e-9)
+    dt_c = time.perf_counter() - tc
+    small["c1"] = {"lattice": list(cf["L"]), "iterations": int(its), "seconds": dt_c,
+                   "solves_per_s": 1.0 / dt_c, "residual": float(res)}
+    cf = S.CONFIGS["c2"]
+    Uc = S.gauge_links(cf["L"], cf["eps_links"], cf["seed"])
+    ec = O.noise_z4(cf["L"], S.NOISE_SEEDS["c2"], 0)
+    tc = time.perf_counter()
+    O.cgnr_iterations(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 1)
+    ta = time.perf_counter() - tc
+    tc = time.perf_counter()
+    O.cgnr_iterations(cf["L"], cf["kappa"], cf["two_kappa_mu"], -1, Uc, ec, 6)
+    tb = time.perf_counter() - tc
+    small["c2"] = {"lattice": list(cf["L"]), "per_iteration_s": (tb - ta) / 5}
+    model, nproc = cpu_info()
+    full = None
+    if args.cpu_full_solve:
+        tc = time.perf_counter()
+        _, its, res = O.cgnr(L, kappa, eps, -1, U, src, 1e-9)
+        full = {"seconds": time.perf_counter() - tc, "iterations": int(its), "true_rel_res": float(res),
+                "threads": threads}
+        print("[bench] oracle 32^3x64 solve to 1e-9: %d iterations, %.1fs" % (its, full["seconds"]),
+              file=sys.stderr, flush=True)
+    return {"value": 1.0 / cpu_solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "nproc": nproc,
+            "per_iteration_s": it_all, "per_iteration_s_1thread": it_one,
+            "solves_per_s_1thread": 1.0 / (setup * threads + plain_iters * it_one),
+            "full_lattice_hop_s": hop_s, "small_lattices": small, "full_solve": full,
+            "sample": "FP64 oracle CGNR on the even-odd system, same source and lattice as the plain GPU "
+                      "solve; %d + %d CG iterations timed at %d threads (%.1fs) and 1 + 1 at one thread "
+                      "(%.1fs): %.2f s and %.2f s per iteration, scaled to the %d iterations the plain "
+                      "FP64 GPU solve needed for 1e-9" % (1, 1 + args.cpu_iters, threads, t_all, t_one,
+                                                          it_all, it_one, plain_iters)}
 
 
 def make_context(P, S, torch, dev, name):
@@ -470,11 +583,16 @@ def dslash_traffic(alg_bytes):
 
 def ptc_leg(args, P, S, torch, dev):
     """Learned preconditioner on the 32^3x64 lattice with 16^3x32-lattice
-    physics (links exp(i 0.2 H), kappa 0.124, 2 kappa mu 0.0028): train the
-    parallel-transport network on (eta, M^-1 eta) pairs from 16^3x32 solves
-    (Z4 spin-colour-diluted sources, mixed CG to 1e-6, BF16 pair store),
-    then solve 32^3x64 right-hand sides to 1e-9 with FGMRES(16) + network,
-    FGMRES(16) without it, and the mixed-precision CG."""
+    physics (links exp(i 0.2 H), kappa 0.124, 2 kappa mu 0.0028).  Training
+    on the 16^3x32 lattice of the same physics (the network is a local
+    stencil, its weights carry over to any volume): pairs from the mixed CG's
+    own iterates (Z4 spin-colour-diluted sources, (b - M x_k, x* - x_k) at
+    k = 8, 16, 32, 64, BF16 store), residual loss |M N(r) - r|^2 / |r|^2,
+    Adam, from the second-order hopping expansion.  Then all 24 right-hand
+    sides (2 noises x 12) solved to 1e-9 on 32^3x64 by mixed CG (12 per call)
+    and by FGMRES(16) with the trained network on the matrix cores (BF16),
+    with the trained network in FP32, with the analytic start, and without
+    a network."""
     def log(msg):
         print("[bench/ptc] " + msg, file=sys.stderr, flush=True)
 
@@ -484,26 +602,27 @@ def ptc_leg(args, P, S, torch, dev):
     res = {}
     c2, cfg2 = make("c2")
     V2 = int(np.prod(cfg2["L"]))
-    npairs = args.ptc_pairs // 12 * 12
-    c2.ptc_pairs_reserve(npairs, P.TM_BF16)
+    iters = [8, 16, 32, 64]
+    n_src = max(args.ptc_pairs // (12 * len(iters)), 1)
+    c2.ptc_pairs_reserve(n_src * 12 * len(iters), P.TM_BF16)
     eta = torch.zeros((12, V2, 4, 3), dtype=torch.complex128, device=dev)
-    x = torch.zeros_like(eta)
-    lp = P.solve_params(tol=1e-6, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+    mixed = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
     t0 = time.perf_counter()
-    for k in range(npairs // 12):
+    npairs = 0
+    for k in range(n_src):
         c2.noise(eta, 9000, k, P.TM_DIL_SPIN_COLOUR)
-        c2.solve(x, eta, 12, lp)
-        c2.ptc_pairs_add(eta, x, 12)
+        npairs += c2.ptc_pairs_from_solve(eta, 12, mixed, iters)
     torch.cuda.synchronize()
     res["pairs"] = npairs
+    res["pairs_iterations"] = iters
     res["pairs_seconds"] = time.perf_counter() - t0
-    log("%d pairs in %.1fs" % (npairs, res["pairs_seconds"]))
-    del eta, x
+    log("%d iterate pairs in %.1fs" % (npairs, res["pairs_seconds"]))
+    del eta
     c2.ptc_init_hopping(nc=12, mu_sign=1, seed=1, noise=1e-3)
     W1h, W2h = c2.ptc_get_weights(12)
-    st, _ = c2.ptc_train(epochs=2, batch=16, lr=1e-3, seed=3)
-    res["train"] = {"steps": st.steps, "batch": 16, "epochs": 2, "loss_first_epoch": st.loss_first,
-                    "loss_last_epoch": st.loss_last, "seconds": st.seconds}
+    st, _ = c2.ptc_train(epochs=2, batch=16, lr=1e-3, seed=3, loss=P.TM_PTC_LOSS_RESIDUAL, mu_sign=1)
+    res["train"] = {"loss": "residual |M N(r) - r|^2 / |r|^2", "steps": st.steps, "batch": 16, "epochs": 2,
+                    "loss_first_epoch": st.loss_first, "loss_last_epoch": st.loss_last, "seconds": st.seconds}
     log("trained: loss %.4f -> %.4f in %.1fs" % (st.loss_first, st.loss_last, st.seconds))
     W1t, W2t = c2.ptc_get_weights(12)
     c2.close()
@@ -515,43 +634,42 @@ def ptc_leg(args, P, S, torch, dev):
     b = torch.zeros((12, V5, 4, 3), dtype=torch.complex128, device=dev)
     x = torch.zeros_like(b)
 
-    def run(name, params, nrhs):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        status, stats = c5.solve(x[:nrhs], b[:nrhs], nrhs, params, allow_noconv=True)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        ok = sum(1 for s_ in stats if s_.true_rel_res <= 1e-9)
-        r = {"rhs": nrhs, "verified": ok, "solves_per_s": ok / dt,
-             "iters_mean": float(np.mean([s_.iters for s_ in stats])),
-             "max_true_rel_res": max(s_.true_rel_res for s_ in stats), "seconds": dt}
-        log("%s: %d/%d verified, %.1f iterations, %.2fs" % (name, ok, nrhs, r["iters_mean"], dt))
+    def run24(name, params):
+        tot, n_ok, its, worst, fb = 0.0, 0, [], 0.0, 0
+        for k in range(2):
+            c5.noise(b, 505, k, P.TM_DIL_SPIN_COLOUR)
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            status, stats = c5.solve(x, b, 12, params, allow_noconv=True)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t
+            n_ok += sum(1 for s_ in stats if s_.true_rel_res <= 1e-9)
+            its += [s_.iters for s_ in stats]
+            worst = max(worst, max(s_.true_rel_res for s_ in stats))
+            fb += sum(s_.fallback for s_ in stats)
+        r = {"rhs": 24, "verified": n_ok, "solves_per_s": n_ok / tot, "iters_mean": float(np.mean(its)),
+             "max_true_rel_res": worst, "seconds": tot, "fallbacks": fb}
+        log("%s: %d/24 verified, %.1f iterations, %.2fs" % (name, n_ok, r["iters_mean"], tot))
         return r
 
-    # mixed CG on all 24 right-hand sides (2 noises x 12), 12 per call
-    tot, n_ok, its = 0.0, 0, []
-    for k in range(2):
-        c5.noise(b, 505, k, P.TM_DIL_SPIN_COLOUR)
-        r = run("mixed CG noise %d" % k, P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED,
-                                                         inner_prec=P.TM_F16), 12)
-        tot += r["seconds"]
-        n_ok += r["verified"]
-        its.append(r["iters_mean"])
-    res["mixed_cg"] = {"rhs": 24, "verified": n_ok, "solves_per_s": n_ok / tot,
-                       "iters_mean": float(np.mean(its)), "seconds": tot}
-    c5.noise(b, 505, 0, P.TM_DIL_SPIN_COLOUR)
-    n = min(args.ptc_rhs, 12)
+    res["mixed_cg"] = run24("mixed CG", mixed)
+    res["plain_cg_f64"] = run24("plain FP64 CG", P.solve_params(tol=1e-9, solver=P.TM_CG_F64))
     fg = dict(tol=1e-9, check_every=16, maxiter=3000)
     c5.ptc_set_weights(W1t, W2t)
-    res["fgmres_ptc_trained"] = run("FGMRES(16)+network (trained)",
-                                    P.solve_params(solver=P.TM_FGMRES_PTC, **fg), n)
+    c5.ptc_set_arith(P.TM_BF16)
+    res["fgmres_ptc_trained_bf16"] = run24("FGMRES(16)+network (trained, BF16 matrix cores)",
+                                           P.solve_params(solver=P.TM_FGMRES_PTC, **fg))
+    c5.ptc_set_arith(P.TM_F32)
+    res["fgmres_ptc_trained_f32"] = run24("FGMRES(16)+network (trained, FP32)",
+                                          P.solve_params(solver=P.TM_FGMRES_PTC, **fg))
     c5.ptc_set_weights(W1h, W2h)
-    res["fgmres_ptc_hopping_init"] = run("FGMRES(16)+network (hopping-expansion weights)",
-                                         P.solve_params(solver=P.TM_FGMRES_PTC, **fg), n)
-    res["fgmres_no_net"] = run("FGMRES(16) without network", P.solve_params(solver=P.TM_FGMRES, **fg), n)
+    res["fgmres_ptc_hopping_init"] = run24("FGMRES(16)+network (hopping-expansion weights)",
+                                           P.solve_params(solver=P.TM_FGMRES_PTC, **fg))
+    res["fgmres_no_net"] = run24("FGMRES(16) without network", P.solve_params(solver=P.TM_FGMRES, **fg))
     res["workload"] = ("32^3x64, links exp(i 0.2 H) seed 105, kappa 0.124, 2 kappa mu 0.0028; "
-                       "Z4 noise seed 505 spin-colour diluted; FGMRES legs on the first %d "
-                       "dilutions of noise 0" % n)
+                       "Z4 noise seed 505, 2 noises x 12 spin-colour dilutions = 24 RHS per solver, "
+                       "12 per call; network trained on 16^3x32 of the same physics")
     c5.close()
     return res
 

@@ -183,3 +183,37 @@ def test_bf16_network_fgmres_converges():
             assert res / np.linalg.norm(b[r]) <= 1e-9 and st[r].converged == 1
     finally:
         ctx.close()
+
+
+def test_trained_network_beats_hopping_start():
+    """What training gains: the network trained with the residual loss on
+    pairs from the mixed CG's own iterates needs fewer FGMRES(16) steps on
+    held-out right-hand sides than its analytic start, the second-order
+    hopping expansion (8^3x16, the uneven-batch physics; the steps are the
+    same for every held-out source to within one)."""
+    ctx, cfg, U = make_ctx("c4a")
+    try:
+        L = cfg["L"]
+        ctx.ptc_init_hopping(nc=12, mu_sign=1, seed=3, noise=1e-3)
+        fg = P.solve_params(tol=1e-9, solver=P.TM_FGMRES_PTC, check_every=16, maxiter=4000)
+        held = cuda(S.random_spinor(L, 421, 2))
+
+        def steps():
+            x = torch.zeros_like(held)
+            _, st = ctx.solve(x, held, 2, fg)
+            assert all(s.converged == 1 and s.fallback == 0 for s in st)
+            return max(s.iters for s in st)
+
+        start = steps()
+        train = cuda(S.random_spinor(L, 422, 8))
+        mixed = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+        ctx.ptc_pairs_reserve(32, P.TM_F32)
+        n = ctx.ptc_pairs_from_solve(train, 8, mixed, [4, 8, 16, 32])
+        assert n == 32
+        st, hist = ctx.ptc_train(epochs=10, batch=8, lr=1e-3, seed=5, n_pairs=n, loss=P.TM_PTC_LOSS_RESIDUAL,
+                                 mu_sign=1)
+        assert st.loss_last < st.loss_first
+        trained = steps()
+        assert trained < start, (start, trained)
+    finally:
+        ctx.close()
