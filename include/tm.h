@@ -33,8 +33,12 @@
  *     one parity p, half-site index i = s >> 1 over the sites of parity p
  *     (unique because Lx is even), structure of arrays:
  *     element (rhs r, spin a, colour c, half-site i) at complex offset
- *     (r*12 + 3*a + c) * (V/2) + i, each complex stored as (re, im) pairs of
+ *     (r*12 + 3*a + c) * HS + i, each complex stored as (re, im) pairs of
  *     the precision given (double, float, IEEE binary16, bfloat16).
+ *     HS = tm_half_stride(ctx) >= V/2 is V/2 rounded up to an odd multiple
+ *     of 32; the HS - V/2 pad entries of each (r, a, c) plane are never read
+ *     for a result and the library leaves their contents unspecified.  A
+ *     half field of nrhs right-hand sides takes 12 * HS * nrhs complex.
  *
  * OWNERSHIP AND STREAMS
  *   Every pointer argument is owned by the caller; the library never frees
@@ -83,8 +87,8 @@ typedef struct {
 
 /* Create a context on HIP device `device` for the given lattice.
  * Returns TM_ERR_ARG for odd or non-positive extents, TM_ERR_UNSUPPORTED when
- * one FP64 right-hand side of a half field (V/2 x 12 x 16 bytes) exceeds
- * 2^31 - 1 bytes (the kernels' 32-bit offsets; V <= 22369620 sites, e.g.
+ * one FP64 right-hand side of a half field (HS x 12 x 16 bytes) exceeds
+ * 2^31 - 1 bytes (the kernels' 32-bit offsets; V <= 22369600 sites, e.g.
  * 48^3 x 96 fits, 64^3 x 128 does not). */
 int tm_create(tm_ctx **ctx, const tm_lattice *lat, int device);
 
@@ -93,6 +97,11 @@ void tm_destroy(tm_ctx *ctx);
 
 /* Message for the last failing call on ctx ("" if none). */
 const char *tm_last_error(const tm_ctx *ctx);
+
+/* Plane stride HS of the half-lattice layout (see LAYOUTS): V/2 rounded up
+ * to an odd multiple of 32 half-sites, so that the 12 planes of a field do
+ * not sit a power of two apart in memory.  0 for a null context. */
+int tm_half_stride(const tm_ctx *ctx);
 
 /* Upload the gauge field.  U: device pointer, canonical [4][V][3][3] complex
  * double.  Builds the internal even-odd link layout (forward links and

@@ -86,6 +86,7 @@ _SIGS = {
     "tm_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(tm_lattice), ctypes.c_int]),
     "tm_destroy": (None, [_vp]),
     "tm_last_error": (ctypes.c_char_p, [_vp]),
+    "tm_half_stride": (ctypes.c_int, [_vp]),
     "tm_set_gauge": (ctypes.c_int, [_vp, _vp, _vp]),
     "tm_dslash": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, _vp]),
@@ -175,6 +176,8 @@ class Context:
         if st != TM_OK:
             raise TMError(st, "tm_create failed")
         self.h = h
+        # plane stride of the half-lattice layout (>= vh, padded)
+        self.hs = int(tm_half_stride(h))
 
     def close(self):
         if getattr(self, "h", None):
@@ -193,8 +196,9 @@ class Context:
         return st
 
     def half_numel(self, prec, nrhs=1):
-        """Bytes of a half-lattice field of nrhs right-hand sides."""
-        return PREC_BYTES[prec] * 12 * self.vh * nrhs
+        """Bytes of a half-lattice field of nrhs right-hand sides ([nrhs][12][hs],
+        the last hs - vh sites of every plane are padding)."""
+        return PREC_BYTES[prec] * 12 * self.hs * nrhs
 
     def set_gauge(self, U, stream=None):
         self._check(tm_set_gauge(self.h, _ptr(U), _stream(stream)))

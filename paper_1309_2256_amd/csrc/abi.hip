@@ -128,7 +128,7 @@ int guarded(tm_ctx *c, F &&f)
 
 hipStream_t hs(tm_stream s) { return (hipStream_t)s; }
 
-size_t half_bytes(tm_ctx *c, int prec, int nrhs) { return prec_bytes(prec) * 12 * (size_t)c->geo.vh * nrhs; }
+size_t half_bytes(tm_ctx *c, int prec, int nrhs) { return prec_bytes(prec) * 12 * (size_t)c->geo.hs * nrhs; }
 
 bool valid_prec(int p) { return p == TM_F64 || p == TM_F32 || p == TM_F16 || p == TM_BF16; }
 
@@ -148,7 +148,7 @@ extern "C" int tm_create(tm_ctx **out, const tm_lattice *lat, int device)
     if (V / 2 > (1L << 30)) return TM_ERR_ARG;
     // the kernels address one right-hand side of a half field with 32-bit
     // byte offsets (FP64: 12 complex of 16 bytes per half-site)
-    if ((V / 2) * 12L * 16L > 0x7fffffffL) return TM_ERR_UNSUPPORTED;
+    if ((long)half_stride((int)(V / 2)) * 12L * 16L > 0x7fffffffL) return TM_ERR_UNSUPPORTED;
     if (!std::isfinite(lat->kappa) || !std::isfinite(lat->two_kappa_mu)) return TM_ERR_ARG;
     if (lat->t_bc != 1 && lat->t_bc != -1) return TM_ERR_ARG;
     int ndev = 0;
@@ -164,6 +164,7 @@ extern "C" int tm_create(tm_ctx **out, const tm_lattice *lat, int device)
     c->geo.lxh = lat->L[0] / 2;
     c->geo.vh = (int)(V / 2);
     c->geo.vsh = lat->L[0] * lat->L[1] * lat->L[2] / 2;
+    c->geo.hs = half_stride(c->geo.vh);
     c->kappa = lat->kappa;
     c->eps = lat->two_kappa_mu;
     c->t_bc = lat->t_bc;
@@ -185,6 +186,8 @@ extern "C" void tm_destroy(tm_ctx *c)
 }
 
 extern "C" const char *tm_last_error(const tm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int tm_half_stride(const tm_ctx *c) { return c ? c->geo.hs : 0; }
 
 extern "C" int tm_set_gauge(tm_ctx *c, const double *U, tm_stream stream)
 {

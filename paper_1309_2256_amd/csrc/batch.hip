@@ -266,7 +266,7 @@ extern "C" int tm_batch_solve(tm_batch *b, double *const *x, const double *const
         }
         for (int i = 0; i < n; i++) {
             tm_ctx *c = b->ctx[i];
-            const size_t hb = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * nrhs[i];
+            const size_t hb = field_bytes(c, TM_F64, nrhs[i]);
             void *be = ws_get(c, "a_be", hb), *bo = ws_get(c, "a_bo", hb);
             xe[i] = ws_get(c, "a_xe", hb);
             xo[i] = ws_get(c, "a_xo", hb);
@@ -326,7 +326,7 @@ extern "C" int tm_batch_loops(tm_batch *b, const tm_loop_params *p, double *cons
             c->stream = s;
             per_noise[i] = p[i].dilution == TM_DIL_SPIN_COLOUR ? 12 : 1;
             nr[i] = per_noise[i] * p[i].n_hp;
-            const size_t one = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * per_noise[i];
+            const size_t one = field_bytes(c, TM_F64, per_noise[i]);
             ee[i] = ws_get(c, "b_eta_e", one * p[i].n_hp);
             eo[i] = ws_get(c, "b_eta_o", one * p[i].n_hp);
             se[i] = ws_get(c, "b_s_e", one * p[i].n_hp);
@@ -353,7 +353,7 @@ extern "C" int tm_batch_loops(tm_batch *b, const tm_loop_params *p, double *cons
                     n_est++;
                 }
             const double epsp = eps_of(c, p[i].mu_sign);
-            const size_t one = prec_bytes(TM_F64) * 12 * (size_t)c->geo.vh * per_noise[i];
+            const size_t one = field_bytes(c, TM_F64, per_noise[i]);
             std::vector<cx<double>> acc(n_est * per, cx<double>{0, 0}), one_loop(n_est * per);
             for (int k = 0; k < p[i].n_hp; k++) {
                 contract_noise(c, p[i].estimators, p[i].derivative, (char *)ee[i] + one * k, (char *)eo[i] + one * k,

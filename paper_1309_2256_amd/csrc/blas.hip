@@ -36,14 +36,14 @@ __device__ __forceinline__ double block_sum(double v)
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_spin_diag(S *out, const S *in, int vh, cx<float> fu,
+__global__ __launch_bounds__(kBlock) void k_spin_diag(S *out, const S *in, int hs, cx<float> fu,
                                                       cx<float> fl, cx<double> du, cx<double> dl)
 {
     using T = typename StoreTraits<S>::real;
-    const size_t n = (size_t)12 * vh;
+    const size_t n = (size_t)12 * hs;
     const size_t base = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
-        const int k = (int)(e / vh);
+        const int k = (int)(e / hs);
         cx<T> f;
         if (sizeof(T) == 8) {
             cx<double> d = k < 6 ? du : dl;
@@ -97,16 +97,19 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dev(SY *y, const SX *x, size_t 
     }
 }
 
+// partial |v|^2 of right-hand side blockIdx.y over the vh valid sites of
+// each of its 12 planes (the pad sites of a plane are skipped)
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_partial_norm2(const S *v, size_t n, double *part, int nblk)
+__global__ __launch_bounds__(kBlock) void k_partial_norm2(const S *v, int vh, int hs, double *part, int nblk)
 {
     using T = typename StoreTraits<S>::real;
-    const size_t base = (size_t)blockIdx.y * n;
+    const size_t base = (size_t)blockIdx.y * 12 * hs;
     double acc = 0;
-    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
-        cx<T> a = ldT<T>(v, base + e);
-        acc += (double)(a.r * a.r + a.i * a.i);
-    }
+    for (int k = 0; k < 12; k++)
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < vh; i += gridDim.x * kBlock) {
+            cx<T> a = ldT<T>(v, base + (size_t)k * hs + i);
+            acc += (double)(a.r * a.r + a.i * a.i);
+        }
     double s = block_sum(acc);
     if (threadIdx.x == 0) part[(size_t)blockIdx.y * nblk + blockIdx.x] = s;
 }
@@ -197,7 +200,8 @@ __global__ __launch_bounds__(kBlock) void k_update_px(S *p, const S *rv, XS *x, 
     }
 }
 
-size_t half_elems(tm_ctx *c) { return (size_t)12 * c->geo.vh; }
+// complex elements of one right-hand side of a half field, pads included
+size_t half_elems(tm_ctx *c) { return (size_t)12 * c->geo.hs; }
 
 int grid_for(size_t n)
 {
@@ -229,7 +233,7 @@ void launch_spin_diag(tm_ctx *c, void *out, const void *in, int prec, int nrhs, 
     account(c, 2.0 * n * nrhs * prec_bytes(prec), 6.0 * n * nrhs);
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_spin_diag<S>, grid, dim3(kBlock), 0, s, (S *)out, (const S *)in, c->geo.vh, fu,
+        hipLaunchKernelGGL(k_spin_diag<S>, grid, dim3(kBlock), 0, s, (S *)out, (const S *)in, c->geo.hs, fu,
                            fl, d.u, d.l);
     });
     TM_HIP(hipGetLastError());
@@ -267,8 +271,9 @@ void launch_axpby_host(tm_ctx *c, void *y, const void *x, int prec, int nrhs, do
 // partial-sum blocks of the vector norms (a few per CU, at most kMaxPart)
 static int reduce_blocks(tm_ctx *c)
 {
-    size_t n = half_elems(c);
-    size_t g = (n + kBlock * 8 - 1) / (kBlock * 8);
+    // one site per thread: its 12 planes, 12 elements
+    size_t n = c->geo.vh;
+    size_t g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
     if (g > kMaxPart) g = kMaxPart;
     return (int)g;
@@ -276,11 +281,10 @@ static int reduce_blocks(tm_ctx *c)
 
 static void partial_norm2(tm_ctx *c, const void *v, int prec, int nrhs, double *part, int nblk, hipStream_t s)
 {
-    size_t n = half_elems(c);
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_partial_norm2<S>, dim3(nblk, nrhs), dim3(kBlock), 0, s, (const S *)v, n, part,
-                           nblk);
+        hipLaunchKernelGGL(k_partial_norm2<S>, dim3(nblk, nrhs), dim3(kBlock), 0, s, (const S *)v, c->geo.vh,
+                           c->geo.hs, part, nblk);
     });
     TM_HIP(hipGetLastError());
 }

@@ -10,7 +10,7 @@
 // extra memory pass.
 //
 // Memory layout (all coalesced over the half-site index i):
-//   spinors  [rhs][spin*3 + colour][vh]
+//   spinors  [rhs][spin*3 + colour][hs] (hs >= vh, the padded plane stride)
 //   links    [direction 0..7][row*3 + col][vh] for the output parity; the
 //            backward links are stored conjugated and the antiperiodic
 //            boundary phase is folded in, so the kernel has no branch on it.
@@ -593,7 +593,7 @@ __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, co
         for (int rr = 0; rr < R; rr++) {
             hv2 psi[12];
 #pragma unroll
-            for (int k = 0; k < 12; k++) psi[k] = ld_hv2(sr[rr], j * (int)sizeof(h2), k * a.g.vh * (int)sizeof(h2));
+            for (int k = 0; k < 12; k++) psi[k] = ld_hv2(sr[rr], j * (int)sizeof(h2), k * a.g.hs * (int)sizeof(h2));
             hop_dir_h<MU, S>(reinterpret_cast<cx<float> *>(acc[rr]), W, psi);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -621,7 +621,7 @@ __device__ __forceinline__ void do_dir(cx<T> acc[R][12], const DParams<T> &a, co
 #pragma unroll
     for (int rr = 0; rr < R; rr++) {
         rawc<typename RawT<SS>::L> psi[12];
-        load_spinor<SS>(psi, sr[rr], a.g.vh * (int)sizeof(SS), j * (int)sizeof(SS));
+        load_spinor<SS>(psi, sr[rr], a.g.hs * (int)sizeof(SS), j * (int)sizeof(SS));
         hop_dir<MU, S>(acc[rr], W, psi, a.one);
     }
     // keep the loads of one direction from being hoisted above the previous
@@ -680,7 +680,7 @@ __device__ __forceinline__ void dslash_block(const DParams<T> &a, int bhw, int n
     const bool valid = i_raw < a.g.vh;
     if (EPI == EPI_STORE && !valid) return;
     const int i = valid ? i_raw : a.g.vh - 1;  // idle lanes join the block reduction
-    const size_t fbytes = (size_t)12 * a.g.vh * sizeof(SS);  // one right-hand side
+    const size_t fbytes = (size_t)12 * a.g.hs * sizeof(SS);  // one right-hand side
     rsrc_t sr[R];
 #pragma unroll
     for (int rr = 0; rr < R; rr++) sr[rr] = make_rsrc((const char *)a.in + (r0 + rr) * fbytes, fbytes);
@@ -720,7 +720,7 @@ __device__ __forceinline__ void dslash_block(const DParams<T> &a, int bhw, int n
         }
     }
 
-    const int vb = a.g.vh * (int)sizeof(SS), vo = i * (int)sizeof(SS);
+    const int vb = a.g.hs * (int)sizeof(SS), vo = i * (int)sizeof(SS);
     constexpr int NQ = EPI == EPI_CG ? 2 : 1;
     double nrm[R][NQ];
 #pragma unroll
@@ -980,7 +980,7 @@ void launch_rhs(tm_ctx *c, const DslashCall &dc, hipStream_t s)
         return;
     } else {
         if (dc.epi == EPI_CG) {  // not capturing here: allocation is allowed
-            const size_t fb = (size_t)prec_bytes(dc.spinor_prec) * 12 * c->geo.vh * n;
+            const size_t fb = (size_t)prec_bytes(dc.spinor_prec) * 12 * c->geo.hs * n;
             tc.r = ws_get(c, "tune_r", fb);
             tc.rho = dc.rho ? ws_get(c, "tune_rho", fb) : nullptr;
         }

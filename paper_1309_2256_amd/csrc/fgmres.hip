@@ -7,7 +7,7 @@
 // recomputed in FP64 and the cycle restarts from it.
 //
 // Vectors are full fields as two half-lattice FP64 blocks, the even block
-// [nrhs][12][vh] followed by the odd one; the preconditioned directions z_j
+// [nrhs][12][hs] followed by the odd one; the preconditioned directions z_j
 // are kept in FP32 (the precision the network returns them in), so
 // x = x0 + sum_j y_j z_j uses exactly the vectors that M was applied to.
 #include <algorithm>
@@ -37,25 +37,29 @@ __device__ __forceinline__ cx<double> ldv(const SV *p, size_t k)
 }
 
 // part[((r*kChunk + i)*2 + h)*nblk + blk] (re, im) = block sums of conj(v_i) w
-// over half h of right-hand side r; grid (nblk, nrhs, 2)
+// over half h of right-hand side r (the vh valid sites of its 12 planes of
+// stride ps; pad sites skipped); grid (nblk, nrhs, 2)
 template <typename SV>
 __global__ __launch_bounds__(kBlock) void k_mdot(const SV *V, size_t vstride, int nb, const double2 *w, size_t n,
-                                                 size_t hs, double2 *part)
+                                                 size_t half, int vh, int ps, double2 *part)
 {
     const int r = blockIdx.y, h = blockIdx.z, nblk = gridDim.x;
-    const size_t base = h * hs + (size_t)r * n;
+    const size_t base = h * half + (size_t)r * n;
     double acc[2 * kChunk];
 #pragma unroll
     for (int q = 0; q < 2 * kChunk; q++) acc[q] = 0;
-    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)nblk * kBlock) {
-        const double2 wv = w[base + e];
+    for (int k = 0; k < 12; k++) {
+        for (int si = blockIdx.x * kBlock + threadIdx.x; si < vh; si += nblk * kBlock) {
+            const size_t e = (size_t)k * ps + si;
+            const double2 wv = w[base + e];
 #pragma unroll
-        for (int i = 0; i < kChunk; i++)
-            if (i < nb) {
-                const cx<double> v = ldv(V, i * vstride + base + e);
-                acc[2 * i] = fma(v.r, wv.x, fma(v.i, wv.y, acc[2 * i]));
-                acc[2 * i + 1] = fma(v.r, wv.y, fma(-v.i, wv.x, acc[2 * i + 1]));
-            }
+            for (int i = 0; i < kChunk; i++)
+                if (i < nb) {
+                    const cx<double> v = ldv(V, i * vstride + base + e);
+                    acc[2 * i] = fma(v.r, wv.x, fma(v.i, wv.y, acc[2 * i]));
+                    acc[2 * i + 1] = fma(v.r, wv.y, fma(-v.i, wv.x, acc[2 * i + 1]));
+                }
+        }
     }
     __shared__ double red[kBlock / 64][2 * kChunk];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -96,10 +100,10 @@ __global__ void k_mdot_finish(const double2 *part, int nb, int nblk, int nrhs, d
 template <typename SV>
 __global__ __launch_bounds__(kBlock) void k_maxpy(double2 *w, const SV *V, size_t vstride, int nb,
                                                   const double2 *__restrict__ coef, int ld, int i0, double sign,
-                                                  size_t n, size_t hs)
+                                                  size_t n, size_t half)
 {
     const int r = blockIdx.y, h = blockIdx.z;
-    const size_t base = h * hs + (size_t)r * n;
+    const size_t base = h * half + (size_t)r * n;
     cx<double> cf[kChunk];
 #pragma unroll
     for (int i = 0; i < kChunk; i++) {
@@ -216,7 +220,7 @@ __global__ void k_backsolve(GState st, double2 *y, int m, int nrhs)
 struct Fg {
     tm_ctx *c;
     int nrhs, m;
-    size_t n, hs;  // elements per right-hand side per half, per half
+    size_t n, hs;  // elements per right-hand side per half (pads included), per half
     hipStream_t s;
     double2 *part;
 };
@@ -230,7 +234,7 @@ void mdot(Fg &f, const SV *V, size_t vstride, int nb, const double2 *w, double2 
     for (int c0 = 0; c0 < nb; c0 += kChunk) {
         const int k = std::min(kChunk, nb - c0);
         hipLaunchKernelGGL(k_mdot<SV>, dim3(kDotBlk, f.nrhs, 2), dim3(kBlock), 0, f.s, V + c0 * vstride, vstride, k,
-                           w, f.n, f.hs, f.part);
+                           w, f.n, f.hs, f.c->geo.vh, f.c->geo.hs, f.part);
         TM_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_mdot_finish, dim3((f.nrhs * k + 63) / 64), dim3(64), 0, f.s, (const double2 *)f.part, k,
                            kDotBlk, f.nrhs, out, ld, i0 + c0);
@@ -274,7 +278,7 @@ SolveOut fgmres_halves(tm_ctx *c, void *xe, void *xo, const void *be, const void
     const int m = p.check_every > 0 ? p.check_every : 16;
     TM_REQUIRE(m >= 1 && m <= kMaxM, "restart length must be in [1, 32]");
     const double epsp = eps_of(c, p.mu_sign);
-    Fg f{c, nrhs, m, (size_t)12 * c->geo.vh, (size_t)12 * c->geo.vh * nrhs, s, nullptr};
+    Fg f{c, nrhs, m, (size_t)12 * c->geo.hs, (size_t)12 * c->geo.hs * nrhs, s, nullptr};
     const size_t vs = 2 * f.hs;  // complex elements per full vector (all rhs)
     f.part = (double2 *)ws_get(c, "fg_part", sizeof(double2) * nrhs * kChunk * 2 * kDotBlk);
     double2 *V = (double2 *)ws_get(c, "fg_V", sizeof(double2) * vs * (m + 1));

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(S *even, S *odd, const double2 
 #pragma unroll
     for (int k = 0; k < 12; k++) {
         double2 v = full[((size_t)r * V + s) * 12 + k];
-        stT<double>(dst, (size_t)(r * 12 + k) * g.vh + i, cx<double>{sc * v.x, sc * v.y});
+        stT<double>(dst, (size_t)(r * 12 + k) * g.hs + i, cx<double>{sc * v.x, sc * v.y});
     }
 }
 
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack(double2 *full, const S *even,
     const S *src = p ? odd : even;
 #pragma unroll
     for (int k = 0; k < 12; k++) {
-        cx<double> v = ldT<double>(src, (size_t)(r * 12 + k) * g.vh + i);
+        cx<double> v = ldT<double>(src, (size_t)(r * 12 + k) * g.hs + i);
         full[((size_t)r * V + s) * 12 + k] = make_double2(v.r, v.i);
     }
 }
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(double2 *even, double2 *odd, G
         for (int d = 0; d < nsc; d++)
             for (int k = 0; k < 12; k++) {
                 const bool keep = on && (!dilution || k == d);
-                dst[(size_t)((q * nsc + d) * 12 + k) * g.vh + i] = keep ? eta[k] : make_double2(0, 0);
+                dst[(size_t)((q * nsc + d) * 12 + k) * g.hs + i] = keep ? eta[k] : make_double2(0, 0);
             }
     }
 }
@@ -340,8 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_outer(const S *ve, const S *vo, cons
                 cx<double> a[12], b[12];
 #pragma unroll
                 for (int k = 0; k < 12; k++) {
-                    a[k] = ldT<double>(v, (size_t)(r * 12 + k) * g.vh + i);
-                    b[k] = ldT<double>(w, (size_t)(r * 12 + k) * g.vh + i);
+                    a[k] = ldT<double>(v, (size_t)(r * 12 + k) * g.hs + i);
+                    b[k] = ldT<double>(w, (size_t)(r * 12 + k) * g.hs + i);
                 }
 #pragma unroll
                 for (int sb = 0; sb < 4; sb++)

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_sites(const double2 *ve, const
         cx<double> a[12], b[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            const double2 va = v[(size_t)(r * 12 + k) * g.vh + i], vb = w[(size_t)(r * 12 + k) * g.vh + i];
+            const double2 va = v[(size_t)(r * 12 + k) * g.hs + i], vb = w[(size_t)(r * 12 + k) * g.hs + i];
             a[k] = {va.x, va.y};
             b[k] = {vb.x, vb.y};
         }
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_deriv_sites(const double2 *ve,
     c4[3] = (int)(q2 / g.L[2]);
     const int p = (c4[0] + c4[1] + c4[2] + c4[3]) & 1;
     const size_t i = (size_t)(s >> 1);
-    const size_t vh = (size_t)g.vh;
+    const size_t vh = (size_t)g.vh, hs = (size_t)g.hs;  // link and spinor plane strides
     int cf[4] = {c4[0], c4[1], c4[2], c4[3]}, cb[4] = {c4[0], c4[1], c4[2], c4[3]};
     cf[mu] = cf[mu] + 1 == g.L[mu] ? 0 : cf[mu] + 1;
     cb[mu] = cb[mu] == 0 ? g.L[mu] - 1 : cb[mu] - 1;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_deriv_sites(const double2 *ve,
         cx<double> ff[3], fb[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            const double2 x1 = f[(base + a * 3 + c) * vh + jf], x2 = f[(base + a * 3 + c) * vh + jb];
+            const double2 x1 = f[(base + a * 3 + c) * hs + jf], x2 = f[(base + a * 3 + c) * hs + jb];
             ff[c] = {x1.x, x1.y};
             fb[c] = {x2.x, x2.y};
         }
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_deriv_sites(const double2 *ve,
         cx<double> wx[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            const double2 a = ws[(base + k) * vh + i];
+            const double2 a = ws[(base + k) * hs + i];
             wx[k] = {a.x, a.y};
         }
 #pragma unroll
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_deriv_sites(const double2 *ve,
         cx<double> vx[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            const double2 a = vs[(base + k) * vh + i];
+            const double2 a = vs[(base + k) * hs + i];
             vx[k] = {a.x, a.y};
         }
 #pragma unroll

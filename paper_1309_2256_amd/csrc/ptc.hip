@@ -75,10 +75,10 @@ __device__ __forceinline__ void transport_at(cx<float> out[12], int k, const S *
                                              const float2 *links, const Geo &g, int i, int x, int y, int z,
                                              int t)
 {
-    const size_t vh = (size_t)g.vh;
+    const size_t vh = (size_t)g.vh, hs = (size_t)g.hs;  // link and field plane strides
     if (k == 0) {
 #pragma unroll
-        for (int e = 0; e < 12; e++) out[e] = ldT<float>(same, e * vh + i);
+        for (int e = 0; e < 12; e++) out[e] = ldT<float>(same, e * hs + i);
         return;
     }
     const int d = k - 1;
@@ -90,12 +90,12 @@ __device__ __forceinline__ void transport_at(cx<float> out[12], int k, const S *
         W[e] = {w.x, w.y};
     }
 #pragma unroll
-    for (int e = 0; e < 12; e++) f[e] = ldT<float>(other, e * vh + j);
+    for (int e = 0; e < 12; e++) f[e] = ldT<float>(other, e * hs + j);
     colour_mul(out, W, f);
 }
 
 // u_k (parity p) = sum_k' A[k][k'] T_k' in, for kKG consecutive k per thread.
-// grid (site blocks, nrhs, 3); u layout [9][nrhs][12][vh].
+// grid (site blocks, nrhs, 3); u layout [9][nrhs][12][hs].
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_ptc_mix(const S *in_same, const S *in_other, const float2 *links,
                                                     const float2 *__restrict__ A, float2 *u, Geo g, int p,
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_ptc_mix(const S *in_same, const S *i
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.vh) return;
     const int r = blockIdx.y, k0 = blockIdx.z * kKG;
-    const size_t fs = (size_t)12 * g.vh;
+    const size_t fs = (size_t)12 * g.hs;
     const S *same = in_same + r * fs, *other = in_other + r * fs;
     int x, y, z, t;
     eo_coords(g, p, i, x, y, z, t);
@@ -131,12 +131,12 @@ __global__ __launch_bounds__(kBlock) void k_ptc_mix(const S *in_same, const S *i
                 }
         }
     }
-    const size_t vh = (size_t)g.vh;
+    const size_t hs = (size_t)g.hs;
 #pragma unroll
     for (int kk = 0; kk < kKG; kk++) {
         float2 *uo = u + ((size_t)(k0 + kk) * nrhs + r) * fs;
 #pragma unroll
-        for (int e = 0; e < 12; e++) uo[e * vh + i] = make_float2(acc[kk][e].r, acc[kk][e].i);
+        for (int e = 0; e < 12; e++) uo[e * hs + i] = make_float2(acc[kk][e].r, acc[kk][e].i);
     }
 }
 
@@ -179,7 +179,7 @@ __global__ void k_ptc_afrag(const float2 *A, bf16x8 *frag)
 }
 
 // u_k (parity p) for all nine k on the matrix cores; block of 4 waves = 64
-// sites, grid (site blocks of 64, nrhs).  u layout [9][nrhs][12][vh].
+// sites, grid (site blocks of 64, nrhs).  u layout [9][nrhs][12][hs].
 template <typename S>
 __global__ __launch_bounds__(kBlock, 2) void k_ptc_mix_mfma(const S *in_same, const S *in_other,
                                                             const float2 *links, const bf16x8 *frag, float2 *u,
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_ptc_mix_mfma(const S *in_same, co
     const bool valid = i_raw < g.vh;
     const int i = valid ? i_raw : g.vh - 1;
     const int r = blockIdx.y;
-    const size_t fs = (size_t)12 * g.vh, vh = (size_t)g.vh;
+    const size_t fs = (size_t)12 * g.hs, hs = (size_t)g.hs;
     const S *same = in_same + r * fs, *other = in_other + r * fs;
     int x, y, z, t;
     eo_coords(g, p, i, x, y, z, t);
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_ptc_mix_mfma(const S *in_same, co
                 for (int e = 0; e < 2; e++) {
                     const int cr = 8 * tt + 2 * grp + e, k = cr / 4, a = cr % 4;
                     if (k < 9)
-                        u[(((size_t)k * nrhs + r) * 12 + 3 * a + c) * vh + i] =
+                        u[(((size_t)k * nrhs + r) * 12 + 3 * a + c) * hs + i] =
                             make_float2(acc[tt][2 * e], acc[tt][2 * e + 1]);
                 }
         }
@@ -253,14 +253,14 @@ __global__ __launch_bounds__(kBlock) void k_ptc_gather(const float2 *u_same, con
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.vh) return;
     const int r = blockIdx.y;
-    const size_t fs = (size_t)12 * g.vh, vh = (size_t)g.vh;
+    const size_t fs = (size_t)12 * g.hs, hs = (size_t)g.hs;
     int x, y, z, t;
     eo_coords(g, p, i, x, y, z, t);
     cx<float> acc[12];
     const float2 *u0 = u_same + (size_t)r * fs;
 #pragma unroll
     for (int e = 0; e < 12; e++) {
-        const float2 v = u0[e * vh + i];
+        const float2 v = u0[e * hs + i];
         acc[e] = {v.x, v.y};
     }
 #pragma unroll 1
@@ -273,26 +273,29 @@ __global__ __launch_bounds__(kBlock) void k_ptc_gather(const float2 *u_same, con
     }
     SO *o = out + (size_t)r * fs;
 #pragma unroll
-    for (int e = 0; e < 12; e++) stT<float>(o, e * vh + i, acc[e]);
+    for (int e = 0; e < 12; e++) stT<float>(o, e * hs + i, acc[e]);
 }
 
 // delta = 2 (out - e) / (nrhs |e_b|^2) for sample b, partial |out - e|^2
-// per block.  grid (blocks, nrhs); part [nrhs][nblk].
+// per block, over the vh valid sites of each plane (stride hs; the pad
+// sites of delta are not written).  grid (blocks, nrhs); part [nrhs][nblk].
 template <typename SE>
 __global__ __launch_bounds__(kBlock) void k_ptc_delta(const float2 *out, const SE *e, const double *en2,
-                                                      float2 *delta, double *part, size_t n, int nblk)
+                                                      float2 *delta, double *part, int vh, int hs, int nblk)
 {
     const int r = blockIdx.y;
-    const size_t base = (size_t)r * n;
+    const size_t base = (size_t)r * 12 * hs;
     const float sc = (float)(2.0 / (gridDim.y * en2[r]));
     double acc = 0;
-    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (size_t)gridDim.x * kBlock) {
-        const float2 o = out[base + k];
-        const cx<float> ev = ldT<float>(e, base + k);
-        const float dr = o.x - ev.r, di = o.y - ev.i;
-        acc += (double)dr * dr + (double)di * di;
-        delta[base + k] = make_float2(sc * dr, sc * di);
-    }
+    for (int q = 0; q < 12; q++)
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < vh; i += gridDim.x * kBlock) {
+            const size_t k = base + (size_t)q * hs + i;
+            const float2 o = out[k];
+            const cx<float> ev = ldT<float>(e, k);
+            const float dr = o.x - ev.r, di = o.y - ev.i;
+            acc += (double)dr * dr + (double)di * di;
+            delta[k] = make_float2(sc * dr, sc * di);
+        }
     __shared__ double red[kBlock / 64];
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -320,19 +323,22 @@ __global__ void k_ptc_loss_finish(const double *part0, const double *part1, cons
 }
 
 // Residual loss: w -= r (r in the pair-store precision), partial |w|^2 per
-// block.  grid (blocks, nrhs); part [nrhs][nblk].
+// block, over the vh valid sites of each plane (stride hs).  grid (blocks,
+// nrhs); part [nrhs][nblk].
 template <typename SR>
-__global__ __launch_bounds__(kBlock) void k_ptc_resid(float2 *w, const SR *r, double *part, size_t n, int nblk)
+__global__ __launch_bounds__(kBlock) void k_ptc_resid(float2 *w, const SR *r, double *part, int vh, int hs, int nblk)
 {
-    const size_t base = (size_t)blockIdx.y * n;
+    const size_t base = (size_t)blockIdx.y * 12 * hs;
     double acc = 0;
-    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (size_t)gridDim.x * kBlock) {
-        const float2 o = w[base + k];
-        const cx<float> rv = ldT<float>(r, base + k);
-        const float dr = o.x - rv.r, di = o.y - rv.i;
-        acc += (double)dr * dr + (double)di * di;
-        w[base + k] = make_float2(dr, di);
-    }
+    for (int q = 0; q < 12; q++)
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < vh; i += gridDim.x * kBlock) {
+            const size_t k = base + (size_t)q * hs + i;
+            const float2 o = w[k];
+            const cx<float> rv = ldT<float>(r, k);
+            const float dr = o.x - rv.r, di = o.y - rv.i;
+            acc += (double)dr * dr + (double)di * di;
+            w[k] = make_float2(dr, di);
+        }
     __shared__ double red[kBlock / 64];
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_ptc_grad(const S *in_same, const S *
 {
     const int pair = blockIdx.y, k = pair / 9, kp = pair % 9;
     const int kbar = k == 0 ? 0 : (k <= 4 ? k + 4 : k - 4);
-    const size_t fs = (size_t)12 * g.vh;
+    const size_t fs = (size_t)12 * g.hs;
     double acc[32];
 #pragma unroll
     for (int q = 0; q < 32; q++) acc[q] = 0;
@@ -527,7 +533,7 @@ template <typename S>
 void forward_t(tm_ctx *c, const void *in_e, const void *in_o, float2 *out_e, float2 *out_o, int nrhs, hipStream_t s)
 {
     ensure_links32(c, s);
-    const size_t fl = (size_t)12 * c->geo.vh * nrhs;
+    const size_t fl = (size_t)12 * c->geo.hs * nrhs;
     float2 *u[2] = {(float2 *)ws_get(c, "ptc_u0", sizeof(float2) * 9 * fl),
                     (float2 *)ws_get(c, "ptc_u1", sizeof(float2) * 9 * fl)};
     const float2 *A = (const float2 *)ws_get(c, "ptc_A", sizeof(float2) * 81 * 16);
@@ -578,7 +584,7 @@ template <typename S>
 void loss_grad_t(tm_ctx *c, LossKind kind, double epsp, const void *r_e, const void *r_o, const void *e_e,
                  const void *e_o, const double *en2, int nrhs, double *loss, hipStream_t s)
 {
-    const size_t fl = (size_t)12 * c->geo.vh * nrhs;
+    const size_t fl = (size_t)12 * c->geo.hs * nrhs;
     float2 *out[2] = {(float2 *)ws_get(c, "ptc_out0", sizeof(float2) * fl),
                       (float2 *)ws_get(c, "ptc_out1", sizeof(float2) * fl)};
     forward_t<S>(c, r_e, r_o, out[0], out[1], nrhs, s);
@@ -591,7 +597,7 @@ void loss_grad_t(tm_ctx *c, LossKind kind, double epsp, const void *r_e, const v
         const S *ee[2] = {(const S *)e_e, (const S *)e_o};
         for (int p = 0; p < 2; p++) {
             hipLaunchKernelGGL(k_ptc_delta<S>, dim3(nbd, nrhs), dim3(kBlock), 0, s, (const float2 *)out[p], ee[p],
-                               en2, dl[p], part[p], (size_t)12 * c->geo.vh, nbd);
+                               en2, dl[p], part[p], c->geo.vh, c->geo.hs, nbd);
             TM_HIP(hipGetLastError());
         }
     } else {
@@ -604,14 +610,14 @@ void loss_grad_t(tm_ctx *c, LossKind kind, double epsp, const void *r_e, const v
         const S *rr[2] = {(const S *)r_e, (const S *)r_o};
         for (int p = 0; p < 2; p++) {
             hipLaunchKernelGGL(k_ptc_resid<S>, dim3(nbd, nrhs), dim3(kBlock), 0, s, w[p], rr[p], part[p],
-                               (size_t)12 * c->geo.vh, nbd);
+                               c->geo.vh, c->geo.hs, nbd);
             TM_HIP(hipGetLastError());
         }
         // dl = M^dag w = R(-eps) w_p - kappa Hop^dag w_{1-p}, scaled by 2 / (n |r|^2)
         for (int p = 0; p < 2; p++)
             op_dslash(c, dl[p], w[1 - p], w[p], nrhs, TM_F32, p, 1, sd_scalar(-k), sd_twist(-epsp), s);
         for (int p = 0; p < 2; p++) {
-            hipLaunchKernelGGL(k_ptc_scale, dim3(nbd, nrhs), dim3(kBlock), 0, s, dl[p], en2, (size_t)12 * c->geo.vh);
+            hipLaunchKernelGGL(k_ptc_scale, dim3(nbd, nrhs), dim3(kBlock), 0, s, dl[p], en2, (size_t)12 * c->geo.hs);
             TM_HIP(hipGetLastError());
         }
     }
@@ -685,8 +691,8 @@ void reset_adam(tm_ctx *c, hipStream_t s)
     c->ptc_step = 0;
 }
 
-// store layout: [parity][capacity][12][vh] of the store precision
-size_t store_half_bytes(const tm_ctx *c) { return prec_bytes(c->ptc_store) * 12 * (size_t)c->geo.vh; }
+// store layout: [parity][capacity][12][hs] of the store precision
+size_t store_half_bytes(const tm_ctx *c) { return prec_bytes(c->ptc_store) * 12 * (size_t)c->geo.hs; }
 
 }  // namespace
 
@@ -883,7 +889,7 @@ extern "C" int tm_ptc_pairs_reserve(tm_ctx *c, int capacity, int store_prec)
 
 namespace {
 
-// append n pairs given as FP64 half fields (r_e, r_o, e_e, e_o; [n][12][vh]
+// append n pairs given as FP64 half fields (r_e, r_o, e_e, e_o; [n][12][hs]
 // each) to the store, converted to its precision; pairs with r = 0 or
 // e = 0 in the stored precision are dropped when skip_zero, else an error.
 // Returns the number appended.

@@ -37,7 +37,7 @@ std::vector<double> norms_host(tm_ctx *c, const void *v, int prec, int nrhs, hip
     return h;
 }
 
-size_t field_bytes(tm_ctx *c, int prec, int nrhs) { return prec_bytes(prec) * 12 * (size_t)c->geo.vh * nrhs; }
+size_t field_bytes(tm_ctx *c, int prec, int nrhs) { return prec_bytes(prec) * 12 * (size_t)c->geo.hs * nrhs; }
 
 void copy_field(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
@@ -609,7 +609,7 @@ void contract_noise(tm_ctx *c, int estimators, int derivative, const void *ee, c
     auto outer_loops = [&](const void *ve, const void *vo, const void *we, const void *wo, GammaForm form,
                            cx<double> coef, bool deriv, cx<double> *out, bool slice_ok = false) {
         if (!mom && slice_ok && td && td->period > 0) {
-            const size_t grp = (size_t)td->nsc * 12 * c->geo.vh * sizeof(double2);
+            const size_t grp = field_bytes(c, TM_F64, td->nsc);
             std::vector<cx<double>> acc((size_t)16 * Lt, cx<double>{0, 0});
             for (int q = 0; q < td->n_off; q++) {
                 outer_slices_host(c, (const char *)ve + q * grp, (const char *)vo + q * grp,

@@ -76,6 +76,7 @@ def test_create_rejects_bad_bc_and_nulls():
     # calls on a null context fail cleanly
     assert P.tm_dslash(None, None, None, 1, 0, 1, 0, 0, None) == P.TM_ERR_ARG
     assert P.tm_last_error(None) == b"null context"
+    assert P.tm_half_stride(None) == 0
     P.tm_destroy(None)
 
 

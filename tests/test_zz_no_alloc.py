@@ -1,7 +1,8 @@
 """tm_dslash_noalloc against tm_dslash: the same operator from the device
 scratch array instead of context workspace.
 
-Both entry points run the same kernels, so outputs are compared bit for bit,
+Both entry points run the same kernels, so outputs are compared bit for bit
+(on the valid half-sites; the pad sites of the half layout are unspecified),
 on two calls in a row with the second on fewer right-hand sides (the scratch
 keeps the first call's contents), for the kinds with intermediate fields
 (Schur complement, its adjoint, the normal operator, the full operator) and
@@ -38,6 +39,12 @@ def ctx():
     c.close()
 
 
+def valid_sites(c, t, nrhs):
+    """The valid half-sites of every plane of a half field given as bytes
+    (the hs - vh pad sites at the end of each plane are unspecified)."""
+    return t.view(nrhs, 12, c.hs, -1)[:, :, :c.vh]
+
+
 def half_input(c, prec, nrhs, seed):
     full = cuda(S.random_spinor(L, seed, nrhs))
     e = torch.zeros(c.half_numel(prec, nrhs), dtype=torch.uint8, device=DEV)
@@ -61,7 +68,7 @@ def test_half_kinds_match_tm_dslash(ctx, kind, prec):
         ctx.dslash(ref, inp, nrhs, kind, mu, prec)
         ctx.dslash_noalloc(out, inp, nrhs, kind, mu, prec)
         torch.cuda.synchronize()
-        assert torch.equal(out, ref), (kind, prec, nrhs)
+        assert torch.equal(valid_sites(ctx, out, nrhs), valid_sites(ctx, ref, nrhs)), (kind, prec, nrhs)
 
 
 def test_full_kinds_match_tm_dslash(ctx):
@@ -100,6 +107,6 @@ def test_missing_link_copy_is_refused():
         c.dslash(ref, inp, 1, P.TM_RINV_HOP_OE, 1, P.TM_F16)  # builds the copy
         c.dslash_noalloc(out, inp, 1, P.TM_RINV_HOP_OE, 1, P.TM_F16)
         torch.cuda.synchronize()
-        assert torch.equal(out, ref)
+        assert torch.equal(valid_sites(c, out, 1), valid_sites(c, ref, 1))
     finally:
         c.close()
