@@ -518,8 +518,10 @@ def time_dilution_leg(P, S, torch, dev):
 def batch_leg(P, S, torch, dev):
     """Uneven batch: 8^3x16 / 12^3x24 / 16^3x32 lattices with 4 / 2 / 1 Z4
     noises x 12 spin-colour dilutions (48 / 24 / 12 right-hand sides), mixed
-    CG to 1e-9 and standard + one-end loops, solved as one batch (one
-    graph-captured iteration stream) and, for comparison, lattice by lattice."""
+    CG to 1e-9 and standard + one-end loops, solved as one batch (the
+    library's timed choice between the persistent kernel and the graph of
+    multi-instance launches; each form also forced and timed) and, for
+    comparison, lattice by lattice."""
     names = ("c4a", "c4b", "c4c")
     ctxs = [make_context(P, S, torch, dev, n)[0] for n in names]
     hp = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
@@ -531,14 +533,31 @@ def batch_leg(P, S, torch, dev):
         p.hp = hp
         return p
     plist = [lp_of(k, n) for k, n in enumerate((4, 2, 1))]
-    batch = P.Batch(ctxs)
-    batch.loops(plist)  # warm
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    _, bst, _ = batch.loops(plist)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t
-    batch.close()
+
+    def timed_batch(form):
+        # form: None = the library's timed choice, "1" persistent kernel, "0" graph
+        old = os.environ.get("TM_BATCH_PERSIST")
+        if form is not None:
+            os.environ["TM_BATCH_PERSIST"] = form
+        try:
+            batch = P.Batch(ctxs)
+        finally:
+            if form is not None:
+                if old is None:
+                    os.environ.pop("TM_BATCH_PERSIST")
+                else:
+                    os.environ["TM_BATCH_PERSIST"] = old
+        batch.loops(plist)  # warm (and, for the timed choice, one group of each form)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st, _ = batch.loops(plist)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        batch.close()
+        return dt, st
+    tb, bst = timed_batch(None)
+    tp, _ = timed_batch("1")
+    tg, _ = timed_batch("0")
     for c, p in zip(ctxs, plist):
         c.loops(p)  # warm
     torch.cuda.synchronize()
@@ -555,6 +574,7 @@ def batch_leg(P, S, torch, dev):
     return {"workload": "8^3x16 / 12^3x24 / 16^3x32 (links 0.3/0.2/0.15, seeds 1041-1043, kappa "
                         "0.124, 2 kappa mu 0.005), 48/24/12 RHS, mixed CG to 1e-9, STD + one-end loops",
             "solves": n, "all_verified": ok, "batch_seconds": tb, "batch_solves_per_s": n / tb,
+            "persistent_kernel_seconds": tp, "graph_seconds": tg,
             "sequential_seconds": ts, "sequential_solves_per_s": n / ts, "speedup": ts / tb,
             "iters": [q.iters_hp for q in bst]}
 

@@ -1,11 +1,14 @@
-// Uneven batches: several lattices (contexts) solved together.  Every CG
-// iteration of all instances is four multi-instance half-Dslash launches
-// (one kernel each, all lattices in one grid) plus per-instance scalar and
-// vector kernels; a group of `check_every` iterations is captured once into a
-// HIP graph and replayed, so the host issues one graph launch per group and
-// reads the convergence scalars only between groups.  Reliable updates and
-// convergence decisions are per instance, with the same cadence as a single
-// solve, so each instance follows exactly the arithmetic of its own solve.
+// Uneven batches: several lattices (contexts) solved together.  A group of
+// `check_every` CG iterations of all instances is one launch of the
+// persistent batch kernel (up to four instances: the four half-Dslash
+// stages, the CG scalars and the vector update of every iteration, with grid
+// barriers between the stages; see dslash.hip).  Otherwise every iteration
+// is four multi-instance half-Dslash launches (all lattices in one grid)
+// plus per-instance scalar and vector kernels, the group captured once into
+// a HIP graph and replayed.  Either way the host reads the convergence
+// scalars only between groups.  Reliable updates and convergence decisions
+// are per instance, with the same cadence as a single solve, so each
+// instance follows exactly the arithmetic of its own solve.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -25,10 +28,23 @@ struct tm_batch {
     std::vector<int> graph_set;  // instances captured in the current graph
     int graph_iters = 0, graph_R = 0;
     std::map<std::vector<int>, int> tuned_R;  // (prec, nrhs...) -> RHS per thread
-    // debugging switches (environment): TM_BATCH_EAGER=1 replays the
-    // iterations without graph capture, TM_BATCH_SINGLE=1 uses per-instance
-    // launches instead of the multi-instance kernels
+    PersistBatch pb;
+    std::vector<int> pb_set;  // instances of the prepared persistent launch
+    // launch form per (precision, nrhs...): 1 persistent kernel, 0 graph;
+    // untuned keys time one group of each form and keep the faster (their
+    // results are bit-identical)
+    std::map<std::vector<int>, int> tuned_form;
+    std::map<std::vector<int>, float> form_ms[2];
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    // switches (environment): TM_BATCH_PERSIST=1 / 0 forces the persistent
+    // kernel / the graph of multi-instance launches (default: timed choice),
+    // TM_BATCH_EAGER=1 replays the graph's iterations without capture,
+    // TM_BATCH_SINGLE=1 uses per-instance launches; TM_BATCH_SPIN_LIMIT sets
+    // the persistent kernel's barrier wait bound in polls (each at least
+    // ~0.5 us: the default gives up after 0.5 s or more, far beyond any stage)
+    int persist = -1;  // -1 timed choice, 1 persistent, 0 graph
     bool eager = false, single_launches = false;
+    unsigned long long spin_limit = 1ull << 20;
 };
 
 namespace {
@@ -40,6 +56,7 @@ void drop_graph(tm_batch *b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_set.clear();
+    b->pb_set.clear();
 }
 
 template <typename F>
@@ -97,6 +114,12 @@ int choose_R(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set)
 {
     const int prec = S[set[0]].lp;
     if (prec == TM_F64) return 1;
+    if (const char *e = getenv("TM_BATCH_RHS_TILE")) {  // fixed tile, if it divides every nrhs
+        const int R = atoi(e);
+        bool ok = R >= 1 && R <= 3;
+        for (int i : set) ok = ok && S[i].nrhs % R == 0;
+        if (ok) return R;
+    }
     std::vector<int> key{prec};
     for (int i : set) key.push_back(S[i].nrhs);
     auto it = b->tuned_R.find(key);
@@ -151,6 +174,48 @@ void build_graph(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &se
     b->graph_R = R;
 }
 
+// the persistent kernel runs the FP32-arithmetic solvers (FP32, FP16 or
+// BF16 storage); plain FP64 batches take the graph path
+bool persist_usable(tm_batch *b, const std::vector<Solver> &S, const std::vector<int> &set)
+{
+    return b->persist != 0 && !b->eager && !b->single_launches && (int)set.size() <= kPersistInst &&
+           S[set[0]].lp != TM_F64 && persist_supported(b->device);
+}
+
+std::vector<int> form_key(const std::vector<Solver> &S, const std::vector<int> &set)
+{
+    std::vector<int> key{S[set[0]].lp};
+    for (int i : set) key.push_back(S[i].nrhs);
+    return key;
+}
+
+// K iterations of the instances in `set` as one persistent launch; false
+// (nothing run) if the runtime refuses the cooperative launch.  `timed`:
+// record the start event after the set-up, right before the launch.
+bool run_persist(tm_batch *b, std::vector<Solver> &S, const std::vector<int> &set, int K, bool timed)
+{
+    if (b->pb_set != set) {
+        const int R = choose_R(b, S, set);
+        std::vector<PersistInst> v;
+        for (int i : set) {
+            PersistInst q;
+            q.c = S[i].c;
+            for (int k = 0; k < 4; k++) q.st[k] = S[i].stage(k + 1);
+            q.x = S[i].w.x;
+            q.sc = S[i].w.dsc;
+            q.delta = S[i].delta;
+            v.push_back(q);
+        }
+        persist_prepare(b->pb, v, R, b->stream);
+        b->pb_set = set;
+    }
+    if (timed) TM_HIP(hipEventRecord(b->ev[0], b->stream));
+    if (!persist_launch(b->pb, K, b->spin_limit, b->stream)) return false;
+    if (persist_failed(b->pb, b->stream))
+        throw TmError{TM_ERR_HIP, "persistent batch kernel: a grid barrier wait exceeded its limit"};
+    return true;
+}
+
 // Run all solvers to completion.
 void run_batch(tm_batch *b, std::vector<Solver> &S)
 {
@@ -176,12 +241,42 @@ void run_batch(tm_batch *b, std::vector<Solver> &S)
         // recorded launch (a graph is recorded once and replayed)
         for (int i : set) S[i].c->acct_pause++;
         try {
-            if (b->eager) {
+            // launch form: forced, tuned, or (untuned) the one not timed yet
+            const std::vector<int> key = form_key(S, set);
+            int form = 0;
+            bool timing = false;
+            if (persist_usable(b, S, set)) {
+                auto it = b->tuned_form.find(key);
+                if (b->persist == 1) {
+                    form = 1;
+                } else if (it != b->tuned_form.end()) {
+                    form = it->second;
+                } else {
+                    form = b->form_ms[1].count(key) ? 0 : 1;
+                    timing = true;
+                }
+            }
+            bool ran = false;
+            if (form == 1) {
+                ran = run_persist(b, S, set, K, timing);
+                if (!ran) b->persist = 0;  // refused: the graph path from now on
+            }
+            if (!ran && b->eager) {
                 if (!b->single_launches) prepare_stages(b, S, set, choose_R(b, S, set));
                 for (int k = 0; k < K; k++) launch_iteration(b, S, set);
-            } else {
+            } else if (!ran) {
                 if (b->graph_set != set || b->graph_iters != K) build_graph(b, S, set, K);
+                if (timing) TM_HIP(hipEventRecord(b->ev[0], b->stream));  // graph set-up not timed
                 TM_HIP(hipGraphLaunch(b->exec, b->stream));
+            }
+            if (timing && ran == (form == 1)) {
+                TM_HIP(hipEventRecord(b->ev[1], b->stream));
+                TM_HIP(hipEventSynchronize(b->ev[1]));
+                float ms = 0;
+                TM_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+                b->form_ms[form][key] = ms;
+                if (b->form_ms[0].count(key) && b->form_ms[1].count(key))
+                    b->tuned_form[key] = b->form_ms[1][key] < b->form_ms[0][key] ? 1 : 0;
             }
         } catch (...) {
             for (int i : set) S[i].c->acct_pause--;
@@ -217,10 +312,15 @@ extern "C" int tm_batch_create(tm_batch **out, tm_ctx *const *ctxs, int n)
     if (!b) return TM_ERR_OOM;
     b->ctx.assign(ctxs, ctxs + n);
     b->device = ctxs[0]->device;
+    if (const char *e = getenv("TM_BATCH_PERSIST")) b->persist = atoi(e) != 0 ? 1 : 0;
+    if (const char *e = getenv("TM_BATCH_SPIN_LIMIT")) b->spin_limit = strtoull(e, nullptr, 10);
+    if (const char *e = getenv("TM_BATCH_BLOCKS_PER_CU")) b->pb.blocks_per_cu = atoi(e);
     if (const char *e = getenv("TM_BATCH_EAGER")) b->eager = atoi(e) != 0;
     if (const char *e = getenv("TM_BATCH_SINGLE")) b->single_launches = atoi(e) != 0;
     int st = bguard(b, [&]() {
         TM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        TM_HIP(hipEventCreate(&b->ev[0]));
+        TM_HIP(hipEventCreate(&b->ev[1]));
         return TM_OK;
     });
     if (st != TM_OK) {
@@ -238,6 +338,8 @@ extern "C" void tm_batch_destroy(tm_batch *b)
     drop_graph(b);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->stream) (void)hipStreamDestroy(b->stream);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
     delete b;
 }
 

@@ -4,36 +4,16 @@
 // wave-then-LDS tree) and a single block per right-hand side sums the
 // partials in a fixed order.  Products are formed in the arithmetic precision
 // and accumulated in FP64.
-#include "tm_internal.h"
+#include "cg_device.h"
 
 namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxPart = 1024;
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// sum over the block; result valid in thread 0
-__device__ __forceinline__ double block_sum(double v)
-{
-    __shared__ double red[kBlock / 64];
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double s = 0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < kBlock / 64; k++) s += red[k];
-    }
-    __syncthreads();
-    return s;
-}
+using cgdev::block_sum;
+using cgdev::sum_partials;
+static_assert(kBlock == cgdev::kThreads, "block sums assume 256 threads");
 
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_spin_diag(S *out, const S *in, int hs, cx<float> fu,
@@ -114,68 +94,23 @@ __global__ __launch_bounds__(kBlock) void k_partial_norm2(const S *v, int vh, in
     if (threadIdx.x == 0) part[(size_t)blockIdx.y * nblk + blockIdx.x] = s;
 }
 
-// out[r] = sum_b part[(r * nslot + slot) * nblk + b] for the given slot
-__device__ double sum_partials(const double *part, int nblk, int idx)
-{
-    double acc = 0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += part[(size_t)idx * nblk + b];
-    return block_sum(acc);
-}
-
 __global__ __launch_bounds__(kBlock) void k_finish_sum(const double *part, int nblk, double *out)
 {
     double s = sum_partials(part, nblk, blockIdx.x);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0; }
-
 // part layout: [rhs][nblk] (one slot)
 __global__ __launch_bounds__(kBlock) void k_finish_alpha(CGScalars *sc, const double *part, int nblk)
 {
-    const int r = blockIdx.x;
-    double qq = sum_partials(part, nblk, r);
-    if (threadIdx.x == 0) {
-        CGScalars &s = sc[r];
-        s.qq = qq;
-        if (!finite(qq) || !finite(s.rr)) s.bad = 1;
-        s.alpha = (s.active && qq > 0 && finite(qq)) ? s.rr / qq : 0.0;
-    }
+    cgdev::finish_alpha(sc, part, nblk, blockIdx.x);
 }
 
-// part layout: [slot 0: |r|^2 for all rhs][slot 1: |rho|^2 for all rhs].
-// With reliable updates (delta > 0) slot 1 is not used: the Schur residual
-// rho -= alpha q has |rho'|^2 = |rho|^2 - 2 alpha <r, p> + alpha^2 |q|^2
-// = |rho|^2 - alpha |r|^2 (CG: <r, p> = |r|^2, alpha = |r|^2 / |q|^2), a
-// recurrence whose rounding stays far below the delta^2 |rho_ref|^2 it is
-// compared with between two updates (each update resets it to the FP64
-// true residual).
+// part layout: [slot 0: |r|^2 for all rhs][slot 1: |rho|^2 for all rhs]
 __global__ __launch_bounds__(kBlock) void k_finish_beta(CGScalars *sc, const double *part, int nblk,
                                                         int nrhs, double delta)
 {
-    const int r = blockIdx.x;
-    double rr = sum_partials(part, nblk, r);
-    double rho2 = delta > 0 ? 0.0 : sum_partials(part, nblk, nrhs + r);
-    if (threadIdx.x == 0) {
-        CGScalars &s = sc[r];
-        if (delta > 0) rho2 = s.active ? fmax(s.rho2 - s.alpha * s.rr, 0.0) : s.rho2;
-        if (!finite(rr) || !finite(rho2)) s.bad = 1;
-        if (s.active) {
-            s.beta = (s.rr > 0) ? rr / s.rr : 0.0;
-            s.rr = rr;
-            s.rho2 = rho2;
-            s.iters += 1;
-            if (delta > 0) {
-                // reliable-update solver: converged estimate or residual fallen
-                // by delta since the last update -> request an update
-                if (rho2 <= s.target2 || rho2 < delta * delta * s.rho2_ref) s.want_update = 1;
-            } else if (rho2 <= s.target2) {
-                s.active = 0;
-            }
-        } else {
-            s.beta = 0.0;
-        }
-    }
+    cgdev::finish_beta(sc, part, nblk, nrhs, delta, blockIdx.x);
 }
 
 // x += alpha p; p = r + beta p  (the solution update of this iteration folded
@@ -183,21 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_finish_beta(CGScalars *sc, const dou
 template <typename S, typename XS>
 __global__ __launch_bounds__(kBlock) void k_update_px(S *p, const S *rv, XS *x, size_t n, const CGScalars *sc)
 {
-    using T = typename StoreTraits<S>::real;
-    using TX = typename StoreTraits<XS>::real;
-    const int r = blockIdx.y;
-    if (!sc[r].active && sc[r].alpha == 0.0) return;
-    const T b = sc[r].active ? (T)sc[r].beta : (T)0;
-    const TX ax = (TX)sc[r].alpha;
-    const bool upd_p = sc[r].active != 0;
-    const size_t base = (size_t)r * n;
-    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
-        const size_t k = base + e;
-        cx<T> pv = ldT<T>(p, k);
-        cx<TX> xv = ldT<TX>(x, k);
-        stT<TX>(x, k, xv + ax * cx<TX>{(TX)pv.r, (TX)pv.i});
-        if (upd_p) stT<T>(p, k, ldT<T>(rv, k) + b * pv);
-    }
+    cgdev::update_px(p, rv, x, n, sc, blockIdx.y, (size_t)blockIdx.x * kBlock + threadIdx.x, n,
+                     (size_t)gridDim.x * kBlock);
 }
 
 // complex elements of one right-hand side of a half field, pads included

@@ -17,7 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 
-#include "tm_internal.h"
+#include "cg_device.h"
 
 namespace {
 
@@ -730,7 +730,7 @@ __device__ __forceinline__ void dslash_block(const DParams<T> &a, int bhw, int n
         const rsrc_t rr_r = make_rsrc((char *)a.r + (r0 + rr) * fbytes, fbytes);
         const rsrc_t rho_r = make_rsrc((char *)a.rho + (r0 + rr) * fbytes, fbytes);
         T alpha = 0;
-        if constexpr (EPI == EPI_CG) alpha = (T)a.sc[r0 + rr].alpha;
+        if constexpr (EPI == EPI_CG) alpha = (T)cgdev::ld_coh(&a.sc[r0 + rr].alpha);
 #pragma unroll
         for (int q = 0; q < NQ; q++) nrm[rr][q] = 0;
         // all loads of this right-hand side first, then arithmetic and
@@ -792,7 +792,7 @@ __device__ __forceinline__ void dslash_block(const DParams<T> &a, int bhw, int n
             double s = 0;
 #pragma unroll
             for (int k = 0; k < kBlock / 64; k++) s += red[k][threadIdx.x];
-            a.part[((size_t)q * a.nrhs + r0 + rr) * a.nblk + sblk] = s;
+            cgdev::st_coh(a.part + ((size_t)q * a.nrhs + r0 + rr) * a.nblk + sblk, s);
         }
     }
 }
@@ -825,6 +825,185 @@ __global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_dslash_multi(co
     const int nreal = m.p[i].nblk * m.p[i].ngroups;
     if (local >= nreal) return;
     dslash_block<SS, LS, T, R, DAG, OWN, EPI>(m.p[i], local, nreal);
+}
+
+// ---------------------------------------------------------------- persistent batch
+// One launch runs `iters` CG iterations of every instance of a batch: the
+// four half-Dslash stages, the CG scalars and the vector update, separated
+// by grid-wide barriers.  The grid is sized so that every block is resident
+// (cooperative launch).  Each Dslash stage walks the virtual blocks of all
+// instances (the same (instance, site block, RHS group) decomposition and
+// XCD mapping as the multi-instance kernel: the grid is a multiple of 8, so
+// virtual block v runs on XCD v % 8); the scalar stages give one
+// (instance, right-hand side) to a block and run the code of the
+// stand-alone scalar kernels, so every instance follows its single solve
+// bit for bit.  Per iteration:
+//   S1 | S2 | S3 + alpha | S4 | beta | update |
+// (alpha is summed while the third stage runs: that stage does not read it).
+
+// Barrier state in device memory (zeroed before each launch), one 128-byte
+// line per word: arrivals of the blocks with blockIdx % 8 == j, arrivals of
+// the eight groups, the generation published to group j, the failure flag.
+constexpr int kBarLine = 32;  // unsigned words per line
+constexpr int kBarWords = 18 * kBarLine;
+__device__ __forceinline__ unsigned *bar_cnt(unsigned *b, int j) { return b + j * kBarLine; }
+__device__ __forceinline__ unsigned *bar_top(unsigned *b) { return b + 8 * kBarLine; }
+__device__ __forceinline__ unsigned *bar_gen(unsigned *b, int j) { return b + (9 + j) * kBarLine; }
+__device__ __forceinline__ unsigned *bar_fail(unsigned *b) { return b + 17 * kBarLine; }
+
+// Launch parameters, kept in device memory (read-only during the launch):
+// the stages index them with the instance number, which a kernel-argument
+// block would have to copy to per-lane scratch memory.
+template <typename T>
+struct PersistArgs {
+    DParams<T> st[4][kPersistInst];  // the stage forms of each instance
+    void *x[kPersistInst];           // solution accumulator (FP32)
+    CGScalars *sc[kPersistInst];
+    double delta[kPersistInst];
+    int start[kPersistInst + 1];     // virtual Dslash blocks, multiples of 8
+    int ustart[kPersistInst + 1];    // update work items (right-hand side x chunk)
+    int uchunks[kPersistInst];       // chunks per right-hand side
+    int fstart[kPersistInst + 1];    // scalar work items (right-hand sides)
+    int n;
+    unsigned *bar;                   // kBarWords words
+};
+
+constexpr int kUpdChunk = 8 * kBlock;  // elements per update work item
+
+// Grid-wide barrier with a bounded wait, in two levels (the blocks of each
+// of the eight residue classes of blockIdx, then the eight classes) so that
+// no address takes more than G/8 arrivals or pollers.  Returns false (in
+// every thread) when this or another block gave up; the caller then leaves
+// the kernel.
+__device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned long long spin_limit)
+{
+    __shared__ int ok;
+    // every wave waits until its own stores have reached the L2 (the
+    // workgroup barrier alone does not wait for other waves' stores); the
+    // release below then writes this L2's dirty lines back once per block
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int j = blockIdx.x & 7;
+        const unsigned per = gridDim.x >> 3;  // the grid is a multiple of 8
+        // release this block's results to the other XCDs (L2 write-back)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // the generation is read before arriving (acquire: the arrival below
+        // cannot be performed first), so it cannot have advanced yet
+        const unsigned g = __hip_atomic_load(bar_gen(bar, j), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        int good = 1;
+        if (__hip_atomic_fetch_add(bar_cnt(bar, j), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == per) {
+            // the class's counter is reset before the class arrives above (a
+            // block of the class may arrive at the next barrier as soon as
+            // the generation moves)
+            __hip_atomic_store(bar_cnt(bar, j), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            if (__hip_atomic_fetch_add(bar_top(bar), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == 8) {
+                __hip_atomic_store(bar_top(bar), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                for (int k = 0; k < 8; k++)
+                    __hip_atomic_fetch_add(bar_gen(bar, k), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        // poll about every 0.5 us, the failure flag every 32nd poll
+        unsigned long long n = 0;
+        while (__hip_atomic_load(bar_gen(bar, j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            if (++n > spin_limit ||
+                ((n & 31) == 0 && __hip_atomic_load(bar_fail(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                __hip_atomic_store(bar_fail(bar), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(20);
+        }
+        if (__hip_atomic_load(bar_fail(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) good = 0;
+        // acquire the other blocks' results (invalidate this CU's L1 and
+        // the stale L2 lines)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// One Dslash stage over the virtual blocks of all instances; stage index k.
+template <typename SS, typename LS, typename T, int R, int DAG, int OWN, int EPI>
+__device__ __forceinline__ void persist_stage(const PersistArgs<T> &a, int k)
+{
+    const int total = a.start[a.n];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        int i = 0;
+        while (i + 1 < a.n && vb >= a.start[i + 1]) i++;
+        const DParams<T> &p = a.st[k][i];
+        const int local = vb - a.start[i];
+        const int nreal = p.nblk * p.ngroups;
+        if (local >= nreal) continue;
+        dslash_block<SS, LS, T, R, DAG, OWN, EPI>(p, local, nreal);
+        // the block reduction of the next virtual block reuses the LDS
+        if constexpr (EPI != EPI_STORE) __syncthreads();
+    }
+}
+
+// The CG scalars of one right-hand side per block: alpha from the partial
+// sums of stage 2 (BETA = false) or beta and the flags from those of stage 4.
+template <typename T, bool BETA>
+__device__ __forceinline__ void persist_scalars(const PersistArgs<T> &a)
+{
+    const int total = a.fstart[a.n];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        int i = 0;
+        while (i + 1 < a.n && w >= a.fstart[i + 1]) i++;
+        const int r = w - a.fstart[i];
+        if constexpr (BETA) {
+            const DParams<T> &p = a.st[3][i];
+            cgdev::finish_beta(a.sc[i], p.part, p.nblk, p.nrhs, a.delta[i], r);
+        } else {
+            const DParams<T> &p = a.st[1][i];
+            cgdev::finish_alpha(a.sc[i], p.part, p.nblk, r);
+        }
+    }
+}
+
+template <typename SS, typename T>
+__device__ __forceinline__ void persist_update(const PersistArgs<T> &a)
+{
+    const int total = a.ustart[a.n];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        int i = 0;
+        while (i + 1 < a.n && w >= a.ustart[i + 1]) i++;
+        const int local = w - a.ustart[i];
+        const int r = local / a.uchunks[i], ch = local - r * a.uchunks[i];
+        const DParams<T> &p0 = a.st[0][i];  // stage 1 reads p
+        const DParams<T> &p3 = a.st[3][i];  // stage 4 updates r
+        const size_t n = (size_t)12 * p0.g.hs;
+        const size_t e0 = (size_t)ch * kUpdChunk, e1 = e0 + kUpdChunk < n ? e0 + kUpdChunk : n;
+        cgdev::update_px((SS *)p0.in, (const SS *)p3.r, (float2 *)a.x[i], n, a.sc[i], r, e0 + threadIdx.x, e1,
+                         (size_t)kBlock);
+    }
+}
+
+template <typename SS, typename LS, typename T, int R>
+__global__ __launch_bounds__(kBlock, (waves_for<T, R>())) void k_batch_persist(const PersistArgs<T> *__restrict__ pa,
+                                                                             int iters,
+                                                                             unsigned long long spin_limit)
+{
+    const PersistArgs<T> &a = *pa;
+    for (int it = 0; it < iters; it++) {
+        persist_stage<SS, LS, T, R, 0, 0, EPI_STORE>(a, 0);  // t = R_oo^-1 H_oe p
+        if (!grid_sync(a.bar, spin_limit)) return;
+        persist_stage<SS, LS, T, R, 0, 1, EPI_NORM>(a, 1);   // q = R_ee p - H_eo t, |q|^2 partials
+        if (!grid_sync(a.bar, spin_limit)) return;
+        persist_stage<SS, LS, T, R, 1, 0, EPI_STORE>(a, 2);  // t = R_oo^-1 H_oe^dag q
+        persist_scalars<T, false>(a);                       // alpha
+        if (!grid_sync(a.bar, spin_limit)) return;
+        persist_stage<SS, LS, T, R, 0, 1, EPI_CG>(a, 3);     // r -= alpha Ahat^dag q, partials
+        if (!grid_sync(a.bar, spin_limit)) return;
+        persist_scalars<T, true>(a);                        // beta, flags
+        if (!grid_sync(a.bar, spin_limit)) return;
+        persist_update<SS, T>(a);                           // x += alpha p, p = r + beta p
+        if (it + 1 < iters && !grid_sync(a.bar, spin_limit)) return;
+    }
 }
 
 template <typename T>
@@ -1097,6 +1276,69 @@ void multi_dispatch(int prec, bool recon12, bool recon8, int R, F &&f)
     }
 }
 
+template <typename SS, typename LS, typename T, int R>
+void persist_fill(PersistBatch &pb, const std::vector<PersistInst> &v, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 8) {
+        throw TmError{TM_ERR_UNSUPPORTED, "the persistent batch kernel takes FP32-arithmetic solvers"};
+    } else {
+    PersistArgs<T> a{};
+    a.n = (int)v.size();
+    for (int k = 0; k < a.n; k++) {
+        for (int st = 0; st < 4; st++) {
+            TM_REQUIRE(v[k].st[st].nrhs % R == 0, "RHS tile must divide every instance's nrhs");
+            a.st[st][k] = fill_params<SS, LS, T, R>(v[k].c, v[k].st[st]);
+        }
+        const int nb = a.st[0][k].nblk * a.st[0][k].ngroups;
+        a.start[k + 1] = a.start[k] + (nb + 7) / 8 * 8;
+        const size_t n = (size_t)12 * v[k].c->geo.hs;
+        a.uchunks[k] = (int)((n + kUpdChunk - 1) / kUpdChunk);
+        a.ustart[k + 1] = a.ustart[k] + a.uchunks[k] * v[k].st[0].nrhs;
+        a.fstart[k + 1] = a.fstart[k] + v[k].st[0].nrhs;
+        a.x[k] = v[k].x;
+        a.sc[k] = v[k].sc;
+        a.delta[k] = v[k].delta;
+    }
+    pb.work = std::max(a.start[a.n], a.ustart[a.n]);
+    pb.sync_bytes = sizeof(unsigned) * kBarWords;
+    pb.bar = ws_get(v[0].c, "persist_sync", pb.sync_bytes);
+    a.bar = (unsigned *)pb.bar;
+    pb.args_bytes = sizeof(a);
+    // the table is rewritten only when no launch that reads it is in flight
+    TM_HIP(hipStreamSynchronize(s));
+    pb.dev_args = ws_get(v[0].c, "persist_args", sizeof(a));
+    TM_HIP(hipMemcpy(pb.dev_args, &a, sizeof(a), hipMemcpyHostToDevice));
+    // co-resident blocks of this instantiation: the grid of the cooperative launch
+    int per_cu = 0, ncu = 0;
+    TM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persist<SS, LS, T, R>, kBlock, 0));
+    TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, v[0].c->device));
+    if (pb.blocks_per_cu > 0) per_cu = std::min(per_cu, pb.blocks_per_cu);
+    const int cap = per_cu * ncu / 8 * 8;
+    TM_REQUIRE(cap >= 8, "the persistent batch kernel does not fit the device");
+    pb.grid = std::min(cap, (pb.work + 7) / 8 * 8);
+    }
+}
+
+template <typename SS, typename LS, typename T, int R>
+bool persist_go(const PersistBatch &pb, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 8) {
+        return false;
+    } else {
+    TM_REQUIRE(pb.args_bytes == sizeof(PersistArgs<T>), "persistent batch arguments of another precision");
+    const PersistArgs<T> *pa = (const PersistArgs<T> *)pb.dev_args;
+    int iters = pb.iters;
+    unsigned long long spin = pb.spin_limit;
+    void *kargs[] = {&pa, &iters, &spin};
+    if (hipLaunchCooperativeKernel((const void *)k_batch_persist<SS, LS, T, R>, dim3(pb.grid), dim3(kBlock), kargs,
+                                   0, s) != hipSuccess) {
+        (void)hipGetLastError();  // refused (e.g. the grid cannot be co-resident): nothing was launched
+        return false;
+    }
+    return true;
+    }
+}
+
 }  // namespace
 
 void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const std::vector<DslashCall> &dcs, int R,
@@ -1149,6 +1391,66 @@ void multi_dslash_launch(const MultiDslash &m, hipStream_t s)
 {
     multi_dispatch(m.prec, m.recon12, m.recon8, m.R,
                    [&]<typename SS, typename LS, typename T, int RR>() { multi_go<SS, LS, T, RR>(m, s); });
+}
+
+bool persist_supported(int device)
+{
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return coop != 0;
+}
+
+void persist_prepare(PersistBatch &pb, const std::vector<PersistInst> &v, int R, hipStream_t s)
+{
+    TM_REQUIRE(!v.empty() && (int)v.size() <= kPersistInst, "persistent batch: 1 to 4 instances");
+    const int prec = v[0].st[0].spinor_prec;
+    TM_REQUIRE(prec != TM_F64, "the persistent batch kernel takes FP32-arithmetic solvers");
+    tm_ctx *c0 = v[0].c;
+    bool recon8 = false;
+    for (const auto &q : v) {
+        // the link copies the stage forms read (the same choice as the
+        // multi-instance launches of the same stages)
+        MultiDslash m;
+        std::vector<tm_ctx *> cs(1, q.c);
+        for (int st = 0; st < 4; st++) {
+            TM_REQUIRE(q.st[st].spinor_prec == prec, "batched solves share precision");
+            multi_dslash_prepare(m, cs, std::vector<DslashCall>(1, q.st[st]), R, s);
+        }
+        TM_REQUIRE(recon12_ok(q.c, prec) == recon12_ok(c0, prec), "batched instances must share the link format");
+        if (&q == &v[0]) recon8 = m.recon8;
+        TM_REQUIRE(m.recon8 == recon8, "batched instances must share the link format");
+    }
+    pb.prec = prec;
+    pb.R = R;
+    pb.recon12 = recon12_ok(c0, prec);
+    pb.recon8 = recon8;
+    multi_dispatch(pb.prec, pb.recon12, pb.recon8, R,
+                   [&]<typename SS, typename LS, typename T, int RR>() { persist_fill<SS, LS, T, RR>(pb, v, s); });
+}
+
+bool persist_launch(PersistBatch &pb, int iters, unsigned long long spin_limit, hipStream_t s)
+{
+    TM_REQUIRE(iters >= 1, "iters must be >= 1");
+    pb.iters = iters;
+    pb.spin_limit = spin_limit;
+    // the barrier state starts at zero (a launch that gave up may have left
+    // it set)
+    TM_HIP(hipMemsetAsync(pb.bar, 0, pb.sync_bytes, s));
+    bool ok = false;
+    multi_dispatch(pb.prec, pb.recon12, pb.recon8, pb.R,
+                   [&]<typename SS, typename LS, typename T, int RR>() { ok = persist_go<SS, LS, T, RR>(pb, s); });
+    return ok;
+}
+
+bool persist_failed(const PersistBatch &pb, hipStream_t s)
+{
+    unsigned fail = 0;
+    TM_HIP(hipMemcpyAsync(&fail, (const unsigned *)pb.bar + 17 * kBarLine, sizeof(fail), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    return fail != 0;
 }
 
 int dslash_site_blocks(tm_ctx *c) { return (c->geo.vh + kBlock - 1) / kBlock; }

@@ -442,6 +442,34 @@ void multi_dslash_prepare(MultiDslash &m, const std::vector<tm_ctx *> &cs, const
                           hipStream_t s);
 void multi_dslash_launch(const MultiDslash &m, hipStream_t s);
 
+// Persistent batch: `iters` CG iterations of up to kPersistInst instances in
+// one cooperative launch (grid barriers between the stages, bounded waits);
+// solvers with FP32 arithmetic (FP32, FP16 or BF16 storage) only.
+constexpr int kPersistInst = 4;
+struct PersistInst {
+    tm_ctx *c = nullptr;
+    DslashCall st[4];       // the four stage forms of one CG iteration
+    void *x = nullptr;      // solution accumulator of the update
+    CGScalars *sc = nullptr;
+    double delta = 0;       // reliable-update threshold (0: none)
+};
+struct PersistBatch {
+    void *dev_args = nullptr;          // launch parameters (device, owned by the first context)
+    size_t args_bytes = 0, sync_bytes = 0;
+    int grid = 0, work = 0, iters = 0;
+    int blocks_per_cu = 0;             // cap on resident blocks per CU (0: as many as fit)
+    int prec = 0, R = 1;
+    bool recon12 = false, recon8 = false;
+    void *bar = nullptr;               // barrier state (device)
+    unsigned long long spin_limit = 0;
+};
+bool persist_supported(int device);
+void persist_prepare(PersistBatch &pb, const std::vector<PersistInst> &v, int R, hipStream_t s);
+// false if the runtime refused the cooperative launch (nothing launched)
+bool persist_launch(PersistBatch &pb, int iters, unsigned long long spin_limit, hipStream_t s);
+// reads the barrier state (synchronises the stream): true if a wait gave up
+bool persist_failed(const PersistBatch &pb, hipStream_t s);
+
 // ---------------------------------------------------------------- blas
 
 // All vectors: half layout [nrhs][12][hs] of the given precision.

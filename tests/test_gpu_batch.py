@@ -1,10 +1,17 @@
-"""Uneven batches (three lattices in one graph-captured CG iteration stream).
+"""Uneven batches (three lattices; each group of CG iterations one launch of
+the persistent batch kernel or a graph of multi-instance launches, timed
+once each and the faster kept; beyond four lattices, and for FP64, the
+graph).
 
 Each instance of a batch must reproduce its own single-lattice solve bit for
 bit (same arithmetic, same reliable-update cadence); residuals are also
 recomputed by the FP64 oracle, and the per-instance loops are checked
-against the oracle and against the single-lattice loop driver.
+against the oracle and against the single-lattice loop driver.  The
+persistent kernel's barrier waits are bounded: with a spin limit of zero
+the launch gives up, the call reports it, and the device stays usable.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -161,3 +168,78 @@ def test_batch_argument_checks(inst):
         batch.loops(bad)
     assert ei.value.status == P.TM_ERR_ARG
     batch.close()
+
+
+def batch_solve_env(inst, names, params, env, seed0):
+    """Batch solve of the listed instances with environment switches set
+    while the batch is created; returns (sources, solutions, stats)."""
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        batch = P.Batch([inst[n]["ctx"] for n in names])
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    try:
+        bs = [cuda(sources(inst[n], inst[n]["nrhs"], seed0 + k)) for k, n in enumerate(names)]
+        xs = [torch.zeros_like(b) for b in bs]
+        st, stats = batch.solve(xs, bs, [inst[n]["nrhs"] for n in names], params)
+    finally:
+        batch.close()
+    return bs, xs, stats
+
+
+@pytest.fixture(scope="module")
+def five():
+    """Five lattices: the three c4 ones and two more small ones."""
+    out = {}
+    specs = [(n, S.CONFIGS[n]["L"], S.CONFIGS[n]["kappa"], S.CONFIGS[n]["two_kappa_mu"],
+              S.CONFIGS[n]["eps_links"], S.CONFIGS[n]["seed"], NRHS[n] // 4) for n in C4]
+    specs += [("e1", (4, 4, 4, 8), 0.124, 0.01, 0.3, 1101, 6), ("e2", (6, 4, 4, 6), 0.124, 0.005, 0.2, 1102, 3)]
+    for name, L, kappa, eps, el, seed, n in specs:
+        U = S.gauge_links(L, el, seed)
+        ctx = P.Context(L, kappa, eps)
+        ctx.set_gauge(cuda(U))
+        out[name] = dict(name=name, cfg=dict(L=L), ctx=ctx, nrhs=n)
+    yield out
+    for d in out.values():
+        d["ctx"].close()
+
+
+def test_graph_path_beyond_four_lattices_matches_persistent(five):
+    """Five lattices take the graph of multi-instance launches; on three, the
+    persistent kernel (forced), the graph (forced) and the timed choice give
+    the same solutions: all bit-identical to the single-lattice solves."""
+    params = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+    names5 = ["c4a", "c4b", "c4c", "e1", "e2"]
+    bs, xs, _ = batch_solve_env(five, names5, params, {}, 700)
+    _, xs_p, _ = batch_solve_env(five, names5[:3], params, {"TM_BATCH_PERSIST": "1"}, 700)
+    _, xs_g, _ = batch_solve_env(five, names5[:3], params, {"TM_BATCH_PERSIST": "0"}, 700)
+    _, xs_t, _ = batch_solve_env(five, names5[:3], params, {}, 700)
+    for k, n in enumerate(names5):
+        x1 = torch.zeros_like(bs[k])
+        five[n]["ctx"].solve(x1, bs[k], five[n]["nrhs"], params)
+        assert torch.equal(xs[k], x1), n
+        if k < 3:
+            assert torch.equal(xs_p[k], x1) and torch.equal(xs_g[k], x1) and torch.equal(xs_t[k], x1), n
+
+
+def test_persistent_barrier_wait_is_bounded(five):
+    """A spin limit of zero makes the persistent kernel's barrier waits give
+    up at once: every block leaves the kernel, the call fails with
+    TM_ERR_HIP and says why, and the next batch on the same contexts solves
+    normally."""
+    params = P.solve_params(tol=1e-9, solver=P.TM_CG_MIXED, inner_prec=P.TM_F16)
+    names = ["c4a", "c4b", "c4c"]
+    with pytest.raises(P.TMError) as ei:
+        batch_solve_env(five, names, params, {"TM_BATCH_SPIN_LIMIT": "0", "TM_BATCH_PERSIST": "1"}, 710)
+    assert ei.value.status == P.TM_ERR_HIP and "barrier" in str(ei.value)
+    bs, xs, stats = batch_solve_env(five, names, params, {}, 710)
+    for k, n in enumerate(names):
+        x1 = torch.zeros_like(bs[k])
+        five[n]["ctx"].solve(x1, bs[k], five[n]["nrhs"], params)
+        assert torch.equal(xs[k], x1), n
+        assert all(s.converged == 1 for s in stats[k])
