@@ -12,26 +12,42 @@ __device__ __forceinline__ long lex_site(const Geo &g, int x, int y, int z, int 
 
 // ---------------------------------------------------------------- pack / unpack
 
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_pack(S *even, S *odd, const double2 *full, Geo g, long V,
-                                                 const double *scale)
+// The canonical field stores the 12 complex of a site contiguously, the half
+// layout one plane per component: a block stages its 256 sites' 3072
+// complex in LDS (row stride 13 to spread the banks), so that the global
+// reads and the plane writes are both coalesced.
+constexpr int kPackRow = 13;
+
+__device__ __forceinline__ int site_parity(const Geo &g, long s)
 {
-    const long s = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= V) return;
-    const int r = blockIdx.y;
     int q = (int)(s / g.L[0]);
     int x = (int)(s - (long)q * g.L[0]);
     int y = q % g.L[1];
     int q2 = q / g.L[1];
     int z = q2 % g.L[2];
     int t = q2 / g.L[2];
-    const int p = (x + y + z + t) & 1;
+    return (x + y + z + t) & 1;
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_pack(S *even, S *odd, const double2 *full, Geo g, long V,
+                                                 const double *scale)
+{
+    __shared__ double2 buf[kBlock * kPackRow];
+    const long s0 = (long)blockIdx.x * kBlock;
+    const int r = blockIdx.y;
+    const int ns = (int)(V - s0 < kBlock ? V - s0 : kBlock);  // sites of this block
+    const double2 *src = full + ((size_t)r * V + s0) * 12;
+    for (int e = threadIdx.x; e < 12 * ns; e += kBlock) buf[(e / 12) * kPackRow + e % 12] = src[e];
+    __syncthreads();
+    if ((int)threadIdx.x >= ns) return;
+    const long s = s0 + threadIdx.x;
     const int i = (int)(s >> 1);
-    S *dst = p ? odd : even;
+    S *dst = site_parity(g, s) ? odd : even;
     const double sc = scale ? scale[r] : 1.0;
 #pragma unroll
     for (int k = 0; k < 12; k++) {
-        double2 v = full[((size_t)r * V + s) * 12 + k];
+        const double2 v = buf[threadIdx.x * kPackRow + k];
         stT<double>(dst, (size_t)(r * 12 + k) * g.hs + i, cx<double>{sc * v.x, sc * v.y});
     }
 }
@@ -39,23 +55,23 @@ __global__ __launch_bounds__(kBlock) void k_pack(S *even, S *odd, const double2 
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_unpack(double2 *full, const S *even, const S *odd, Geo g, long V)
 {
-    const long s = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= V) return;
+    __shared__ double2 buf[kBlock * kPackRow];
+    const long s0 = (long)blockIdx.x * kBlock;
     const int r = blockIdx.y;
-    int q = (int)(s / g.L[0]);
-    int x = (int)(s - (long)q * g.L[0]);
-    int y = q % g.L[1];
-    int q2 = q / g.L[1];
-    int z = q2 % g.L[2];
-    int t = q2 / g.L[2];
-    const int p = (x + y + z + t) & 1;
-    const int i = (int)(s >> 1);
-    const S *src = p ? odd : even;
+    const int ns = (int)(V - s0 < kBlock ? V - s0 : kBlock);
+    if ((int)threadIdx.x < ns) {
+        const long s = s0 + threadIdx.x;
+        const int i = (int)(s >> 1);
+        const S *src = site_parity(g, s) ? odd : even;
 #pragma unroll
-    for (int k = 0; k < 12; k++) {
-        cx<double> v = ldT<double>(src, (size_t)(r * 12 + k) * g.hs + i);
-        full[((size_t)r * V + s) * 12 + k] = make_double2(v.r, v.i);
+        for (int k = 0; k < 12; k++) {
+            const cx<double> v = ldT<double>(src, (size_t)(r * 12 + k) * g.hs + i);
+            buf[threadIdx.x * kPackRow + k] = make_double2(v.r, v.i);
+        }
     }
+    __syncthreads();
+    double2 *dst = full + ((size_t)r * V + s0) * 12;
+    for (int e = threadIdx.x; e < 12 * ns; e += kBlock) dst[e] = buf[(e / 12) * kPackRow + e % 12];
 }
 
 // ---------------------------------------------------------------- gauge
