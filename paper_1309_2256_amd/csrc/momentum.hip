@@ -59,13 +59,21 @@ __global__ __launch_bounds__(kBlock) void k_outer_sites(const double2 *ve, const
     for (int e = 0; e < 16; e++) Cf[(size_t)e * V + s] = make_double2(C[e].r, C[e].i);
 }
 
-// D_mu(x) for mu = blockIdx.y; Cf[mu][e][s] with e = 4 b + a
+// D_mu(x); Cf[mu][e][s] with e = 4 b + a.
+// Block order: block b runs on XCD b % 8 (round-robin dispatch).  XCD k owns
+// the contiguous range of site blocks [k per, (k + 1) per) and takes them in
+// order, the four directions of one site block as four consecutive blocks, so
+// that the directions read the site's 12-RHS fields (4.6 KB per site) while
+// they are in that XCD's L2 instead of streaming them from memory once per
+// direction.  Blocks past the last site block exit.
 __global__ __launch_bounds__(kBlock) void k_outer_deriv_sites(const double2 *ve, const double2 *vo, const double2 *we,
                                                               const double2 *wo, const double2 *l0, const double2 *l1,
-                                                              Geo g, long V, int nrhs, double2 *Cf)
+                                                              Geo g, long V, int nrhs, int per, double2 *Cf)
 {
-    const long s = (long)blockIdx.x * kBlock + threadIdx.x;
-    const int mu = blockIdx.y;
+    const int m = (int)(blockIdx.x >> 3);
+    const int mu = m & 3;
+    const long sblk = (long)(blockIdx.x & 7) * per + (m >> 2);
+    const long s = sblk * kBlock + threadIdx.x;
     if (s >= V) return;
     int c4[4];
     c4[0] = (int)(s % g.L[0]);
@@ -301,9 +309,12 @@ void outer_deriv_host(tm_ctx *c, const void *ve, const void *vo, const void *we,
     TM_REQUIRE(c->have_gauge, "no gauge field set");
     const long V = c->V;
     double2 *Cf = (double2 *)ws_get(c, "mom_cfd", sizeof(double2) * 64 * V);
-    hipLaunchKernelGGL(k_outer_deriv_sites, dim3((unsigned)((V + kBlock - 1) / kBlock), 4), dim3(kBlock), 0, s,
-                       (const double2 *)ve, (const double2 *)vo, (const double2 *)we, (const double2 *)wo,
-                       (const double2 *)c->links64[0], (const double2 *)c->links64[1], c->geo, V, nrhs, Cf);
+    const long nsb = (V + kBlock - 1) / kBlock;
+    const long per = (nsb + 7) / 8;  // site blocks per XCD
+    TM_REQUIRE(32 * per <= 0x7fffffffL, "lattice too large for the derivative contraction grid");
+    hipLaunchKernelGGL(k_outer_deriv_sites, dim3((unsigned)(32 * per)), dim3(kBlock), 0, s, (const double2 *)ve,
+                       (const double2 *)vo, (const double2 *)we, (const double2 *)wo, (const double2 *)c->links64[0],
+                       (const double2 *)c->links64[1], c->geo, V, nrhs, (int)per, Cf);
     TM_HIP(hipGetLastError());
     project_components(c, Cf, 4, mom, out, s);
 }
