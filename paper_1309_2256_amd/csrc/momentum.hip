@@ -184,6 +184,41 @@ __global__ __launch_bounds__(kBlock) void k_dft_dim(const double2 *in, double2 *
     out[idx] = make_double2(acc.r, acc.i);
 }
 
+// The first direction (inner = 1: the transformed index is the fastest):
+// one thread per row in[o][0..n) forms all W outputs out[o][j], up to kDftJ
+// at a time, so the row is read once (8 consecutive complex per unrolled
+// batch, one 128-byte line per lane) and the phases, the same for every lane,
+// come through scalar loads.  Every output is the same fixed-order sum over m
+// as in k_dft_dim.
+constexpr int kDftJ = 8;
+
+__global__ __launch_bounds__(kBlock) void k_dft_rows(const double2 *in, double2 *out, const double2 *ph, long outer,
+                                                     int n, int W)
+{
+    const long o = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (o >= outer) return;
+    const double2 *row = in + o * n;
+    double2 *dst = out + o * W;
+    for (int j0 = 0; j0 < W; j0 += kDftJ) {
+        cx<double> acc[kDftJ];
+#pragma unroll
+        for (int jj = 0; jj < kDftJ; jj++) acc[jj] = {0, 0};
+#pragma unroll 8
+        for (int m = 0; m < n; m++) {
+            const double2 b = row[m];
+#pragma unroll
+            for (int jj = 0; jj < kDftJ; jj++)
+                if (j0 + jj < W) {
+                    const double2 a = ph[(long)(j0 + jj) * n + m];
+                    cmac(acc[jj], cx<double>{a.x, a.y}, cx<double>{b.x, b.y});
+                }
+        }
+#pragma unroll
+        for (int jj = 0; jj < kDftJ; jj++)
+            if (j0 + jj < W) dst[j0 + jj] = make_double2(acc[jj].r, acc[jj].i);
+    }
+}
+
 // out[m][blk][t][e] = T[16 blk + e][t][nz + N][ny + N][nx + N] for the listed momenta
 __global__ void k_pick_momenta(const double2 *T, const int *mom, int n_mom, int nblk, int Lt, int W, int N,
                                double2 *out)
@@ -257,9 +292,8 @@ void project_components(tm_ctx *c, const double2 *Cf, int nblk, const std::vecto
     // x: [ncomp Lt Lz Ly][Lx][1] -> [ncomp Lt Lz Ly][W][1]
     const long o1 = ncomp * Lt * Lz * Ly;
     double2 *T1 = (double2 *)ws_get(c, "mom_t1", sizeof(double2) * o1 * W);
-    const long n1 = o1 * W;
-    hipLaunchKernelGGL(k_dft_dim, dim3((unsigned)((n1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, Cf, T1,
-                       (const double2 *)dph, o1, Lx, W, 1L);
+    hipLaunchKernelGGL(k_dft_rows, dim3((unsigned)((o1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, Cf, T1,
+                       (const double2 *)dph, o1, Lx, W);
     // y: [ncomp Lt Lz][Ly][W] -> [ncomp Lt Lz][W][W]
     const long o2 = ncomp * Lt * Lz;
     double2 *T2 = (double2 *)ws_get(c, "mom_t2", sizeof(double2) * o2 * W * W);
