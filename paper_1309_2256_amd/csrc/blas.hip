@@ -57,6 +57,17 @@ __global__ __launch_bounds__(kBlock) void k_axpby(S *y, const S *x, size_t n, do
     }
 }
 
+// out = a x + b y with a separate output (the same arithmetic as k_axpby)
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_axpby_to(S *out, const S *x, const S *y, size_t n, double a, double b)
+{
+    using T = typename StoreTraits<S>::real;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+        cx<T> xv = ldT<T>(x, e), yv = ldT<T>(y, e);
+        stT<T>(out, e, (T)a * xv + (T)b * yv);
+    }
+}
+
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_zero(S *y, size_t n)
 {
@@ -186,6 +197,19 @@ void launch_axpby_host(tm_ctx *c, void *y, const void *x, int prec, int nrhs, do
     dispatch_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(k_axpby<S>, dim3(grid_for(n)), dim3(kBlock), 0, s, (S *)y, (const S *)x, n, a, b);
+    });
+    TM_HIP(hipGetLastError());
+}
+
+void launch_axpby_to_host(tm_ctx *c, void *out, const void *x, const void *y, int prec, int nrhs, double a,
+                          double b, hipStream_t s)
+{
+    size_t n = half_elems(c) * nrhs;
+    account(c, 3.0 * n * prec_bytes(prec), 6.0 * n);
+    dispatch_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_axpby_to<S>, dim3(grid_for(n)), dim3(kBlock), 0, s, (S *)out, (const S *)x,
+                           (const S *)y, n, a, b);
     });
     TM_HIP(hipGetLastError());
 }

@@ -443,8 +443,7 @@ void Solver::check(hipStream_t s)
             // sides still above tol continue from it, as after a reliable
             // update
             op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s, true);
-            copy_field(rho64, bh, field_bytes(c, TM_F64, nrhs), s);
-            launch_axpby_host(c, rho64, q64, TM_F64, nrhs, -1.0, 1.0, s);
+            launch_axpby_to_host(c, rho64, q64, bh, TM_F64, nrhs, -1.0, 1.0, s);  // rho = bh - Ahat x
             std::vector<double> nrho = norms_host(c, rho64, TM_F64, nrhs, s);
             bool again = false;
             for (int r = 0; r < nrhs; r++) again |= nrho[r] > p.tol * p.tol * bn2[r];
@@ -461,8 +460,7 @@ void Solver::check(hipStream_t s)
     // reliable update: FP64 true residual of the accumulated solution
     accumulate(s);
     op_schur(c, q64, xe, t64, nrhs, TM_F64, epsp, s, true);
-    copy_field(rho64, bh, field_bytes(c, TM_F64, nrhs), s);
-    launch_axpby_host(c, rho64, q64, TM_F64, nrhs, -1.0, 1.0, s);
+    launch_axpby_to_host(c, rho64, q64, bh, TM_F64, nrhs, -1.0, 1.0, s);  // rho = bh - Ahat x
     for (int r = 0; r < nrhs; r++)
         if (hsc[r].active) n_rel[r]++;
     restart(false, s);

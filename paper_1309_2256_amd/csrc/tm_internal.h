@@ -481,6 +481,9 @@ void launch_copy_convert(tm_ctx *c, void *out, int out_prec, const void *in, int
 // y = a*x + b*y with host scalars (same prec)
 void launch_axpby_host(tm_ctx *c, void *y, const void *x, int prec, int nrhs, double a, double b,
                        hipStream_t s);
+// out = a x + b y (x, y, out distinct or out == y)
+void launch_axpby_to_host(tm_ctx *c, void *out, const void *x, const void *y, int prec, int nrhs, double a,
+                          double b, hipStream_t s);
 void launch_zero(tm_ctx *c, void *y, int prec, int nrhs, hipStream_t s);
 // y[r] += a_dev[r] * x[r]
 void launch_axpy_dev(tm_ctx *c, void *y, int yprec, const void *x, int xprec, int nrhs, const double *a_dev,
