@@ -37,8 +37,10 @@ def make_ctx(L, kappa, eps, seed, eps_links=0.3):
 
 
 @pytest.mark.parametrize("L,p2max", [((4, 4, 4, 8), 2), ((6, 4, 8, 4), 1), ((6, 6, 6, 4), 5),
-                                     ((8, 6, 10, 2), 4)])
+                                     ((8, 6, 10, 2), 4), ((10, 10, 10, 2), 16)])
 def test_contract_momentum_matches_oracle(L, p2max):
+    # |n|^2 <= 16 needs 2N + 1 = 9 components per direction: more than the
+    # x pass forms per chunk (8), so its second chunk is covered
     eps = 0.0123
     ctx, _ = make_ctx(L, 0.124, eps, 61)
     nrhs = 3
