@@ -100,12 +100,16 @@ void launch_iteration(tm_batch *b, std::vector<Solver> &S, const std::vector<int
         for (int i : set) S[i].iteration(s);
         return;
     }
+    std::vector<CgTail> t;
+    for (int i : set)
+        t.push_back(CgTail{S[i].c, S[i].w.dsc, S[i].w.partq, S[i].w.partb, S[i].nsb, S[i].nrhs, S[i].delta, S[i].w.p,
+                           S[i].w.r, S[i].w.x});
     multi_dslash_launch(b->md[0], s);
     multi_dslash_launch(b->md[1], s);
-    for (int i : set) cg_finish_alpha(S[i].c, S[i].w.dsc, S[i].w.partq, S[i].nsb, S[i].nrhs, s);
+    cg_finish_alpha_multi(t, s);
     multi_dslash_launch(b->md[2], s);
     multi_dslash_launch(b->md[3], s);
-    for (int i : set) S[i].iteration_tail(s);
+    cg_tail_multi(t, S[set[0]].w.prec, S[set[0]].w.xprec, s);
 }
 
 // right-hand sides per Dslash thread for the batch: the fastest (timed on the

@@ -133,6 +133,57 @@ __global__ __launch_bounds__(kBlock) void k_update_px(S *p, const S *rv, XS *x, 
                      (size_t)gridDim.x * kBlock);
 }
 
+// Several lattices per launch (a batch iteration).  Scalar kernels: block b
+// is right-hand side b - rstart[i] of lattice i.  Update: lattice i owns
+// blocks [ustart[i], ustart[i+1]) laid out as its single launch's
+// (gx[i] x nrhs) grid, so every element sees the same thread-stride loop.
+constexpr int kTailInst = 8;
+template <typename S, typename XS>
+struct TailArgs {
+    CGScalars *sc[kTailInst];
+    const double *part[kTailInst];
+    S *p[kTailInst];
+    const S *r[kTailInst];
+    XS *x[kTailInst];
+    size_t n[kTailInst];
+    double delta[kTailInst];
+    int nblk[kTailInst], nrhs[kTailInst], gx[kTailInst];
+    int rstart[kTailInst + 1], ustart[kTailInst + 1];
+    int ninst;
+};
+static_assert(sizeof(TailArgs<double2, double2>) <= 4096, "kernel arguments exceed 4 KiB");
+
+__device__ __forceinline__ int tail_inst(const int *start, int n, int b)
+{
+    int i = 0;
+    while (i + 1 < n && b >= start[i + 1]) i++;
+    return i;
+}
+
+template <typename S, typename XS>
+__global__ __launch_bounds__(kBlock) void k_finish_alpha_multi(const TailArgs<S, XS> a)
+{
+    const int i = tail_inst(a.rstart, a.ninst, blockIdx.x);
+    cgdev::finish_alpha(a.sc[i], a.part[i], a.nblk[i], blockIdx.x - a.rstart[i]);
+}
+
+template <typename S, typename XS>
+__global__ __launch_bounds__(kBlock) void k_finish_beta_multi(const TailArgs<S, XS> a)
+{
+    const int i = tail_inst(a.rstart, a.ninst, blockIdx.x);
+    cgdev::finish_beta(a.sc[i], a.part[i], a.nblk[i], a.nrhs[i], a.delta[i], blockIdx.x - a.rstart[i]);
+}
+
+template <typename S, typename XS>
+__global__ __launch_bounds__(kBlock) void k_update_px_multi(const TailArgs<S, XS> a)
+{
+    const int i = tail_inst(a.ustart, a.ninst, blockIdx.x);
+    const int local = blockIdx.x - a.ustart[i], gx = a.gx[i];
+    const int r = local / gx, bx = local - r * gx;
+    cgdev::update_px(a.p[i], a.r[i], a.x[i], a.n[i], a.sc[i], r, (size_t)bx * kBlock + threadIdx.x, a.n[i],
+                     (size_t)gx * kBlock);
+}
+
 // complex elements of one right-hand side of a half field, pads included
 size_t half_elems(tm_ctx *c) { return (size_t)12 * c->geo.hs; }
 
@@ -212,6 +263,75 @@ void launch_axpby_to_host(tm_ctx *c, void *out, const void *x, const void *y, in
                            (const S *)y, n, a, b);
     });
     TM_HIP(hipGetLastError());
+}
+
+template <typename S, typename XS>
+static TailArgs<S, XS> tail_args(const std::vector<CgTail> &t, size_t i0, size_t i1, bool beta)
+{
+    TailArgs<S, XS> a{};
+    a.ninst = (int)(i1 - i0);
+    a.rstart[0] = a.ustart[0] = 0;
+    for (size_t k = i0; k < i1; k++) {
+        const int j = (int)(k - i0);
+        const CgTail &q = t[k];
+        a.sc[j] = q.sc;
+        a.part[j] = beta ? q.partb : q.partq;
+        a.p[j] = (S *)q.p;
+        a.r[j] = (const S *)q.r;
+        a.x[j] = (XS *)q.x;
+        a.n[j] = half_elems(q.c);
+        a.delta[j] = q.delta;
+        a.nblk[j] = q.nblk;
+        a.nrhs[j] = q.nrhs;
+        a.gx[j] = grid_for(a.n[j]);
+        a.rstart[j + 1] = a.rstart[j] + q.nrhs;
+        a.ustart[j + 1] = a.ustart[j] + a.gx[j] * q.nrhs;
+    }
+    return a;
+}
+
+template <typename F>
+static void dispatch_tail(int prec, int xprec, F &&f)
+{
+    if (prec == TM_F64) {
+        TM_REQUIRE(xprec == TM_F64, "FP64 CG needs an FP64 solution vector");
+        f((double2 *)nullptr, (double2 *)nullptr);
+        return;
+    }
+    TM_REQUIRE(xprec == TM_F32, "low-precision CG accumulates in FP32");
+    dispatch_prec(prec, [&](auto *tag) { f(tag, (float2 *)nullptr); });
+}
+
+void cg_finish_alpha_multi(const std::vector<CgTail> &t, hipStream_t s)
+{
+    for (size_t i0 = 0; i0 < t.size(); i0 += kTailInst) {
+        const size_t i1 = std::min(t.size(), i0 + kTailInst);
+        const TailArgs<double2, double2> a = tail_args<double2, double2>(t, i0, i1, false);
+        hipLaunchKernelGGL((k_finish_alpha_multi<double2, double2>), dim3(a.rstart[a.ninst]), dim3(kBlock), 0, s,
+                           a);
+        TM_HIP(hipGetLastError());
+    }
+}
+
+void cg_tail_multi(const std::vector<CgTail> &t, int prec, int xprec, hipStream_t s)
+{
+    for (size_t i0 = 0; i0 < t.size(); i0 += kTailInst) {
+        const size_t i1 = std::min(t.size(), i0 + kTailInst);
+        dispatch_tail(prec, xprec, [&](auto *ts, auto *tx) {
+            using S = std::remove_pointer_t<decltype(ts)>;
+            using XS = std::remove_pointer_t<decltype(tx)>;
+            const TailArgs<S, XS> a = tail_args<S, XS>(t, i0, i1, true);
+            hipLaunchKernelGGL((k_finish_beta_multi<S, XS>), dim3(a.rstart[a.ninst]), dim3(kBlock), 0, s, a);
+            TM_HIP(hipGetLastError());
+            hipLaunchKernelGGL((k_update_px_multi<S, XS>), dim3(a.ustart[a.ninst]), dim3(kBlock), 0, s, a);
+            TM_HIP(hipGetLastError());
+        });
+        for (size_t k = i0; k < i1; k++) {
+            const size_t n = half_elems(t[k].c);
+            account(t[k].c, (double)n * t[k].nrhs * (3 * prec_bytes(prec) + 2 * prec_bytes(xprec)),
+                    8.0 * n * t[k].nrhs);
+        }
+    }
 }
 
 // partial-sum blocks of the vector norms (a few per CU, at most kMaxPart)

@@ -513,6 +513,25 @@ void cg_finish_beta(tm_ctx *c, CGScalars *sc, const double *part, int nblk, int 
 void cg_update_px(tm_ctx *c, void *p, const void *r, void *x, int prec, int xprec, int nrhs, const CGScalars *sc,
                   hipStream_t s);
 
+// The same scalar and vector steps for several lattices in one launch each
+// (a batch's iteration): per lattice its context, CG scalars, partial sums
+// and fields; all share prec and xprec.  Bit-identical to the per-lattice
+// launches (the same device code per right-hand side and element).
+struct CgTail {
+    tm_ctx *c;
+    CGScalars *sc;
+    const double *partq;  // |q|^2 partials (alpha)
+    const double *partb;  // |r|^2 (and |rho|^2) partials (beta)
+    int nblk;             // partial-sum blocks
+    int nrhs;
+    double delta;
+    void *p;
+    const void *r;
+    void *x;
+};
+void cg_finish_alpha_multi(const std::vector<CgTail> &t, hipStream_t s);
+void cg_tail_multi(const std::vector<CgTail> &t, int prec, int xprec, hipStream_t s);  // beta, then x and p
+
 // ---------------------------------------------------------------- misc kernels
 
 void launch_pack(tm_ctx *c, void *even, void *odd, const double *full, int nrhs, int prec,
