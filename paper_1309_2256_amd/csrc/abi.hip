@@ -48,6 +48,23 @@ void *host_stage(tm_ctx *c, size_t bytes)
     return c->host_pinned;
 }
 
+void *host_upload_slot(tm_ctx *c, int slot, size_t bytes, hipStream_t s)
+{
+    TM_REQUIRE(slot >= 0 && slot < kUpSlots, "bad upload slot");
+    const size_t per = (bytes + 255) / 256 * 256;
+    if (!c->host_up || c->host_up_bytes < per * kUpSlots) {
+        if (c->host_up) {
+            TM_HIP(hipStreamSynchronize(s));  // copies from the old slots have completed
+            TM_HIP(hipHostFree(c->host_up));
+        }
+        c->host_up = nullptr;
+        const size_t n = std::max<size_t>(per, 1024) * kUpSlots;
+        TM_HIP(hipHostMalloc(&c->host_up, n, hipHostMallocDefault));
+        c->host_up_bytes = n;
+    }
+    return (char *)c->host_up + (size_t)slot * (c->host_up_bytes / kUpSlots);
+}
+
 void ensure_links32(tm_ctx *c, hipStream_t s)
 {
     if (c->have_links32) return;
@@ -182,6 +199,7 @@ extern "C" void tm_destroy(tm_ctx *c)
     for (int p = 0; p < 2; p++)
         if (c->links64[p]) (void)hipFree(c->links64[p]);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    if (c->host_up) (void)hipHostFree(c->host_up);
     delete c;
 }
 

@@ -20,6 +20,15 @@ void upload(void *dev, const void *host, size_t bytes, hipStream_t s)
     TM_HIP(hipStreamSynchronize(s));
 }
 
+// upload without waiting, through pinned slot `slot` of the context (see
+// host_upload_slot: the slot is reused only after a stream synchronisation)
+static void upload_async(tm_ctx *c, int slot, void *dev, const void *host, size_t bytes, hipStream_t s)
+{
+    void *st = host_upload_slot(c, slot, bytes, s);
+    memcpy(st, host, bytes);
+    TM_HIP(hipMemcpyAsync(dev, st, bytes, hipMemcpyHostToDevice, s));
+}
+
 void download(tm_ctx *c, void *host, const void *dev, size_t bytes, hipStream_t s)
 {
     void *stage = host_stage(c, bytes);
@@ -324,20 +333,23 @@ void Solver::restart(bool first, hipStream_t s, bool reactivate)
         // unit RMS; r = Ahat^dag rho is formed at the iteration's precision
         // (the FP64 part of the update is the residual itself), then both
         // are rescaled to unit RMS of r and p follows the new scale
+        // the scale uploads go through pinned slots without waiting: slot 0
+        // follows the norms_host synchronisation after accumulate's copy,
+        // slots 1-3 are each used once between two synchronisations
         std::vector<double> srho(nrhs);
         for (int r = 0; r < nrhs; r++) srho[r] = unit_scale(nrho[r]);
-        upload(dscale, srho.data(), sizeof(double) * nrhs, s);
+        upload_async(c, 1, dscale, srho.data(), sizeof(double) * nrhs, s);
         launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
         op_schur_dag(c, w.r, w.rho, w.tmp, nrhs, lp, epsp, s);
         std::vector<double> nrl = norms_host(c, w.r, lp, nrhs, s);
         for (int r = 0; r < nrhs; r++) sig_new[r] = unit_scale(nrl[r] / (srho[r] * srho[r]));
         for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r] / srho[r];
-        upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+        upload_async(c, 2, dscale, hscale.data(), sizeof(double) * nrhs, s);
         launch_copy_convert(c, w.r, lp, w.r, lp, nrhs, dscale, s);
-        upload(dscale, sig_new.data(), sizeof(double) * nrhs, s);
+        upload_async(c, 3, dscale, sig_new.data(), sizeof(double) * nrhs, s);
         launch_copy_convert(c, w.rho, lp, rho64, TM_F64, nrhs, dscale, s);
         for (int r = 0; r < nrhs; r++) hscale[r] = sig_new[r] / sigma[r];
-        upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+        upload_async(c, 0, dscale, hscale.data(), sizeof(double) * nrhs, s);
         launch_copy_convert(c, w.p, lp, w.p, lp, nrhs, dscale, s);
     }
     launch_zero(c, w.x, TM_F32, nrhs, s);
@@ -369,7 +381,9 @@ void Solver::accumulate(hipStream_t s)
 {
     std::vector<double> hscale(nrhs);
     for (int r = 0; r < nrhs; r++) hscale[r] = 1.0 / sigma[r];
-    upload(dscale, hscale.data(), sizeof(double) * nrhs, s);
+    // slot 0; every caller synchronises (a norm download) before the next
+    // use of the slot
+    upload_async(c, 0, dscale, hscale.data(), sizeof(double) * nrhs, s);
     launch_axpy_dev(c, xe, TM_F64, w.x, TM_F32, nrhs, dscale, s);
 }
 

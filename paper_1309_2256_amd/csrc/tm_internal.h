@@ -315,6 +315,8 @@ struct tm_ctx {
     // pinned host staging for scalar read-back
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
+    void *host_up = nullptr;  // pinned slots of asynchronous uploads (host_upload_slot)
+    size_t host_up_bytes = 0;
     // learned preconditioner (ptc.hip): channel count (0 = no weights),
     // Adam step counter, training-pair store (capacity, count, precision)
     int ptc_nc = 0;
@@ -362,6 +364,11 @@ inline void account(tm_ctx *c, double bytes, double flops)
 
 void *ws_get(tm_ctx *c, const std::string &name, size_t bytes);
 void *host_stage(tm_ctx *c, size_t bytes);
+// Pinned staging slot `slot` (< kUpSlots) of `bytes` for an asynchronous
+// upload on stream s.  A slot's previous copy must have completed before it
+// is reused (the callers synchronise the stream in between).
+constexpr int kUpSlots = 4;
+void *host_upload_slot(tm_ctx *c, int slot, size_t bytes, hipStream_t s);
 void ensure_links32(tm_ctx *c, hipStream_t s);
 void ensure_links16(tm_ctx *c, hipStream_t s);
 void ensure_links12(tm_ctx *c, hipStream_t s);
