@@ -227,6 +227,34 @@ def test_graph_path_beyond_four_lattices_matches_persistent(five):
             assert torch.equal(xs_p[k], x1) and torch.equal(xs_g[k], x1) and torch.equal(xs_t[k], x1), n
 
 
+def test_ten_lattices_match_single_solves():
+    """Ten small lattices in one batch: the multi-lattice scalar and update
+    launches take at most eight lattices each, so an iteration issues two of
+    each; every solution equals its single-lattice solve bit for bit, in the
+    FP16 mixed and the plain FP64 solver."""
+    shapes = [(4, 4, 4, 8), (6, 4, 4, 6), (4, 4, 6, 4), (4, 6, 4, 4), (6, 6, 4, 4)]
+    inst = {}
+    try:
+        for k in range(10):
+            L = shapes[k % len(shapes)]
+            U = S.gauge_links(L, 0.2 + 0.02 * k, 1200 + k)
+            ctx = P.Context(L, 0.124, 0.004 + 0.001 * k)
+            ctx.set_gauge(cuda(U))
+            inst["t%d" % k] = dict(name="t%d" % k, cfg=dict(L=L), ctx=ctx, nrhs=1 + k % 3)
+        names = sorted(inst)
+        for solver, prec in ((P.TM_CG_MIXED, P.TM_F16), (P.TM_CG_F64, P.TM_F32)):
+            params = P.solve_params(tol=1e-9, solver=solver, inner_prec=prec)
+            bs, xs, stats = batch_solve_env(inst, names, params, {}, 1300)
+            for k, n in enumerate(names):
+                x1 = torch.zeros_like(bs[k])
+                inst[n]["ctx"].solve(x1, bs[k], inst[n]["nrhs"], params)
+                assert torch.equal(xs[k], x1), (solver, n)
+                assert all(st.converged == 1 for st in stats[k]), (solver, n)
+    finally:
+        for d in inst.values():
+            d["ctx"].close()
+
+
 def test_persistent_barrier_wait_is_bounded(five):
     """A spin limit of zero makes the persistent kernel's barrier waits give
     up at once: every block leaves the kernel, the call fails with
